@@ -1,0 +1,638 @@
+/*
+ * ftgemm_oracle.c -- plain CPU oracle for the fault-tolerant GEMM.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * statement of what the GPU path must compute.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it; the product
+ * library (libftgemm) never links, loads or calls it, and the two share no
+ * code, header, table or helper.
+ *
+ * Source of the method: Wu, Zhai, Huang, Jian, Chen, "FT-GEMM: A Fault
+ * Tolerant High Performance GEMM Implementation on x86 CPUs" (HPDC'23 poster).
+ *   - Section 2.1 (Implementation of DGEMM): C = alpha*A*B + beta*C computed
+ *     block by block; blocks of the output are the unit of work.
+ *   - Section 2.2 (FT-DGEMM): the two checksum vectors of C are encoded while
+ *     C is scaled by beta, the operand checksums are formed while A and B are
+ *     staged (each staged element of B feeds B's own checksum and the
+ *     encoded row checksum of C; each staged element of A feeds the encoded
+ *     column checksum of C), and the reference checksums are the sums of the
+ *     computed output; comparing the two verifies the multiplication.
+ *   - Section 2.3 (Parallel FT-DGEMM): the output is split into independent
+ *     parts, each carrying its own slice of the checksums.
+ *   - Section 1 (Introduction): fail-continue soft errors in compute logic are
+ *     the fault model; Huang and Abraham's ABFT is the underlying scheme.
+ *
+ * Notation (the reading taken of Section 2.2, where the paper never writes a
+ * formula): e is the all-ones vector, X^c = X e (one entry per row) and
+ * X^r = e^T X (one entry per column).  Everything here is FP64 and
+ * column-major, in the BLAS convention: op(A) is m x k, op(B) is k x n.
+ *
+ * Pins (tests/test_oracle_*.py): the checksum identities e^T(AB) = (e^T A)B
+ * and (AB)e = A(Be) bit-exactly on small-integer data; brute-force location
+ * of single injected errors; bit-exact recovery of integer data; GEMM against
+ * numpy's matmul; BLAS special cases; exhaustive decoders against torch; the
+ * hand-worked example in tests/golden/.  The detection threshold has no
+ * closed form in the paper: it is pinned statistically (no false positives on
+ * fault-free data, detection of every guard-banded injection) -- parity for
+ * the threshold's exact value is therefore "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Number formats (inputs of the low-precision GEMMs), decoded from their    */
+/* bit-level definitions.                                                    */
+/* ------------------------------------------------------------------------- */
+
+/* bfloat16: 1 sign bit, 8 exponent bits (bias 127), 7 fraction bits. */
+double oracle_bf16_value(uint16_t h)
+{
+    int sign = (h >> 15) & 1;
+    int e = (h >> 7) & 0xff;
+    int f = h & 0x7f;
+    double v;
+    if (e == 0xff)
+        v = (f == 0) ? INFINITY : NAN;
+    else if (e == 0)
+        v = ldexp((double)f, -126 - 7);            /* subnormal: 0.f * 2^-126 */
+    else
+        v = ldexp((double)(128 + f), e - 127 - 7); /* 1.f * 2^(e-127) */
+    return sign ? -v : v;
+}
+
+/* OCP FP8 E4M3 ("fn": finite, no infinities): 1 sign, 4 exponent bits
+ * (bias 7), 3 fraction bits; exponent 15 with fraction 7 is NaN, so the
+ * largest finite magnitude is 1.75 * 2^8 = 448. */
+double oracle_e4m3_value(uint8_t b)
+{
+    int sign = (b >> 7) & 1;
+    int e = (b >> 3) & 0xf;
+    int f = b & 0x7;
+    double v;
+    if (e == 0xf && f == 0x7)
+        v = NAN;
+    else if (e == 0)
+        v = ldexp((double)f, -6 - 3);              /* subnormal: 0.f * 2^-6 */
+    else
+        v = ldexp((double)(8 + f), e - 7 - 3);     /* 1.f * 2^(e-7) */
+    return sign ? -v : v;
+}
+
+void oracle_decode_bf16(const uint16_t *src, double *dst, int64_t n)
+{
+    for (int64_t t = 0; t < n; ++t)
+        dst[t] = oracle_bf16_value(src[t]);
+}
+
+void oracle_decode_e4m3(const uint8_t *src, double *dst, int64_t n)
+{
+    for (int64_t t = 0; t < n; ++t)
+        dst[t] = oracle_e4m3_value(src[t]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Plain GEMM (Section 2.1): C_out = alpha * op(A) op(B) + beta * C_in.     */
+/* beta == 0 means C_in is not read (BLAS convention), so NaNs in it do not */
+/* reach the result.                                                        */
+/* ------------------------------------------------------------------------- */
+
+static inline double opA(const double *A, int64_t lda, int ta, int64_t i, int64_t p)
+{
+    return ta ? A[p + i * lda] : A[i + p * lda];
+}
+
+static inline double opB(const double *B, int64_t ldb, int tb, int64_t p, int64_t j)
+{
+    return tb ? B[j + p * ldb] : B[p + j * ldb];
+}
+
+void oracle_gemm(int ta, int tb, int64_t m, int64_t n, int64_t k,
+                 double alpha, const double *A, int64_t lda,
+                 const double *B, int64_t ldb, double beta,
+                 const double *Cin, int64_t ldc, double *Cout, int64_t ldo)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j) {
+        double *col = Cout + j * ldo;
+        for (int64_t i = 0; i < m; ++i)
+            col[i] = 0.0;
+        for (int64_t p = 0; p < k; ++p) {
+            double b = opB(B, ldb, tb, p, j);
+            for (int64_t i = 0; i < m; ++i)
+                col[i] += opA(A, lda, ta, i, p) * b;
+        }
+        for (int64_t i = 0; i < m; ++i)
+            col[i] = (beta == 0.0) ? alpha * col[i]
+                                   : alpha * col[i] + beta * Cin[i + j * ldc];
+    }
+}
+
+/* Selected entries only, one dot product each (used to check large runs on
+ * sampled outputs). */
+void oracle_gemm_entries(int ta, int tb, int64_t k, double alpha,
+                         const double *A, int64_t lda, const double *B,
+                         int64_t ldb, double beta, const double *Cin,
+                         int64_t ldc, const int64_t *rows, const int64_t *cols,
+                         int64_t count, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t i = rows[t], j = cols[t];
+        double s = 0.0;
+        for (int64_t p = 0; p < k; ++p)
+            s += opA(A, lda, ta, i, p) * opB(B, ldb, tb, p, j);
+        out[t] = (beta == 0.0) ? alpha * s : alpha * s + beta * Cin[i + j * ldc];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Fault-tolerant GEMM, tile by tile (Sections 2.2 and 2.3).                 */
+/* ------------------------------------------------------------------------- */
+
+enum { INJ_ADD = 0, INJ_BITFLIP = 1 };
+enum { TGT_ACC = 0, TGT_ROW_CHECKSUM = 1, TGT_COL_CHECKSUM = 2 };
+enum { KIND_CORRECTED = 1, KIND_CHECKSUM_ONLY = 2, KIND_RECOMPUTED = 3,
+       KIND_UNCORRECTABLE = 4 };
+
+/* One planned soft error.  It lands after the inner-dimension step (of
+ * length bk) that contains k_index has been accumulated.  TGT_ACC hits the
+ * accumulator of C(row, col); TGT_ROW_CHECKSUM hits the encoded row checksum
+ * entry of column col; TGT_COL_CHECKSUM the encoded column checksum entry of
+ * row row. */
+typedef struct {
+    int64_t row, col, k_index;
+    int32_t mode, target;
+    double delta;
+    int32_t bit, pad;
+} oracle_injection;
+
+typedef struct {
+    int64_t tile_m, tile_n;
+    int64_t row, col;          /* located element, -1 where not applicable */
+    int32_t kind, nbad_rows, nbad_cols, pad;
+    double d_row, d_col;       /* residuals of the row / column checksum   */
+    double tau_row, tau_col;   /* thresholds they were held to             */
+    double before, after;      /* element value before / after correction  */
+} oracle_record;
+
+typedef struct {
+    int64_t row, col, k_index;
+    int32_t applied, pad;
+    double before, after;      /* the perturbed quantity, before and after */
+} oracle_echo;
+
+typedef struct {
+    int32_t ta, tb;
+    int64_t m, n, k, lda, ldb, ldc;
+    double alpha, beta;        /* alpha already carries any input scales   */
+    int64_t tm, tn, bk;        /* verification tile and inner step          */
+    int32_t acc_bits;          /* 64: FP64 accumulators; 32: FP32           */
+    int32_t correct;           /* 0: detect and classify only               */
+    double lambda;             /* threshold multiplier                      */
+} oracle_params;
+
+/* Flip one bit of an accumulator held at the given precision. */
+static double flip_bit(double v, int bit, int acc_bits)
+{
+    if (acc_bits == 32) {
+        float f = (float)v;
+        uint32_t u;
+        memcpy(&u, &f, 4);
+        u ^= (uint32_t)1u << bit;
+        memcpy(&f, &u, 4);
+        return (double)f;
+    }
+    uint64_t u;
+    memcpy(&u, &v, 8);
+    u ^= (uint64_t)1u << bit;
+    memcpy(&v, &u, 8);
+    return v;
+}
+
+/* Rounding-error threshold of one checksum entry.
+ *
+ * The paper gives no threshold; the reading taken is a probabilistic
+ * rounding-error bound (Higham and Mary's sqrt(n) model, lambda standard
+ * deviations) built only from input norms, so a corrupted accumulator can
+ * never inflate its own threshold.  For the row checksum of column j of a
+ * tile with rows I (|I| = h), with u the unit roundoff of the arithmetic:
+ *
+ *   tau_j = lambda * ( |alpha| * ||b_j|| * [ (u sqrt(k) + u) ||A_I||_F
+ *                                           + u (sqrt(k) ||x|| + sqrt(h) ||A_I||_F) ]
+ *                      + 2 u |beta| ||Cin(I, j)|| )
+ *
+ * where b_j is column j of op(B) over all k, x = e^T op(A)(I, :) is the
+ * tile's operand checksum, and the four terms bound the accumulation of the
+ * products, the rounding of the output, the encoding product x^T b_j, and
+ * the rounding inside x.  The column checksum entry of row i swaps the roles
+ * of A and B. */
+static double threshold(double lambda, double u, int64_t k, int64_t h,
+                        double alpha, double nrm_vec, double frob_tile,
+                        double nrm_chk, double beta, double nrm_cin)
+{
+    double sk = sqrt((double)k);
+    double sh = sqrt((double)h);
+    double prod = (u * sk + u) * frob_tile + u * (sk * nrm_chk + sh * frob_tile);
+    return lambda * (fabs(alpha) * nrm_vec * prod + 2.0 * u * fabs(beta) * nrm_cin);
+}
+
+/* Accumulate one tile, applying the injections aimed at its accumulators
+ * after the step that contains their k_index.  acc is h x w, column-major. */
+static void tile_accumulate(const oracle_params *P, const double *A,
+                            const double *B, int64_t i0, int64_t j0, int64_t h,
+                            int64_t w, double *acc,
+                            const oracle_injection *inj, int64_t ninj,
+                            oracle_echo *echo)
+{
+    for (int64_t t = 0; t < h * w; ++t)
+        acc[t] = 0.0;
+    int64_t nsteps = (P->k + P->bk - 1) / P->bk;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        int64_t p0 = s * P->bk, p1 = p0 + P->bk < P->k ? p0 + P->bk : P->k;
+        for (int64_t jj = 0; jj < w; ++jj)
+            for (int64_t p = p0; p < p1; ++p) {
+                double b = opB(B, P->ldb, P->tb, p, j0 + jj);
+                for (int64_t ii = 0; ii < h; ++ii)
+                    acc[ii + jj * h] += opA(A, P->lda, P->ta, i0 + ii, p) * b;
+            }
+        for (int64_t q = 0; inj && q < ninj; ++q) {
+            const oracle_injection *f = &inj[q];
+            if (f->target != TGT_ACC || f->k_index / P->bk != s)
+                continue;
+            if (f->row < i0 || f->row >= i0 + h || f->col < j0 || f->col >= j0 + w)
+                continue;
+            double *a = &acc[(f->row - i0) + (f->col - j0) * h];
+            double before = *a;
+            *a = (f->mode == INJ_ADD) ? *a + f->delta : flip_bit(*a, f->bit, P->acc_bits);
+            if (echo) {
+                echo[q].applied = 1;
+                echo[q].before = before;
+                echo[q].after = *a;
+            }
+        }
+    }
+}
+
+/* Encoded checksums (Pr, Pc) and thresholds (tr, tc) of one tile of h rows
+ * starting at i0 and w columns starting at j0. */
+static void tile_encode(const oracle_params *P, const double *A, const double *B,
+                        const double *Cin, int64_t i0, int64_t j0, int64_t h,
+                        int64_t w, double *Pr, double *Pc, double *tr, double *tc)
+{
+    const int64_t k = P->k;
+    const double u = (P->acc_bits == 32) ? ldexp(1.0, -24) : ldexp(1.0, -53);
+    const double alpha = P->alpha, beta = P->beta;
+    double *x = malloc(sizeof(double) * (k > 0 ? k : 1));
+    double *y = malloc(sizeof(double) * (k > 0 ? k : 1));
+    double *nb = malloc(sizeof(double) * w), *na = malloc(sizeof(double) * h);
+    double *gc = malloc(sizeof(double) * w), *gr = malloc(sizeof(double) * h);
+
+    /* Operand checksums of the tile: x = e^T op(A)(I,:), y = op(B)(:,J) e. */
+    for (int64_t p = 0; p < k; ++p) {
+        double sx = 0.0, sy = 0.0;
+        for (int64_t ii = 0; ii < h; ++ii)
+            sx += opA(A, P->lda, P->ta, i0 + ii, p);
+        for (int64_t jj = 0; jj < w; ++jj)
+            sy += opB(B, P->ldb, P->tb, p, j0 + jj);
+        x[p] = sx;
+        y[p] = sy;
+    }
+    /* Encoded checksums of C (Section 2.2): the product part from the
+     * operand checksums, the beta part from the input C. */
+    for (int64_t jj = 0; jj < w; ++jj) {
+        double s = 0.0, c = 0.0;
+        for (int64_t p = 0; p < k; ++p)
+            s += x[p] * opB(B, P->ldb, P->tb, p, j0 + jj);
+        if (beta != 0.0)
+            for (int64_t ii = 0; ii < h; ++ii)
+                c += Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+        Pr[jj] = alpha * s + beta * c;
+    }
+    for (int64_t ii = 0; ii < h; ++ii) {
+        double s = 0.0, c = 0.0;
+        for (int64_t p = 0; p < k; ++p)
+            s += opA(A, P->lda, P->ta, i0 + ii, p) * y[p];
+        if (beta != 0.0)
+            for (int64_t jj = 0; jj < w; ++jj)
+                c += Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+        Pc[ii] = alpha * s + beta * c;
+    }
+    /* Norms for the thresholds. */
+    double fa = 0.0, fb = 0.0, nx = 0.0, ny = 0.0;
+    for (int64_t ii = 0; ii < h; ++ii) {
+        double s = 0.0;
+        for (int64_t p = 0; p < k; ++p) {
+            double a = opA(A, P->lda, P->ta, i0 + ii, p);
+            s += a * a;
+        }
+        na[ii] = sqrt(s);
+        fa += s;
+    }
+    for (int64_t jj = 0; jj < w; ++jj) {
+        double s = 0.0;
+        for (int64_t p = 0; p < k; ++p) {
+            double b = opB(B, P->ldb, P->tb, p, j0 + jj);
+            s += b * b;
+        }
+        nb[jj] = sqrt(s);
+        fb += s;
+    }
+    for (int64_t p = 0; p < k; ++p) {
+        nx += x[p] * x[p];
+        ny += y[p] * y[p];
+    }
+    fa = sqrt(fa); fb = sqrt(fb); nx = sqrt(nx); ny = sqrt(ny);
+    for (int64_t jj = 0; jj < w; ++jj) {
+        double s = 0.0;
+        if (beta != 0.0)
+            for (int64_t ii = 0; ii < h; ++ii) {
+                double c = Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+                s += c * c;
+            }
+        gc[jj] = sqrt(s);
+    }
+    for (int64_t ii = 0; ii < h; ++ii) {
+        double s = 0.0;
+        if (beta != 0.0)
+            for (int64_t jj = 0; jj < w; ++jj) {
+                double c = Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+                s += c * c;
+            }
+        gr[ii] = sqrt(s);
+    }
+    for (int64_t jj = 0; jj < w; ++jj)
+        tr[jj] = threshold(P->lambda, u, k, h, alpha, nb[jj], fa, nx, beta, gc[jj]);
+    for (int64_t ii = 0; ii < h; ++ii)
+        tc[ii] = threshold(P->lambda, u, k, w, alpha, na[ii], fb, ny, beta, gr[ii]);
+
+    free(x); free(y); free(nb); free(na); free(gc); free(gr);
+}
+
+/* Thresholds of one tile, exported for the fault planner's guard band. */
+void oracle_tile_thresholds(const oracle_params *P, const double *A, const double *B,
+                            const double *Cin, int64_t tile_m, int64_t tile_n,
+                            double *tr, double *tc)
+{
+    const int64_t i0 = tile_m * P->tm, j0 = tile_n * P->tn;
+    const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 : P->tm;
+    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;
+    double *Pr = malloc(sizeof(double) * w), *Pc = malloc(sizeof(double) * h);
+    tile_encode(P, A, B, Cin, i0, j0, h, w, Pr, Pc, tr, tc);
+    free(Pr); free(Pc);
+}
+
+/* One tile of the fault-tolerant GEMM.  Writes the tile of Cout (and of
+ * Craw, the output before correction, when given) and at most one record.
+ * Returns 1 when a record was produced. */
+static int ft_tile(const oracle_params *P, const double *A, const double *B,
+                   const double *Cin, double *Cout, int64_t ldo, double *Craw,
+                   int64_t tile_m, int64_t tile_n,
+                   const oracle_injection *inj, int64_t ninj,
+                   oracle_echo *echo, oracle_record *rec, double *max_ratio)
+{
+    const int64_t i0 = tile_m * P->tm, j0 = tile_n * P->tn;
+    const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 : P->tm;
+    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;
+    const double alpha = P->alpha, beta = P->beta;
+
+    double *acc = malloc(sizeof(double) * h * w);
+    double *out = malloc(sizeof(double) * h * w);
+    double *Pr = malloc(sizeof(double) * w), *Pc = malloc(sizeof(double) * h);
+    double *Rr = malloc(sizeof(double) * w), *Rc = malloc(sizeof(double) * h);
+    double *tr = malloc(sizeof(double) * w), *tc = malloc(sizeof(double) * h);
+
+    int recomputed = 0, produced = 0;
+    int attempt_faults = 1;
+    for (;;) {
+        /* Encoding (Section 2.2), then the planned faults on the encoded
+         * checksums -- on the first attempt only. */
+        tile_encode(P, A, B, Cin, i0, j0, h, w, Pr, Pc, tr, tc);
+
+        /* Faults aimed at the encoded checksums. */
+        for (int64_t q = 0; attempt_faults && inj && q < ninj; ++q) {
+            const oracle_injection *f = &inj[q];
+            if (f->target == TGT_ROW_CHECKSUM && f->col >= j0 && f->col < j0 + w &&
+                f->row >= i0 && f->row < i0 + h) {
+                double before = Pr[f->col - j0];
+                Pr[f->col - j0] = (f->mode == INJ_ADD) ? before + f->delta
+                                                       : flip_bit(before, f->bit, 64);
+                if (echo) { echo[q].applied = 1; echo[q].before = before; echo[q].after = Pr[f->col - j0]; }
+            } else if (f->target == TGT_COL_CHECKSUM && f->row >= i0 && f->row < i0 + h &&
+                       f->col >= j0 && f->col < j0 + w) {
+                double before = Pc[f->row - i0];
+                Pc[f->row - i0] = (f->mode == INJ_ADD) ? before + f->delta
+                                                       : flip_bit(before, f->bit, 64);
+                if (echo) { echo[q].applied = 1; echo[q].before = before; echo[q].after = Pc[f->row - i0]; }
+            }
+        }
+
+        /* Multiplication (with the planned faults on the first attempt) and
+         * the beta pass. */
+        tile_accumulate(P, A, B, i0, j0, h, w, acc,
+                        attempt_faults ? inj : NULL, ninj, attempt_faults ? echo : NULL);
+        for (int64_t jj = 0; jj < w; ++jj)
+            for (int64_t ii = 0; ii < h; ++ii) {
+                double a = alpha * acc[ii + jj * h];
+                out[ii + jj * h] = (beta == 0.0)
+                    ? a : a + beta * Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+            }
+        if (Craw && attempt_faults)
+            for (int64_t jj = 0; jj < w; ++jj)
+                for (int64_t ii = 0; ii < h; ++ii)
+                    Craw[(i0 + ii) + (j0 + jj) * ldo] = out[ii + jj * h];
+
+        /* Reference checksums: sums of the computed output. */
+        for (int64_t jj = 0; jj < w; ++jj) {
+            double s = 0.0;
+            for (int64_t ii = 0; ii < h; ++ii)
+                s += out[ii + jj * h];
+            Rr[jj] = s;
+        }
+        for (int64_t ii = 0; ii < h; ++ii) {
+            double s = 0.0;
+            for (int64_t jj = 0; jj < w; ++jj)
+                s += out[ii + jj * h];
+            Rc[ii] = s;
+        }
+
+        /* Verify.  The comparison is written so that NaN residuals flag. */
+        int64_t nbad_c = 0, nbad_r = 0, jbad = -1, ibad = -1;
+        for (int64_t jj = 0; jj < w; ++jj) {
+            double d = Rr[jj] - Pr[jj];
+            if (!(fabs(d) <= tr[jj])) {
+                if (nbad_c++ == 0) jbad = jj;
+            } else if (tr[jj] > 0.0 && fabs(d) / tr[jj] > *max_ratio) {
+                *max_ratio = fabs(d) / tr[jj];
+            }
+        }
+        for (int64_t ii = 0; ii < h; ++ii) {
+            double d = Rc[ii] - Pc[ii];
+            if (!(fabs(d) <= tc[ii])) {
+                if (nbad_r++ == 0) ibad = ii;
+            } else if (tc[ii] > 0.0 && fabs(d) / tc[ii] > *max_ratio) {
+                *max_ratio = fabs(d) / tc[ii];
+            }
+        }
+        if (nbad_c == 0 && nbad_r == 0) {
+            if (recomputed && rec) {
+                /* the record of the failed attempt is kept, kind updated */
+                rec->kind = KIND_RECOMPUTED;
+            }
+            break;
+        }
+        if (recomputed) {
+            /* still inconsistent without any injected fault */
+            if (rec) rec->kind = KIND_UNCORRECTABLE;
+            break;
+        }
+        produced = 1;
+        if (rec) {
+            rec->tile_m = tile_m; rec->tile_n = tile_n;
+            rec->row = ibad >= 0 ? i0 + ibad : -1;
+            rec->col = jbad >= 0 ? j0 + jbad : -1;
+            rec->nbad_rows = (int32_t)nbad_r; rec->nbad_cols = (int32_t)nbad_c;
+            rec->d_row = jbad >= 0 ? Rr[jbad] - Pr[jbad] : 0.0;
+            rec->d_col = ibad >= 0 ? Rc[ibad] - Pc[ibad] : 0.0;
+            rec->tau_row = jbad >= 0 ? tr[jbad] : 0.0;
+            rec->tau_col = ibad >= 0 ? tc[ibad] : 0.0;
+            rec->before = (ibad >= 0 && jbad >= 0) ? out[ibad + jbad * h] : 0.0;
+            rec->after = rec->before;
+        }
+        if (!P->correct) {
+            if (rec) rec->kind = (nbad_r == 1 && nbad_c == 1) ? KIND_CORRECTED
+                               : (nbad_r + nbad_c == 1) ? KIND_CHECKSUM_ONLY
+                                                        : KIND_RECOMPUTED;
+            break;
+        }
+        if (nbad_r == 1 && nbad_c == 1) {
+            /* Locate at the crossing of the flagged row and column; rebuild
+             * the element from the encoded row checksum and the rest of its
+             * column (this also repairs NaN / Inf values), then confirm it
+             * against the encoded column checksum of its row. */
+            double sr = 0.0, sc = 0.0;
+            for (int64_t ii = 0; ii < h; ++ii)
+                if (ii != ibad) sr += out[ii + jbad * h];
+            for (int64_t jj = 0; jj < w; ++jj)
+                if (jj != jbad) sc += out[ibad + jj * h];
+            double fixed = Pr[jbad] - sr;
+            if (fabs(sc + fixed - Pc[ibad]) <= tc[ibad]) {
+                out[ibad + jbad * h] = fixed;
+                if (rec) { rec->kind = KIND_CORRECTED; rec->after = fixed; }
+                break;
+            }
+        } else if (nbad_r + nbad_c == 1) {
+            /* A single encoded checksum entry disagrees while every sum on
+             * the other side matches: the fault hit the checksum path and
+             * the data is left as it is.  (Several entries on one side with
+             * none on the other cannot come from one checksum fault: such a
+             * tile is computed again below.) */
+            if (rec) rec->kind = KIND_CHECKSUM_ONLY;
+            break;
+        }
+        /* Several faults, or a correction that does not verify: compute the
+         * tile again (the planned faults are not repeated). */
+        recomputed = 1;
+        attempt_faults = 0;
+    }
+
+    for (int64_t jj = 0; jj < w; ++jj)
+        for (int64_t ii = 0; ii < h; ++ii)
+            Cout[(i0 + ii) + (j0 + jj) * ldo] = out[ii + jj * h];
+
+    free(acc); free(out); free(Pr); free(Pc); free(Rr); free(Rc); free(tr); free(tc);
+    return produced;
+}
+
+/* Encoded and reference checksums of one fault-free tile, exported so the
+ * tests can hold the two against each other (the checksum identities). */
+void oracle_tile_checksums(const oracle_params *P, const double *A, const double *B,
+                           const double *Cin, int64_t tile_m, int64_t tile_n,
+                           double *Pr, double *Pc, double *Rr, double *Rc)
+{
+    const int64_t i0 = tile_m * P->tm, j0 = tile_n * P->tn;
+    const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 : P->tm;
+    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;
+    double *tr = malloc(sizeof(double) * w), *tc = malloc(sizeof(double) * h);
+    double *acc = malloc(sizeof(double) * h * w);
+    tile_encode(P, A, B, Cin, i0, j0, h, w, Pr, Pc, tr, tc);
+    tile_accumulate(P, A, B, i0, j0, h, w, acc, NULL, 0, NULL);
+    for (int64_t jj = 0; jj < w; ++jj) {
+        double s = 0.0;
+        for (int64_t ii = 0; ii < h; ++ii) {
+            double a = P->alpha * acc[ii + jj * h];
+            s += (P->beta == 0.0) ? a : a + P->beta * Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+        }
+        Rr[jj] = s;
+    }
+    for (int64_t ii = 0; ii < h; ++ii) {
+        double s = 0.0;
+        for (int64_t jj = 0; jj < w; ++jj) {
+            double a = P->alpha * acc[ii + jj * h];
+            s += (P->beta == 0.0) ? a : a + P->beta * Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+        }
+        Rc[ii] = s;
+    }
+    free(tr); free(tc); free(acc);
+}
+
+/* Fault-tolerant GEMM over the tile grid.  tiles: list of tile indices
+ * (tile_m + tile_n * tiles_m) to process, or NULL for all tiles.  Records of
+ * detected faults go to rec (at most rec_cap are stored; the return value is
+ * the number produced).  echo (ninj entries, may be NULL) reports the value of
+ * each injected quantity before and after the fault.  Craw (may be NULL)
+ * receives the output before correction. */
+int64_t oracle_ftgemm(const oracle_params *P, const double *A, const double *B,
+                      const double *Cin, double *Cout, int64_t ldo, double *Craw,
+                      const oracle_injection *inj, int64_t ninj,
+                      const int64_t *tiles, int64_t ntiles,
+                      oracle_record *rec, int64_t rec_cap, oracle_echo *echo,
+                      double *max_ratio)
+{
+    if (P->m <= 0 || P->n <= 0)
+        return 0;
+    const int64_t tiles_m = (P->m + P->tm - 1) / P->tm;
+    const int64_t tiles_n = (P->n + P->tn - 1) / P->tn;
+    const int64_t total = tiles ? ntiles : tiles_m * tiles_n;
+    int64_t nrec = 0;
+    double mr = 0.0;
+    if (echo)
+        for (int64_t q = 0; q < ninj; ++q) {
+            echo[q].row = inj[q].row; echo[q].col = inj[q].col;
+            echo[q].k_index = inj[q].k_index; echo[q].applied = 0;
+            echo[q].before = echo[q].after = 0.0;
+        }
+#pragma omp parallel for schedule(dynamic, 1) reduction(max : mr)
+    for (int64_t t = 0; t < total; ++t) {
+        int64_t id = tiles ? tiles[t] : t;
+        oracle_record r;
+        memset(&r, 0, sizeof r);
+        double local = 0.0;
+        int got = ft_tile(P, A, B, Cin, Cout, ldo, Craw, id % tiles_m, id / tiles_m,
+                          inj, ninj, echo, &r, &local);
+        if (local > mr) mr = local;
+        if (got) {
+            int64_t slot;
+#pragma omp atomic capture
+            slot = nrec++;
+            if (rec && slot < rec_cap)
+                rec[slot] = r;
+        }
+    }
+    if (max_ratio)
+        *max_ratio = mr;
+    return nrec;
+}
+
+/* Sizes of the structures, so the Python side can check its mirror. */
+int64_t oracle_sizeof(int which)
+{
+    switch (which) {
+    case 0: return (int64_t)sizeof(oracle_injection);
+    case 1: return (int64_t)sizeof(oracle_record);
+    case 2: return (int64_t)sizeof(oracle_echo);
+    case 3: return (int64_t)sizeof(oracle_params);
+    default: return -1;
+    }
+}

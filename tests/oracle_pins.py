@@ -1,0 +1,243 @@
+"""Pins of the CPU oracle: checks against what the paper and the mathematics
+fix, independent of the oracle's own formulas.  Each function takes an
+``Oracle`` instance (the real build, or a deliberately broken copy in
+test_oracle_mutants.py) and raises AssertionError when the pin fails.
+"""
+import numpy as np
+
+from oracle import oracle as O
+from paper_2305_02444_amd import synth
+
+
+def _ops(A, B, ta, tb):
+    return (A.T if ta else A), (B.T if tb else B)
+
+
+def pin_gemm_vs_numpy(orc):
+    """Plain GEMM equals numpy's matmul (a library routine) for every
+    transpose combination, odd shapes and padded leading dimensions."""
+    g = np.random.default_rng(11)
+    for ta in (False, True):
+        for tb in (False, True):
+            m, n, k = 37, 29, 41
+            sa = (k, m) if ta else (m, k)
+            sb = (n, k) if tb else (k, n)
+            # leading dimension larger than the row count: take a slice of a
+            # taller Fortran array
+            Abig = np.asfortranarray(g.uniform(-1, 1, (sa[0] + 5, sa[1])))
+            Bbig = np.asfortranarray(g.uniform(-1, 1, (sb[0] + 3, sb[1])))
+            A, B = Abig[:sa[0]], Bbig[:sb[0]]
+            Cin = np.asfortranarray(g.uniform(-1, 1, (m, n)))
+            alpha, beta = -0.75, 1.5
+            got = orc.gemm(A, B, Cin, alpha, beta, ta, tb)
+            oa, ob = _ops(A, B, ta, tb)
+            ref = alpha * (oa @ ob) + beta * Cin
+            err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+            assert err < 1e-14, (ta, tb, err)
+
+
+def pin_gemm_integer_exact(orc):
+    """On small integers every partial sum is exact: bit equality with numpy."""
+    g = np.random.default_rng(12)
+    A = np.asfortranarray(g.integers(-8, 9, (19, 23)).astype(float))
+    B = np.asfortranarray(g.integers(-8, 9, (23, 17)).astype(float))
+    Cin = np.asfortranarray(g.integers(-8, 9, (19, 17)).astype(float))
+    got = orc.gemm(A, B, Cin, 2.0, -3.0)
+    assert np.array_equal(got, 2.0 * (A @ B) - 3.0 * Cin)
+
+
+def pin_blas_special_cases(orc):
+    g = np.random.default_rng(13)
+    A = np.asfortranarray(g.uniform(-1, 1, (9, 7)))
+    B = np.asfortranarray(g.uniform(-1, 1, (7, 5)))
+    Cin = np.asfortranarray(g.uniform(-1, 1, (9, 5)))
+    # alpha == 0: beta * C
+    assert np.array_equal(orc.gemm(A, B, Cin, 0.0, 0.5), 0.5 * Cin)
+    # beta == 0: C_in is never read, NaNs in it do not propagate
+    nanC = np.full((9, 5), np.nan, order="F")
+    got = orc.gemm(A, B, nanC, 1.0, 0.0)
+    assert np.all(np.isfinite(got))
+    # k == 0: beta * C
+    A0 = np.zeros((9, 0), order="F")
+    B0 = np.zeros((0, 5), order="F")
+    assert np.array_equal(orc.gemm(A0, B0, Cin, 1.0, 2.0), 2.0 * Cin)
+    # the fault-tolerant path follows the same conventions
+    r = orc.ftgemm(A, B, nanC, 1.0, 0.0, tm=4, tn=4, bk=2)
+    assert np.all(np.isfinite(r.C)) and not r.records
+    r = orc.ftgemm(A0, B0, Cin, 1.0, 2.0, tm=4, tn=4, bk=2)
+    assert np.array_equal(r.C, 2.0 * Cin) and not r.records
+
+
+def pin_checksum_identities(orc):
+    """e^T(AB) = (e^T A)B and (AB)e = A(Be) hold exactly on small integers:
+    the encoded checksums (built from the operands and C_in) must equal the
+    reference checksums (sums of the computed C) bit for bit, in every tile,
+    including ragged edge tiles and transposed operands."""
+    for ta in (False, True):
+        for tb in (False, True):
+            g = synth.rng(90, int(ta) * 2 + int(tb), 0)
+            m, n, k = 21, 18, 40
+            A = np.asfortranarray(g.integers(-8, 9, (k, m) if ta else (m, k)).astype(float))
+            B = np.asfortranarray(g.integers(-8, 9, (n, k) if tb else (k, n)).astype(float))
+            Cin = np.asfortranarray(g.integers(-8, 9, (m, n)).astype(float))
+            for ti in range(-(-m // 8)):
+                for tj in range(-(-n // 8)):
+                    Pr, Pc, Rr, Rc = orc.tile_checksums(A, B, ti, tj, Cin, 2.0, -1.0, ta,
+                                                        tb, tm=8, tn=8, bk=5)
+                    assert np.array_equal(Pr, Rr), (ta, tb, ti, tj)
+                    assert np.array_equal(Pc, Rc), (ta, tb, ti, tj)
+                    # and the reference side really is the sum of the product
+                    oa, ob = _ops(A, B, ta, tb)
+                    Cf = 2.0 * (oa @ ob) - 1.0 * Cin
+                    blk = Cf[ti * 8:ti * 8 + 8, tj * 8:tj * 8 + 8]
+                    assert np.array_equal(Rr, blk.sum(axis=0))
+                    assert np.array_equal(Rc, blk.sum(axis=1))
+
+
+def pin_brute_force_location(orc):
+    """A single injected error is located exactly where the faulty output
+    differs from the fault-free product (found by brute force)."""
+    g = np.random.default_rng(14)
+    m, n, k = 50, 45, 64
+    A = np.asfortranarray(g.uniform(-1, 1, (m, k)))
+    B = np.asfortranarray(g.uniform(-1, 1, (k, n)))
+    Cin = np.asfortranarray(g.uniform(-1, 1, (m, n)))
+    Cff = A @ B * 1.25 + 0.5 * Cin
+    for trial in range(12):
+        row, col, kidx = int(g.integers(m)), int(g.integers(n)), int(g.integers(k))
+        delta = float(g.choice([-1, 1]) * 10 ** g.uniform(-3, 3))
+        r = orc.ftgemm(A, B, Cin, 1.25, 0.5, tm=16, tn=16, bk=8,
+                       injections=[O.Injection(row, col, kidx, O.ADD, delta)])
+        diff = np.abs(r.raw - Cff)
+        bad = np.argwhere(diff > 1e-9)
+        assert bad.tolist() == [[row, col]], (trial, bad)
+        assert len(r.records) == 1
+        rec = r.records[0]
+        assert (rec["row"], rec["col"], rec["kind"]) == (row, col, O.CORRECTED)
+        assert (rec["tile_m"], rec["tile_n"]) == (row // 16, col // 16)
+        assert np.max(np.abs(r.C - Cff)) < 1e-12
+
+
+def pin_exact_recovery(orc):
+    """Integer data and an integer perturbation: the corrected output equals
+    the fault-free product bit for bit."""
+    g = synth.rng(91, 0, 0)
+    m, n, k = 33, 30, 24
+    A = np.asfortranarray(g.integers(-8, 9, (m, k)).astype(float))
+    B = np.asfortranarray(g.integers(-8, 9, (k, n)).astype(float))
+    Cin = np.asfortranarray(g.integers(-8, 9, (m, n)).astype(float))
+    Cff = 3.0 * (A @ B) + 2.0 * Cin
+    plan = [O.Injection(3, 4, 5, O.ADD, 1000.0), O.Injection(20, 17, 23, O.ADD, -77.0),
+            O.Injection(32, 29, 0, O.ADD, 5.0)]
+    r = orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=4, injections=plan)
+    assert np.array_equal(r.C, Cff)
+    assert sorted((d["row"], d["col"]) for d in r.records) == [(3, 4), (20, 17), (32, 29)]
+    assert all(d["kind"] == O.CORRECTED for d in r.records)
+    # the perturbed value is what the record calls "before"
+    for d in r.records:
+        assert d["before"] == Cff[d["row"], d["col"]] + 3.0 * {3: 1000.0, 20: -77.0, 32: 5.0}[d["row"]]
+        assert d["after"] == Cff[d["row"], d["col"]]
+
+
+def pin_nonfinite_recovery(orc):
+    """Exponent bit flips of FP32 accumulators that produce Inf or NaN are
+    repaired by rebuilding the element from its column."""
+    g = np.random.default_rng(15)
+    m, n, k = 40, 40, 32
+    A = np.asfortranarray(g.uniform(-1, 1, (m, k)))
+    B = np.asfortranarray(g.uniform(-1, 1, (k, n)))
+    Cff = A @ B
+    # find an accumulator whose partial sum after the first step (bk = 8)
+    # lies in [1, 2): flipping bit 30 makes its exponent all ones (Inf/NaN)
+    part = A[:, :8] @ B[:8, :]
+    cand = np.argwhere((np.abs(part) >= 1) & (np.abs(part) < 2))
+    assert len(cand)
+    row, col = map(int, cand[0])
+    r = orc.ftgemm(A, B, tm=16, tn=16, bk=8, acc_bits=32,
+                   injections=[O.Injection(row, col, 3, O.BITFLIP, bit=30)])
+    assert not np.isfinite(r.raw[row, col])
+    assert r.echo[0]["applied"] and not np.isfinite(r.echo[0]["after"])
+    assert len(r.records) == 1 and r.records[0]["kind"] == O.CORRECTED
+    assert np.max(np.abs(r.C - Cff)) < 1e-12
+
+
+def pin_classification(orc):
+    """Two errors in one tile -> recomputed; a fault in an encoded checksum
+    only -> checksum-only with C untouched; a perturbation far below the
+    rounding threshold -> not flagged."""
+    g = np.random.default_rng(16)
+    m, n, k = 32, 32, 48
+    A = np.asfortranarray(g.uniform(-1, 1, (m, k)))
+    B = np.asfortranarray(g.uniform(-1, 1, (k, n)))
+    Cff = A @ B
+    two = [O.Injection(1, 2, 3, O.ADD, 50.0), O.Injection(5, 9, 40, O.ADD, -20.0)]
+    r = orc.ftgemm(A, B, tm=16, tn=16, bk=16, injections=two)
+    assert [d["kind"] for d in r.records] == [O.RECOMPUTED]
+    assert r.records[0]["nbad_rows"] == 2 and r.records[0]["nbad_cols"] == 2
+    assert np.max(np.abs(r.C - Cff)) < 1e-13
+    ck = [O.Injection(20, 21, 10, O.ADD, 3.0, target=O.TGT_ROW_CHECKSUM)]
+    r = orc.ftgemm(A, B, tm=16, tn=16, bk=16, injections=ck)
+    assert [d["kind"] for d in r.records] == [O.CHECKSUM_ONLY]
+    assert r.records[0]["col"] == 21 and r.records[0]["row"] == -1
+    assert np.max(np.abs(r.C - Cff)) < 1e-13
+    ck = [O.Injection(20, 21, 10, O.ADD, 3.0, target=O.TGT_COL_CHECKSUM)]
+    r = orc.ftgemm(A, B, tm=16, tn=16, bk=16, injections=ck)
+    assert [d["kind"] for d in r.records] == [O.CHECKSUM_ONLY]
+    assert r.records[0]["row"] == 20 and r.records[0]["col"] == -1
+    # two errors in one row: one row and two columns disagree -> recomputed
+    r = orc.ftgemm(A, B, tm=16, tn=16, bk=16, injections=[
+        O.Injection(3, 1, 3, O.ADD, 5.0), O.Injection(3, 7, 30, O.ADD, 8.0)])
+    assert [d["kind"] for d in r.records] == [O.RECOMPUTED]
+    assert np.max(np.abs(r.C - Cff)) < 1e-13
+    # two errors cancelling in their column: two rows and no column disagree;
+    # that is not a single checksum fault -> recomputed, not left alone
+    r = orc.ftgemm(A, B, tm=16, tn=16, bk=16, injections=[
+        O.Injection(2, 4, 3, O.ADD, 6.0), O.Injection(9, 4, 3, O.ADD, -6.0)])
+    assert [d["kind"] for d in r.records] == [O.RECOMPUTED]
+    assert r.records[0]["nbad_rows"] == 2 and r.records[0]["nbad_cols"] == 0
+    assert np.max(np.abs(r.C - Cff)) < 1e-12
+    # a data error plus a fault in the encoded checksum of its own column:
+    # the rebuilt value does not confirm against the row side -> recomputed
+    r = orc.ftgemm(A, B, tm=16, tn=16, bk=16, injections=[
+        O.Injection(6, 5, 3, O.ADD, 40.0),
+        O.Injection(0, 5, 3, O.ADD, 2.0, target=O.TGT_ROW_CHECKSUM)])
+    assert [d["kind"] for d in r.records] == [O.RECOMPUTED]
+    assert np.max(np.abs(r.C - Cff)) < 1e-13
+    tr, tc = orc.tile_thresholds(A, B, 1, 1, tm=16, tn=16, bk=16)
+    tiny = 0.01 * min(tr.min(), tc.min())
+    r = orc.ftgemm(A, B, tm=16, tn=16, bk=16,
+                   injections=[O.Injection(20, 21, 10, O.ADD, tiny)])
+    assert not r.records
+
+
+def pin_no_false_positives(orc):
+    """Fault-free runs flag nothing, for both accumulator precisions, and the
+    largest residual stays well inside its threshold."""
+    for dist, seed in (("uniform", 0), ("normal", 1)):
+        A, B, Cin = synth.operands(92, seed, 70, 66, 300, dist)
+        for acc in (64, 32):
+            r = orc.ftgemm(A, B, Cin, 1.0, 1.0, tm=32, tn=32, bk=16, acc_bits=acc)
+            assert not r.records
+            assert r.max_ratio < 0.1, r.max_ratio
+
+
+def pin_ragged_and_subset(orc):
+    """Ragged edge tiles, k not a multiple of the step, a subset of tiles."""
+    A, B, Cin = synth.operands(93, 0, 45, 39, 29, "uniform")
+    Cff = 0.5 * (A @ B) - 2.0 * Cin
+    plan = [O.Injection(44, 38, 28, O.ADD, 9.0)]
+    r = orc.ftgemm(A, B, Cin, 0.5, -2.0, tm=16, tn=16, bk=8, injections=plan)
+    assert np.max(np.abs(r.C - Cff)) < 1e-13
+    assert [(d["row"], d["col"], d["kind"]) for d in r.records] == [(44, 38, O.CORRECTED)]
+    tiles_m = 3
+    sub = [2 + 2 * tiles_m]  # tile (2, 2): the bottom-right ragged tile
+    r = orc.ftgemm(A, B, Cin, 0.5, -2.0, tm=16, tn=16, bk=8, injections=plan, tiles=sub)
+    assert np.max(np.abs(r.C[32:, 32:] - Cff[32:, 32:])) < 1e-13
+    assert np.all(np.isnan(r.C[:32, :]))
+    assert len(r.records) == 1
+
+
+ALL_PINS = [pin_gemm_vs_numpy, pin_gemm_integer_exact, pin_blas_special_cases,
+            pin_checksum_identities, pin_brute_force_location, pin_exact_recovery,
+            pin_nonfinite_recovery, pin_classification, pin_no_false_positives,
+            pin_ragged_and_subset]

@@ -1,0 +1,74 @@
+"""The pins have teeth: plausible mistakes planted in copies of the oracle
+(on the CPU, never in the GPU path) must each fail at least one pin."""
+import os
+
+import pytest
+
+import oracle_pins
+from oracle import oracle as O
+
+MUTANTS = {
+    "dropped_beta_term_in_row_checksum": (
+        "Pr[jj] = alpha * s + beta * c;", "Pr[jj] = alpha * s;"),
+    "wrong_operand_checksum_in_row_checksum": (
+        "s += x[p] * opB(B, P->ldb, P->tb, p, j0 + jj);",
+        "s += y[p] * opB(B, P->ldb, P->tb, p, j0 + jj);"),
+    "wrong_sign_in_correction": (
+        "double fixed = Pr[jbad] - sr;", "double fixed = sr - Pr[jbad];"),
+    "transposed_operand_A": (
+        "return ta ? A[p + i * lda] : A[i + p * lda];",
+        "return ta ? A[i + p * lda] : A[p + i * lda];"),
+    "wrong_row_index_in_column_sum": (
+        "s += out[ii + jj * h];\n            Rc[ii] = s;",
+        "s += out[jj + ii * h];\n            Rc[ii] = s;"),
+    "threshold_zero": (
+        "return lambda * (fabs(alpha)", "return 0.0 * (fabs(alpha)"),
+    "fault_one_step_late": (
+        "if (f->target != TGT_ACC || f->k_index / P->bk != s)",
+        "if (f->target != TGT_ACC || f->k_index / P->bk + 1 != s)"),
+    "ragged_tile_loses_a_row": (
+        "const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 : P->tm;\n    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;\n    const double alpha",
+        "const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 - 1 : P->tm;\n    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;\n    const double alpha"),
+    "correction_not_confirmed": (
+        "if (fabs(sc + fixed - Pc[ibad]) <= tc[ibad]) {", "if (1) {"),
+    "bf16_exponent_bias_off_by_one": (
+        "v = ldexp((double)(128 + f), e - 127 - 7);", "v = ldexp((double)(128 + f), e - 126 - 7);"),
+    "e4m3_nan_code_wrong": (
+        "if (e == 0xf && f == 0x7)", "if (e == 0xf && f == 0x6)"),
+    "beta_zero_reads_cin": (
+        "col[i] = (beta == 0.0) ? alpha * col[i]\n                                   : alpha * col[i] + beta * Cin[i + j * ldc];",
+        "col[i] = alpha * col[i] + beta * Cin[i + j * ldc];"),
+}
+
+
+def _format_pins(orc):
+    import numpy as np
+    import torch
+    codes = np.arange(1 << 16, dtype=np.uint16)
+    mine = orc.decode_bf16(codes)
+    ref = torch.from_numpy(codes.view(np.int16)).view(torch.bfloat16).double().numpy()
+    assert np.array_equal(np.isnan(mine), np.isnan(ref))
+    assert np.array_equal(mine[~np.isnan(mine)], ref[~np.isnan(ref)])
+    c8 = np.arange(256, dtype=np.uint8)
+    mine = orc.decode_e4m3(c8)
+    ref = torch.from_numpy(c8).view(torch.float8_e4m3fn).double().numpy()
+    assert np.array_equal(np.isnan(mine), np.isnan(ref))
+    assert np.array_equal(mine[~np.isnan(mine)], ref[~np.isnan(ref)])
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(O.SRC).read()
+    assert src.count(old) == 1, "mutation site not found: " + name
+    path = os.path.join(tmp_path, "mutant.c")
+    with open(path, "w") as fh:
+        fh.write(src.replace(old, new))
+    mutant = O.Oracle(O.compile_source(path, os.path.join(tmp_path, "libmutant.so")))
+    failures = []
+    for pin in oracle_pins.ALL_PINS + [_format_pins]:
+        try:
+            pin(mutant)
+        except AssertionError:
+            failures.append(pin.__name__)
+    assert failures, "no pin caught the mutant " + name
