@@ -1,0 +1,211 @@
+/*
+ * ftgemm.h -- C ABI of libftgemm, a fault-tolerant GEMM for AMD MI355X (gfx950).
+ *
+ * The library computes C = alpha * op(A) * op(B) + beta * C with
+ * algorithm-based fault tolerance fused into the kernel, following
+ * "FT-GEMM: A Fault Tolerant High Performance GEMM Implementation on x86
+ * CPUs" (Wu, Zhai, Huang, Jian, Chen; HPDC'23):
+ *   - the two checksum vectors of each output tile are encoded while C is
+ *     scaled by beta (Section 2.2);
+ *   - the operand checksums are formed from the operand values as they are
+ *     staged for the multiplication, and feed the encoded checksums of C
+ *     (Section 2.2; Section 2.3 for the split of the work into independent
+ *     parts, here one output tile per GPU workgroup);
+ *   - the reference checksums are the sums of the computed tile, taken from
+ *     registers before it is written (Section 2.2);
+ *   - a single soft error per tile (the fail-continue fault model of
+ *     Section 1) is located at the crossing of the disagreeing row and
+ *     column and rebuilt before C is written; a tile with several errors
+ *     is computed again.
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are column-major (BLAS).  op(X) = X for FTGEMM_OP_N and X^T
+ *     for FTGEMM_OP_T.  op(A) is m x k, op(B) is k x n, C is m x n.
+ *     lda >= max(1, transA == N ? m : k), ldb >= max(1, transB == N ? k : n),
+ *     ldc >= max(1, m).
+ *   - A, B and C are device pointers owned by the caller; C is read (unless
+ *     beta == 0) and written.  Nothing is retained after the call returns.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL is the
+ *     default stream).  A report, when requested, is complete once the
+ *     stream has been synchronised.
+ *   - Arguments are checked on the host before any HIP call.  An invalid
+ *     one returns FTGEMM_ERR_INVALID_ARG and ftgemm_last_invalid_arg()
+ *     gives its 1-based BLAS position (1 transA, 2 transB, 3 m, 4 n, 5 k,
+ *     6 alpha, 7 A, 8 lda, 9 B, 10 ldb, 11 beta, 12 C, 13 ldc, 14 the
+ *     report / descriptor), as xerbla does.
+ *   - Quick returns: m == 0 or n == 0, or (alpha == 0 or k == 0) with
+ *     beta == 1, do nothing.  alpha == 0 or k == 0 otherwise only scales C
+ *     by beta (beta == 0 stores zeros and never reads C).
+ *   - Faults found on the device never fail a call (the fail-continue
+ *     model): they show up in the report only.  The status covers host-side
+ *     argument, launch and memory errors.
+ *   - Calls that ask for a report share one device-side report area per
+ *     GPU: such calls must not overlap on one GPU (issue them on one stream,
+ *     or synchronise in between).
+ */
+#ifndef FTGEMM_H
+#define FTGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { FTGEMM_OP_N = 0, FTGEMM_OP_T = 1 } ftgemm_op;
+
+/* Input type.  F64: A, B, C are double.  BF16: A, B are bfloat16 (raw
+ * 16-bit codes), C is float.  FP8_E4M3: A, B are OCP E4M3 (finite) codes
+ * with per-tensor scales scaleA, scaleB (value = code * scale), C is float.
+ * The low-precision types accumulate in FP32 on the matrix cores; the
+ * checksum comparison and the correction are done in FP64. */
+typedef enum { FTGEMM_F64 = 0, FTGEMM_BF16 = 1, FTGEMM_FP8_E4M3 = 2 } ftgemm_dtype;
+
+typedef enum {
+    FTGEMM_OK = 0,
+    FTGEMM_ERR_INVALID_ARG = 1,
+    FTGEMM_ERR_UNSUPPORTED = 2,
+    FTGEMM_ERR_HIP = 3,
+    FTGEMM_ERR_NO_MEMORY = 4
+} ftgemm_status;
+
+/* Outcome of a tile whose checksums disagreed. */
+enum {
+    FTGEMM_KIND_CORRECTED = 1,      /* one element located and rebuilt          */
+    FTGEMM_KIND_CHECKSUM_ONLY = 2,  /* one encoded checksum entry was wrong;
+                                       the data was left as computed           */
+    FTGEMM_KIND_RECOMPUTED = 3,     /* several errors: the tile was computed
+                                       again and then verified clean           */
+    FTGEMM_KIND_UNCORRECTABLE = 4   /* still inconsistent after recomputation   */
+};
+
+/* Fault injection (test hook): mode and target. */
+enum { FTGEMM_INJ_ADD = 0, FTGEMM_INJ_BITFLIP = 1 };
+enum { FTGEMM_TGT_ACC = 0, FTGEMM_TGT_ROW_CHECKSUM = 1, FTGEMM_TGT_COL_CHECKSUM = 2 };
+
+/* One detection.  row / col are global indices into C (-1 where the kind
+ * has none: a checksum-only record names the row of a disagreeing column
+ * checksum entry, or the column of a disagreeing row checksum entry).
+ * d_* are the residuals (reference minus encoded) of the row checksum of
+ * column `col` and of the column checksum of row `row`, tau_* the
+ * thresholds they were held to; before / after are the element of C before
+ * and after correction. */
+typedef struct {
+    int32_t problem;
+    int32_t kind;
+    int32_t tile_m, tile_n;
+    int64_t row, col;
+    int32_t nbad_rows, nbad_cols;
+    double d_row, d_col;
+    double tau_row, tau_col;
+    double before, after;
+} ftgemm_fault_record;
+
+/* Echo of one injected fault as applied on the device: the perturbed
+ * quantity (an accumulator before alpha is applied, or an encoded checksum
+ * entry) before and after the fault. */
+typedef struct {
+    int32_t problem;
+    int32_t applied;
+    int64_t row, col, k_index;
+    double before, after;
+} ftgemm_injection_echo;
+
+/* Per-call report.  The caller sets the capacities and the two arrays
+ * (host memory it owns; NULL with capacity 0 is allowed); the library fills
+ * the rest.  Records beyond a capacity are dropped but still counted. */
+typedef struct {
+    uint64_t tiles_verified;
+    uint64_t detected;          /* tiles whose checksums disagreed          */
+    uint64_t corrected, checksum_only, recomputed, uncorrectable;
+    double max_ratio;           /* largest |residual| / threshold over the
+                                   checksum entries that passed: the margin
+                                   of the rounding-error threshold          */
+    uint32_t record_count, echo_count;
+    uint32_t record_capacity, echo_capacity;
+    ftgemm_fault_record *records;
+    ftgemm_injection_echo *echoes;
+} ftgemm_report;
+
+/* One planned soft error (test hook).  It lands after the inner-dimension
+ * step containing k_index has been accumulated (ACC target), or on the
+ * encoded checksum entry of column `col` (ROW_CHECKSUM) / row `row`
+ * (COL_CHECKSUM) of the tile holding C(row, col).  BITFLIP flips bit `bit`
+ * of the accumulator in its own precision (FP64 for F64, FP32 otherwise);
+ * checksum targets take ADD only.  `problem` selects the problem of a
+ * batched call (0 otherwise). */
+typedef struct {
+    int32_t problem;
+    int32_t mode;
+    int32_t target;
+    int32_t bit;
+    int64_t row, col, k_index;
+    double delta;
+} ftgemm_injection;
+
+/* A GEMM described in full, for ftgemm_gemm_ex and ftgemm_gemm_batched.
+ * abft = 0 runs the same kernel with every checksum operation compiled out
+ * (the plain-GEMM baseline). */
+typedef struct {
+    ftgemm_dtype dtype;
+    ftgemm_op transA, transB;
+    int32_t abft;
+    int64_t m, n, k, lda, ldb, ldc;
+    double alpha, beta;
+    double scaleA, scaleB;          /* FP8 only; ignored otherwise */
+    const void *A;
+    const void *B;
+    void *C;
+} ftgemm_gemm_desc;
+
+/* FP64 fault-tolerant GEMM (Sections 2.2 and 2.3):
+ *   C = alpha * op(A) * op(B) + beta * C, A/B/C double, device pointers.
+ * report: NULL, or filled after the stream synchronises. */
+ftgemm_status ftgemm_gemm(ftgemm_op transA, ftgemm_op transB, int64_t m, int64_t n,
+                          int64_t k, double alpha, const double *A, int64_t lda,
+                          const double *B, int64_t ldb, double beta, double *C,
+                          int64_t ldc, ftgemm_report *report, void *stream);
+
+/* Any input type, with or without the fault tolerance (desc->abft). */
+ftgemm_status ftgemm_gemm_ex(const ftgemm_gemm_desc *desc, ftgemm_report *report,
+                             void *stream);
+
+/* `count` independent GEMMs (Section 2.3's independent parts, taken to
+ * whole problems), each with its own checksums, in one persistent launch
+ * replayed from a captured HIP graph.  problems: host array of `count`
+ * descriptors (device data pointers); all must share dtype and abft.
+ * reports: NULL or a host array of `count` reports, one per problem. */
+ftgemm_status ftgemm_gemm_batched(int32_t count, const ftgemm_gemm_desc *problems,
+                                  ftgemm_report *reports, void *stream);
+
+/* The same problems launched one by one (the baseline the persistent
+ * launch is measured against). */
+ftgemm_status ftgemm_gemm_batched_loop(int32_t count, const ftgemm_gemm_desc *problems,
+                                       ftgemm_report *reports, void *stream);
+
+/* Arm the fault plan (test hook): it applies to every following call until
+ * replaced; n == 0 clears it.  The plan is copied. */
+ftgemm_status ftgemm_set_fault_plan(const ftgemm_injection *plan, int32_t n);
+
+/* Verification tile (tm x tn), inner step bk and split of the inner
+ * dimension chosen for a problem.  split_k > 1 means the inner dimension is
+ * cut into split_k slices, each verified as its own tile. */
+ftgemm_status ftgemm_query_tiling(ftgemm_dtype dtype, int64_t m, int64_t n, int64_t k,
+                                  int32_t *tm, int32_t *tn, int32_t *bk,
+                                  int32_t *split_k);
+
+/* 1-based position of the argument rejected by the last call on this
+ * thread that returned FTGEMM_ERR_INVALID_ARG (0 if none). */
+int32_t ftgemm_last_invalid_arg(void);
+
+const char *ftgemm_status_string(ftgemm_status status);
+
+/* Frees the library's device workspace (report areas, fault plans, batched
+ * descriptors, captured graphs) on every GPU it touched. */
+void ftgemm_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTGEMM_H */

@@ -1,0 +1,22 @@
+// ftgemm_kernels.h -- launchers of the libftgemm kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ftgemm_device.h"
+
+namespace ftg {
+
+// FP64 tile kernel (one 128 x 128 output tile per workgroup).
+hipError_t launch_f64(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream);
+void tiling_f64(int *tm, int *tn, int *bk);
+
+// C = beta * C over an m x n column-major matrix of double (f64) or float.
+hipError_t launch_scale(void *C, bool f64, int64_t m, int64_t n, int64_t ldc, double beta,
+                        hipStream_t stream);
+
+// Clear a report area: counters and the first n echo slots.
+hipError_t launch_clear_report(DevCounters *ct, int ncounters, ftgemm_injection_echo *echo,
+                               int nech, hipStream_t stream);
+
+}  // namespace ftg

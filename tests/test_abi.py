@@ -1,0 +1,85 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, and rejects bad arguments on the host (before any HIP
+call) with the BLAS position of the culprit."""
+import ctypes as C
+
+import pytest
+
+from paper_2305_02444_amd import ftgemm as F
+
+
+def test_exports_every_declared_function():
+    names = F.exported_functions_in_header()
+    assert "ftgemm_gemm" in names and "ftgemm_gemm_batched" in names
+    L = F.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def _gemm(**kw):
+    a = dict(ta=0, tb=0, m=4, n=4, k=4, alpha=1.0, A=1, lda=4, B=1, ldb=4, beta=0.0, Cp=1,
+             ldc=4)
+    a.update(kw)
+    L = F.lib()
+    st = L.ftgemm_gemm(a["ta"], a["tb"], a["m"], a["n"], a["k"], a["alpha"], a["A"], a["lda"],
+                       a["B"], a["ldb"], a["beta"], a["Cp"], a["ldc"], None, None)
+    return st, L.ftgemm_last_invalid_arg()
+
+
+@pytest.mark.parametrize("kw,pos", [
+    (dict(ta=2), 1), (dict(tb=-1), 2), (dict(m=-1), 3), (dict(n=-5), 4), (dict(k=-1), 5),
+    (dict(alpha=float("nan")), 6), (dict(A=None), 7), (dict(lda=3), 8),
+    (dict(ta=1, lda=3), 8), (dict(B=None), 9), (dict(ldb=3), 10), (dict(tb=1, ldb=3), 10),
+    (dict(beta=float("inf")), 11), (dict(Cp=None), 12), (dict(ldc=3), 13),
+])
+def test_invalid_argument_positions(kw, pos):
+    st, p = _gemm(**kw)
+    assert st == F.ERR_INVALID_ARG and p == pos
+
+
+def test_quick_returns_touch_nothing():
+    # m == 0 / n == 0: nothing to do, null pointers are fine
+    assert _gemm(m=0, A=None, B=None, Cp=None, lda=4, ldc=1) == (F.OK, 0)
+    assert _gemm(n=0, A=None, B=None, Cp=None) == (F.OK, 0)
+    # alpha == 0 and beta == 1, or k == 0 and beta == 1: C unchanged
+    assert _gemm(alpha=0.0, beta=1.0, A=None, B=None) == (F.OK, 0)
+    assert _gemm(k=0, beta=1.0, A=None, B=None) == (F.OK, 0)
+
+
+def test_gemm_ex_descriptor_checks():
+    L = F.lib()
+    assert L.ftgemm_gemm_ex(None, None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 14
+    d = F.GemmDesc()
+    d.dtype, d.m, d.n, d.k, d.lda, d.ldb, d.ldc = 7, 4, 4, 4, 4, 4, 4
+    d.alpha, d.A, d.B, d.C = 1.0, 1, 1, 1
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 14
+    d.dtype, d.scaleA, d.scaleB = F.FP8_E4M3, 0.0, 1.0
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+
+
+def test_fault_plan_validation():
+    L = F.lib()
+    bad = F.Injection(0, 5, 0, 0, 1, 1, 1, 1.0)  # unknown mode
+    assert L.ftgemm_set_fault_plan(C.byref(bad), 1) == F.ERR_INVALID_ARG
+    bad = F.Injection(0, F.INJ_BITFLIP, F.TGT_ROW_CHECKSUM, 3, 1, 1, 1, 0.0)
+    assert L.ftgemm_set_fault_plan(C.byref(bad), 1) == F.ERR_INVALID_ARG
+    bad = F.Injection(0, F.INJ_BITFLIP, F.TGT_ACC, 64, 1, 1, 1, 0.0)
+    assert L.ftgemm_set_fault_plan(C.byref(bad), 1) == F.ERR_INVALID_ARG
+    assert L.ftgemm_set_fault_plan(None, -1) == F.ERR_INVALID_ARG
+    ok = F.Injection(0, F.INJ_ADD, F.TGT_ACC, 0, 1, 1, 1, 2.0)
+    assert L.ftgemm_set_fault_plan(C.byref(ok), 1) == F.OK
+    assert L.ftgemm_set_fault_plan(None, 0) == F.OK
+
+
+def test_query_tiling():
+    tm, tn, bk, sk = F.query_tiling(F.F64, 256, 256, 256)
+    assert (tm, tn, bk, sk) == (128, 128, 16, 1)
+    assert F.lib().ftgemm_query_tiling(9, 1, 1, 1, None, None, None, None) == F.ERR_INVALID_ARG
+
+
+def test_status_strings():
+    L = F.lib()
+    for s in range(5):
+        assert L.ftgemm_status_string(s).startswith(b"FTGEMM")

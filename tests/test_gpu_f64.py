@@ -1,0 +1,189 @@
+"""FP64 fault-tolerant GEMM on the GPU against the CPU oracle.
+
+Tolerance: normwise max|C - C_oracle| / max|C_oracle| <= 1e-12 (FP64).
+Flagged (row, col, kind) sets must agree exactly with the oracle's and with
+the accepted fault plan."""
+import numpy as np
+import pytest
+
+from gpu_util import f64_tiling, flagged, gpu_f64, normwise, say, to_oracle
+from oracle import oracle as O
+from paper_2305_02444_amd import ftgemm as F
+from paper_2305_02444_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _plan_acc(g, m, n, k, tm, tn, count, delta):
+    return synth.additive_plan(g, m, n, k, tm, tn, count,
+                               delta if callable(delta) else (lambda _g: delta))
+
+
+def _compare(A, B, Cin, alpha, beta, ta, tb, plan, tiles=None):
+    m, n = Cin.shape
+    k = A.shape[0] if ta else A.shape[1]
+    tm, tn, bk = f64_tiling(m, n, k)
+    say("case m=%d n=%d k=%d ta=%d tb=%d faults=%d" % (m, n, k, ta, tb, len(plan)))
+    got, rep = gpu_f64(A, B, Cin, alpha, beta, ta, tb, plan)
+    ref = O.default().ftgemm(A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, 64,
+                             to_oracle(plan), tiles=tiles)
+    if tiles is None:
+        err = normwise(got, ref.C)
+    else:
+        mask = ~np.isnan(ref.C)
+        err = normwise(got[mask], ref.C[mask])
+    assert err <= TOL, err
+    recs = rep.records
+    if tiles is not None:
+        tiles_m = -(-m // tm)
+        keep = set(int(t) for t in tiles)
+        recs = [r for r in recs if r["tile_m"] + r["tile_n"] * tiles_m in keep]
+    assert flagged(recs) == flagged(ref.records)
+    return got, rep, ref
+
+
+def test_c1_256_four_additive_errors():
+    """256^3, alpha 1, beta 0.5, U[-1,1] from seed 0; four +1e3 faults on
+    accumulators in four distinct tiles, all located and corrected."""
+    A, B, Cin = synth.operands(1, 0, 256, 256, 256, "uniform")
+    g = synth.rng(1, 0, synth.STREAM_PLAN)
+    plan = _plan_acc(g, 256, 256, 256, 128, 128, 4, 1e3)
+    got, rep, ref = _compare(A, B, Cin, 1.0, 0.5, False, False, plan)
+    assert sorted((f.row, f.col) for f in plan) == sorted((r[0], r[1]) for r in flagged(rep.records))
+    assert rep.corrected == 4 and rep.detected == 4 and rep.tiles_verified == 4
+    assert all(r["kind"] == F.KIND_CORRECTED for r in rep.records)
+    for e, f in zip(rep.echoes, plan):
+        assert e["applied"] and (e["row"], e["col"]) == (f.row, f.col)
+        assert abs((e["after"] - e["before"]) - 1e3) < 1e-9
+    assert 0 < rep.max_ratio < 1
+
+
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+def test_ragged_transposes(ta, tb):
+    m, n, k = 300, 260, 77
+    A, B, Cin = synth.operands(2, 1, m, n, k, "normal", ta, tb)
+    g = synth.rng(2, 1, synth.STREAM_PLAN)
+    plan = _plan_acc(g, m, n, k, 128, 128, 5, synth.log_magnitude(3.0))
+    got, rep, ref = _compare(A, B, Cin, -0.7, 1.3, ta, tb, plan)
+    assert rep.corrected == 5
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 3, 5), (128, 128, 16), (129, 127, 17),
+                                   (64, 200, 1), (200, 64, 300)])
+def test_small_and_edge_shapes(m, n, k):
+    A, B, Cin = synth.operands(3, m * 1000 + n, m, n, k, "uniform")
+    _compare(A, B, Cin, 1.0, 1.0, False, False, [])
+
+
+def test_special_cases():
+    A, B, Cin = synth.operands(4, 0, 70, 50, 40, "uniform")
+    # alpha == 0: C <- beta C
+    got, rep = gpu_f64(A, B, Cin, 0.0, 0.5)
+    assert np.array_equal(got, 0.5 * Cin)
+    # beta == 0: C_in never read, NaNs do not propagate
+    nanC = np.full_like(Cin, np.nan)
+    got, rep = gpu_f64(A, B, nanC, 1.0, 0.0)
+    ref = O.default().gemm(A, B, None, 1.0, 0.0)
+    assert normwise(got, ref) <= TOL and not rep.records
+    # k == 0: C <- beta C
+    A0 = np.zeros((70, 0), order="F")
+    B0 = np.zeros((0, 50), order="F")
+    got, rep = gpu_f64(A0, B0, Cin, 1.0, 2.0)
+    assert np.array_equal(got, 2.0 * Cin)
+    # beta == 1 and alpha == 0: untouched
+    got, rep = gpu_f64(A, B, Cin, 0.0, 1.0)
+    assert np.array_equal(got, Cin)
+
+
+def test_padded_leading_dimension_of_c():
+    A, B, Cin = synth.operands(5, 0, 130, 140, 33, "uniform")
+    got, rep = gpu_f64(A, B, Cin, 1.0, 1.0, ldc_pad=7)
+    ref = O.default().gemm(A, B, Cin, 1.0, 1.0)
+    assert normwise(got, ref) <= TOL
+
+
+def test_fault_classes():
+    """Two faults in one tile -> recomputed; a fault on an encoded checksum
+    only -> checksum-only, data untouched; a data fault plus a fault on its
+    column's encoded checksum -> recomputed; an FP64 exponent flip that
+    yields Inf/NaN -> rebuilt; a perturbation far below the threshold ->
+    not flagged."""
+    m = n = k = 256
+    A, B, Cin = synth.operands(6, 0, m, n, k, "uniform")
+    F_ = synth.Fault
+    part = A[:, :16] @ B[:16, :]
+    cand = np.argwhere((np.abs(part) >= 1) & (np.abs(part) < 2))
+    ri, ci = map(int, cand[0])
+    plan = [
+        F_(3, 5, 10, synth.ADD, 50.0), F_(40, 90, 200, synth.ADD, -20.0),      # tile (0,0)
+        F_(130, 7, 0, synth.ADD, 3.0, target=synth.TGT_ROW_CHECKSUM),           # tile (1,0)
+        F_(10, 200, 5, synth.ADD, 40.0),
+        F_(0, 200, 5, synth.ADD, 2.0, target=synth.TGT_ROW_CHECKSUM),           # tile (0,1)
+    ]
+    # a flip in the tile (1,1), on an accumulator whose first-step value is in [1,2)
+    tile_of = lambda r, c: (r // 128, c // 128)
+    used = {tile_of(f.row, f.col) for f in plan}
+    for ri, ci in map(tuple, cand):
+        if tile_of(ri, ci) not in used:
+            break
+    plan.append(F_(int(ri), int(ci), 3, synth.BITFLIP, 0.0, 62))
+    got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, False, False, plan)
+    kinds = sorted(r["kind"] for r in rep.records)
+    assert kinds == sorted([F.KIND_RECOMPUTED, F.KIND_CHECKSUM_ONLY, F.KIND_RECOMPUTED,
+                            F.KIND_CORRECTED])
+    flip = [e for e in rep.echoes if e["row"] == ri and e["col"] == ci][0]
+    assert flip["applied"] and not np.isfinite(flip["after"])
+    # tiny fault: not flagged
+    tr, tc = O.default().tile_thresholds(A, B, 0, 0, Cin, 1.0, 1.0, tm=128, tn=128, bk=16)
+    tiny = [F_(7, 9, 30, synth.ADD, 1e-3 * min(tr.min(), tc.min()))]
+    got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, False, False, tiny)
+    assert not rep.records
+
+
+def test_plain_kernel_matches_oracle():
+    A, B, Cin = synth.operands(7, 0, 333, 222, 111, "normal")
+    got, rep = gpu_f64(A, B, Cin, 1.5, -0.5, abft=False)
+    assert normwise(got, O.default().gemm(A, B, Cin, 1.5, -0.5)) <= TOL
+
+
+def test_bitwise_reproducible():
+    A, B, Cin = synth.operands(8, 0, 384, 256, 200, "uniform")
+    plan = [synth.Fault(100, 100, 50, synth.ADD, 7.0)]
+    g1, r1 = gpu_f64(A, B, Cin, 1.0, 1.0, plan=plan)
+    g2, r2 = gpu_f64(A, B, Cin, 1.0, 1.0, plan=plan)
+    assert np.array_equal(g1, g2) and flagged(r1.records) == flagged(r2.records)
+
+
+@pytest.mark.parametrize("size", [2048])
+def test_c2_square_full_compare(size):
+    """m = n = k = 2048, alpha = beta = 1, U[-1,1]: error-free, then one
+    fault per 64 tiles of size 10^U(0,6) times the typical |C|."""
+    A, B, Cin = synth.operands(20, size, size, size, size, "uniform")
+    _, rep, _ = _compare(A, B, Cin, 1.0, 1.0, False, False, [])
+    assert not rep.records and rep.max_ratio < 1
+    sigma = np.sqrt(size / 9.0 + 1.0 / 3.0)
+    ntiles = (size // 128) ** 2
+    g = synth.rng(20, size, synth.STREAM_PLAN)
+    plan = _plan_acc(g, size, size, size, 128, 128, -(-ntiles // 64), synth.log_magnitude(sigma))
+    _, rep, _ = _compare(A, B, Cin, 1.0, 1.0, False, False, plan)
+    assert rep.corrected == len(plan) == rep.detected
+
+
+def test_c2_8192_sampled_tiles():
+    """Full size 8192^3 as timed by the benchmark; the oracle checks every
+    tile that holds a fault plus sampled clean and corner tiles."""
+    size = 8192
+    A, B, Cin = synth.operands(20, size, size, size, size, "uniform")
+    sigma = np.sqrt(size / 9.0 + 1.0 / 3.0)
+    tiles_m = size // 128
+    g = synth.rng(20, size, synth.STREAM_PLAN)
+    plan = _plan_acc(g, size, size, size, 128, 128, tiles_m * tiles_m // 64,
+                     synth.log_magnitude(sigma))
+    faulty = sorted({(f.row // 128) + (f.col // 128) * tiles_m for f in plan})
+    extra = [0, tiles_m * tiles_m - 1, tiles_m - 1] + list(synth.rng(20, 1, 9).choice(
+        tiles_m * tiles_m, 8, replace=False))
+    tiles = sorted(set(faulty[:24]) | set(int(t) for t in extra))
+    got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, False, False, plan, tiles=tiles)
+    assert rep.corrected == len(plan) == rep.detected
+    assert rep.tiles_verified == tiles_m * tiles_m
