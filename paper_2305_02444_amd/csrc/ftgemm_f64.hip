@@ -35,6 +35,10 @@ constexpr double U = 1.1102230246251565e-16;  // 2^-53, unit roundoff of FP64
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// v_mfma_f64_16x16x4_f64 operands and result, lane l = 16 q + c (q < 4, c < 16):
+// A fragment holds A[c][q], B fragment holds B[q][c], and result register r
+// holds D[4 r + q][c] (measured on gfx950).
+
 struct Stage {
     double A[BK][SA];  // A tile, [p][i]
     double B[BK][SB];  // B tile, [p][j]
@@ -256,9 +260,9 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                             continue;
                         // owner: wave, lane and register of C(row, col)
                         const int ow = (tf.row >> 6) + 2 * (tf.col >> 6);
-                        const int ol = 16 * ((tf.row & 15) >> 2) + (tf.col & 15);
+                        const int ol = 16 * (tf.row & 3) + (tf.col & 15);
                         const int sel = ((tf.row & 63) >> 4) * 16 + ((tf.col & 63) >> 4) * 4 +
-                                        (tf.row & 3);
+                                        ((tf.row & 15) >> 2);
                         if (w != ow) continue;
                         double before = 0.0;
 #pragma unroll
@@ -295,7 +299,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int row = wm * 64 + 16 * mi + 4 * q + r;
+                        const int row = wm * 64 + 16 * mi + 4 * r + q;
                         const int col = wn * 64 + 16 * ni + c16;
                         if (row < hrows && col < wcols) {
                             double *pc = C + (i0 + row) + (j0 + col) * ldc;
@@ -359,7 +363,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 double row_o = 0, row_c = 0, row_c2 = 0;
-                const int row = wm * 64 + 16 * mi + 4 * q + r;
+                const int row = wm * 64 + 16 * mi + 4 * r + q;
 #pragma unroll
                 for (int ni = 0; ni < 4; ++ni) {
                     const int col = wn * 64 + 16 * ni + c16;
@@ -497,7 +501,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int row = wm * 64 + 16 * mi + 4 * q + r;
+                        const int row = wm * 64 + 16 * mi + 4 * r + q;
                         const int col = wn * 64 + 16 * ni + c16;
                         const double o = acc[mi][ni][r];
                         if (col == js && row != is) s_col += o;
@@ -512,8 +516,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             const double fixed = sm.fin_col[js] - sc;
             if (fabs(sr + fixed - sm.fin_row[is]) <= sm.tau_row[is]) {
                 const int ow = (is >> 6) + 2 * (js >> 6);
-                const int ol = 16 * ((is & 15) >> 2) + (js & 15);
-                const int omi = (is & 63) >> 4, oni = (js & 63) >> 4, orr = is & 3;
+                const int ol = 16 * (is & 3) + (js & 15);
+                const int omi = (is & 63) >> 4, oni = (js & 63) >> 4, orr = (is & 15) >> 2;
                 if (w == ow && lane == ol) {
 #pragma unroll
                     for (int mi = 0; mi < 4; ++mi)
@@ -543,7 +547,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
         // the owner lane of a corrected element knows its old value
         if (kind == FTGEMM_KIND_CORRECTED) {
             const int ow = (first_i >> 6) + 2 * (first_j >> 6);
-            const int ol = 16 * ((first_i & 15) >> 2) + (first_j & 15);
+            const int ol = 16 * (first_i & 3) + (first_j & 15);
             if (w == ow && lane == ol) sm.red[0][0] = rec_before;
             __syncthreads();
             rec_before = sm.red[0][0];
@@ -587,7 +591,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = wm * 64 + 16 * mi + 4 * q + r;
+                    const int row = wm * 64 + 16 * mi + 4 * r + q;
                     const int col = wn * 64 + 16 * ni + c16;
                     if (row < hrows && col < wcols)
                         C[(i0 + row) + (j0 + col) * ldc] = acc[mi][ni][r];

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
@@ -49,10 +51,20 @@ ftgemm_status invalid(int pos)
     return FTGEMM_ERR_INVALID_ARG;
 }
 
+// HIP failures become FTGEMM_ERR_HIP (or _NO_MEMORY); with FTGEMM_VERBOSE
+// set in the environment the failing call and HIP's message go to stderr.
+void report_hip_failure(const char *what, hipError_t e)
+{
+    static const bool verbose = std::getenv("FTGEMM_VERBOSE") != nullptr;
+    if (verbose)
+        std::fprintf(stderr, "libftgemm: %s failed: %s\n", what, hipGetErrorString(e));
+}
+
 #define HIP_TRY(expr)                                  \
     do {                                               \
         hipError_t e_ = (expr);                        \
         if (e_ != hipSuccess) {                        \
+            report_hip_failure(#expr, e_);             \
             if (e_ == hipErrorOutOfMemory)             \
                 return FTGEMM_ERR_NO_MEMORY;           \
             return FTGEMM_ERR_HIP;                     \

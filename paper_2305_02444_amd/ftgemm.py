@@ -78,6 +78,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime with the same soname; loading torch
+        # first makes libftgemm bind to that one copy instead of a second one.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libftgemm.so is not built (python -m paper_2305_02444_amd.build)")
         L = C.CDLL(LIB_PATH)
