@@ -54,15 +54,16 @@ struct GemmArgs {
 template <int kCtrl>
 __device__ __forceinline__ double dpp_f64(double v)
 {
-    int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), kCtrl, 0xf, 0xf, false);
-    int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), kCtrl, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
+    const int lo = (int)__double2loint(v), hi = (int)__double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, kCtrl, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, kCtrl, 0xf, 0xf, false));
 }
 
 template <int kCtrl>
 __device__ __forceinline__ float dpp_f32(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, false));
+    const int x = __float_as_int(v);
+    return __int_as_float(__builtin_amdgcn_update_dpp(x, x, kCtrl, 0xf, 0xf, false));
 }
 
 // DPP controls (GFX9 encoding).
@@ -90,12 +91,43 @@ __device__ __forceinline__ float sum16f(float v)
     return v;
 }
 
+// v_permlane16_swap / v_permlane32_swap (gfx950) exchange rows of 16 lanes
+// (odd rows of the first operand with even rows of the second) or halves of
+// 32 lanes; with both operands equal to v, the two results hold v and its
+// partner in every lane, so their sum is the pair sum, bitwise the same in
+// both lanes.
+__device__ __forceinline__ double pair_sum16(double v)
+{
+    const int lo = (int)__double2loint(v), hi = (int)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
+
+__device__ __forceinline__ double pair_sum32(double v)
+{
+    const int lo = (int)__double2loint(v), hi = (int)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
+
+__device__ __forceinline__ float pair_sum16f(float v)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
+__device__ __forceinline__ float pair_sum32f(float v)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
 // Sum over the four rows of 16 (lanes l, l^16, l^32, l^48).
 __device__ __forceinline__ double sum_rows(double v)
 {
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+    return pair_sum32(pair_sum16(v));
 }
 
 __device__ __forceinline__ double sum64(double v)

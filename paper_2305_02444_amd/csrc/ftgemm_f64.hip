@@ -1,36 +1,38 @@
 // ftgemm_f64.hip -- FP64 fault-tolerant GEMM tile for gfx950.
 //
-// One workgroup (4 waves, 2 x 2) owns a 128 x 128 output tile and walks the
+// One workgroup (8 waves, 2 x 4) owns a 128 x 128 output tile and walks the
 // inner dimension in steps of 16.  Each step is staged HBM -> VGPR -> LDS
 // (double-buffered, one barrier per step) and multiplied with
-// v_mfma_f64_16x16x4_f64; every wave owns a 64 x 64 sub-tile.
+// v_mfma_f64_16x16x4_f64; every wave owns a 64 x 32 sub-tile, and the two
+// waves on each SIMD hide each other's LDS and barrier latency.
 //
-// Fault tolerance (FT-GEMM, Section 2.2), all on values already in
-// registers, so it adds no HBM traffic:
-//   * operand checksums: the MFMA operand fragments a wave reads from LDS are
-//     reused for x = e^T A_I (column sums of the A tile), y = B_J e (row sums
-//     of the B tile) and the squared norms of A's rows / B's columns;
-//   * encoded checksums of C: Pc_i += A(i,:) y and Pr_j += x B(:,j), one step
-//     behind so that the partial sums produced by other waves are complete
-//     (they travel through LDS and the step's single barrier);
+// Fault tolerance (FT-GEMM, Section 2.2), entirely on the staged operand
+// values in registers, so it adds no HBM traffic and leaves the MFMA loop
+// untouched:
+//   * every thread's 4 staged elements of a step share one inner index p;
+//     before the step's barrier it adds them into the operand checksums
+//     x_p = sum_i A(i,p) and y_p = sum_j B(p,j) (a short cross-lane
+//     reduction finishes them in LDS) and into the squared norms of its rows
+//     of A / columns of B (each staged element reused, as in the paper's
+//     packing routines);
+//   * after the barrier, with x_p and y_p complete, the same registers feed
+//     the encoded checksums Pc_i += A(i,p) y_p and Pr_j += x_p B(p,j);
 //   * the encoding of C_in is fused into the beta pass of the epilogue, and
 //     the reference checksums are summed from the accumulator registers
-//     before anything is written (Section 2.2);
+//     before anything is written;
 //   * verify, locate, rebuild and confirm one element per tile; a tile with
-//     several disagreements is computed again (the same workgroup, C not yet
-//     written).
-// Work split between the waves (Section 2.3's partition, inside one tile):
-// waves 0 and 3 handle the A-side checksums of rows 0-63 and 64-127, waves 1
-// and 2 the B-side checksums of columns 0-63 and 64-127, so every wave does
-// the same amount of checksum work next to the same amount of MFMA work.
+//     several disagreements is computed again by the same workgroup (C is
+//     not written until the tile verifies).
 #include "ftgemm_device.h"
 #include "ftgemm_kernels.h"
 
 namespace ftg {
 namespace f64 {
 
-constexpr int TM = 128, TN = 128, BK = 16, NT = 256;
-constexpr int SA = TM + 1, SB = TN + 1;  // odd LDS strides: conflict-free transposed stores
+constexpr int TM = 128, TN = 128, BK = 32;
+constexpr int WM = 2, WN = 4, NW = WM * WN, NT = 64 * NW;  // 8 waves, 512 threads
+constexpr int EPT = TM * BK / NT;  // staged elements per thread per operand (8)
+constexpr int S = 145;  // LDS row stride in doubles (odd; 128 + one pad per 8)
 constexpr double U = 1.1102230246251565e-16;  // 2^-53, unit roundoff of FP64
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -38,16 +40,30 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // v_mfma_f64_16x16x4_f64 operands and result, lane l = 16 q + c (q < 4, c < 16):
 // A fragment holds A[c][q], B fragment holds B[q][c], and result register r
 // holds D[4 r + q][c] (measured on gfx950).
+//
+// Wave w = wm + 2 wn holds rows 64 wm .. +63 and columns 32 wn .. +31 as
+// acc[mi][ni][r] = C(64 wm + 16 mi + 4 r + q, 32 wn + 16 ni + c), mi < 4,
+// ni < 2, r < 4.
+
+// LDS column of tile index i: one pad slot after every 8, so lanes that each
+// store 4 consecutive elements spread over the banks, while 16 lanes that
+// read 16 consecutive elements stay conflict-free.
+__device__ __forceinline__ int phys(int i) { return i + (i >> 3); }
 
 struct Stage {
-    double A[BK][SA];  // A tile, [p][i]
-    double B[BK][SB];  // B tile, [p][j]
+    double A[BK][S];  // A tile, [p][phys(i)]
+    double B[BK][S];  // B tile, [p][phys(j)]
 };
 
 struct Epi {
-    double ref_row[2][TM], ref_col[2][TN];    // partial sums of the output
-    double cin_row[2][TM], cin_col[2][TN];    // partial sums of C_in
-    double cin2_row[2][TM], cin2_col[2][TN];  // partial sums of squares of C_in
+    double ref_row[WN][TM], ref_col[WM][TN];    // partial sums of the output
+    double cin_row[WN][TM], cin_col[WM][TN];    // partial sums of C_in
+    double cin2_row[WN][TM], cin2_col[WM][TN];  // partial sums of squares of C_in
+    double enc_row[NW][TM], enc_col[NW][TN];    // product part of the encoded checksums
+    double nrm_row[NW][TM], nrm_col[NW][TN];    // squared norms of A's rows / B's columns
+    double fin_row[TM], fin_col[TN];            // full encoded checksums
+    double tau_row[TM], tau_col[TN];
+    double d_row[TM], d_col[TN];
 };
 
 struct Smem {
@@ -55,59 +71,141 @@ struct Smem {
         Stage st[2];
         Epi epi;
     } u;
-    double xs[2][2][BK];  // [buffer][row half][p]: partial column sums of A
-    double ys[2][2][BK];  // [buffer][col half][p]: partial row sums of B
-    double enc_row[TM], enc_col[TN];  // product part of the encoded checksums
-    double nrm_row[TM], nrm_col[TN];  // squared norms of A's rows / B's columns
-    double fin_row[TM], fin_col[TN];  // full encoded checksums (with beta part)
-    double tau_row[TM], tau_col[TN];
-    double d_row[TM], d_col[TN];
-    double red[4][2];
-    double scal[4];  // |x|^2, |y|^2, |A_I|_F^2, |B_J|_F^2
+    double xs[2][BK][NW];  // [buffer][p][partial]: column sums of the A tile
+    double ys[2][BK][NW];  // [buffer][p][partial]: row sums of the B tile
+    double red[NW][2];
+    double vnrm[2][BK];    // x_p^2, y_p^2 summed over the steps (slot per p)
+    double scal[4];        // |x|^2, |y|^2, |A_I|_F^2, |B_J|_F^2
     TileFault faults[kMaxTileFaults];
     int nfaults;
     int nbad_r, nbad_c, ibad, jbad;
 };
 
-// Fetches one step's part of a stored (column-major) operand: TR stored rows
-// by 256 * 8 / TR stored columns.  Thread t takes stored row t % TR and
-// columns t / TR + r * (256 / TR), r = 0..7, so 64-lane waves read runs of
-// consecutive rows.  Stored rows past the matrix get an out-of-range offset;
-// stored columns past it fall outside the resource's extent; both read 0.
-template <int TR>
+// Fetches one step's part of a stored (column-major) operand: 8 elements per
+// thread, all at the same inner index p.
+//   kContig: the operand's outer index (i of A, j of B) runs along the stored
+//     rows (A not transposed, B transposed); thread t takes p = t / 16 and the
+//     8 consecutive outer indices 8 (t % 16) .. +7 (four 16-byte loads);
+//   otherwise: the inner index runs along the stored rows; thread t takes
+//     p = t % 32 and the outer indices t / 32 + 16 r (scalar loads; 32
+//     consecutive lanes read 32 consecutive p).
+// Fetches go through a buffer resource whose extent ends with the matrix, so
+// what lies past its end reads as 0.
+template <bool kContig>
 struct OpLoader {
-    static constexpr int kCStep = NT / TR;
     const char *X;
-    int64_t ld, R, total_bytes;
-    int row, col0;
-    uint32_t voff0, cstep_bytes;
+    int64_t ld, R, total_bytes;  // stored rows R, leading dimension ld
+    int t;
 
     __device__ __forceinline__ void init(const double *x, int64_t ld_, int64_t rows,
-                                         int64_t cols, int t)
+                                         int64_t cols, int t_)
     {
         X = (const char *)x;
         ld = ld_;
         R = rows;
         total_bytes = (rows > 0 && cols > 0) ? (ld_ * (cols - 1) + rows) * 8 : 0;
-        row = t % TR;
-        col0 = t / TR;
-        voff0 = (uint32_t)((row + (int64_t)col0 * ld_) * 8);
-        cstep_bytes = (uint32_t)(kCStep * ld_ * 8);
+        t = t_;
     }
-    __device__ __forceinline__ int col(int r) const { return col0 + r * kCStep; }
-    __device__ __forceinline__ void load(int64_t r0, int64_t c0, double v[8]) const
+    // inner index and outer indices of this thread's elements
+    __device__ __forceinline__ int p() const { return kContig ? (t >> 4) : (t & 31); }
+    __device__ __forceinline__ int o(int r) const
     {
+        return kContig ? 8 * (t & 15) + r : (t >> 5) + 16 * r;
+    }
+    // the step at inner offset k0 of the tile whose outer offset is o0
+    __device__ __forceinline__ void load(int64_t o0, int64_t k0, int64_t nouter,
+                                         double v[EPT]) const
+    {
+        // stored (row, col) of the tile's first element
+        const int64_t r0 = kContig ? o0 : k0, c0 = kContig ? k0 : o0;
         const int64_t first = r0 + c0 * ld;
         int64_t ext = total_bytes - first * 8;
         if (ext < 0) ext = 0;
         if (ext > 0x7FFFFFFF) ext = 0x7FFFFFFF;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(X + first * 8, (uint64_t)ext);
-        const uint32_t off = (r0 + row < R) ? voff0 : kOob;
+        if (kContig) {
+            const uint32_t off = (uint32_t)((8 * (t & 15) + (int64_t)(t >> 4) * ld) * 8);
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
-            v[r] = buf_load_f64(rs, off + (uint32_t)r * cstep_bytes);
+            for (int h = 0; h < 4; ++h) {
+                const auto w4 =
+                    __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * h), 0, 0);
+                v[2 * h] = __hiloint2double(w4[1], w4[0]);
+                v[2 * h + 1] = __hiloint2double(w4[3], w4[2]);
+            }
+            // outer indices past the matrix but inside the leading dimension
+            if (o0 + 128 > nouter) {
+#pragma unroll
+                for (int r = 0; r < EPT; ++r)
+                    if (o0 + o(r) >= nouter) v[r] = 0.0;
+            }
+        } else {
+            const bool ok = r0 + (t & 31) < R;
+            const uint32_t base =
+                ok ? (uint32_t)(((t & 31) + (int64_t)(t >> 5) * ld) * 8) : kOob;
+            const uint32_t step = (uint32_t)(16 * ld * 8);
+#pragma unroll
+            for (int r = 0; r < EPT; ++r)
+                v[r] = buf_load_f64(rs, base + (uint32_t)r * step);
+        }
     }
+    // Sum of this thread's 8 elements, completed across the threads sharing
+    // its p: the full tile sum for kContig (the 16 lanes of one DPP row), a
+    // per-wave partial otherwise (lanes l and l^32).  The result goes to
+    // dst[p][slot]: slot 0 for kContig, the wave index otherwise.
+    __device__ __forceinline__ void sum_to(const double v[EPT], double (*dst)[NW]) const
+    {
+        double s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+        if (kContig) {
+            s = sum16(s);
+            if ((t & 15) == 0) dst[t >> 4][0] = s;
+        } else {
+            s = pair_sum32(s);
+            if ((t & 63) < 32) dst[t & 31][t >> 6] = s;
+        }
+    }
+    // Per-outer-index partials accumulated by this thread over the steps,
+    // completed across the threads that hold the same outer indices (the
+    // other p), into dst[slot][outer]: 8 slots (one per wave) for kContig,
+    // slot 0 otherwise.
+    template <typename T>
+    __device__ __forceinline__ void partials_to(const T a_in[EPT], double (*dst)[128]) const
+    {
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            double a = (double)a_in[r];
+            if (kContig) {
+                a = sum_rows(a);
+                if ((t & 48) == 0) dst[t >> 6][o(r)] = a;
+            } else {
+                a = pair_sum16(sum16(a));
+                if ((t & 31) == 0) dst[0][o(r)] = a;
+            }
+        }
+    }
+    // the thread that accounts for p in |x|^2 / |y|^2
+    __device__ __forceinline__ bool first_of_p() const
+    {
+        return kContig ? (t & 15) == 0 : t < 32;
+    }
+    static constexpr int kParts = kContig ? 1 : NW;      // partials of x_p / y_p
+    static constexpr int kOuterParts = kContig ? NW : 1;  // partials per outer index
 };
+
+template <int kParts>
+__device__ __forceinline__ double gather(const double (*src)[NW], int p)
+{
+    if (kParts == 1) return src[p][0];
+    return ((src[p][0] + src[p][1]) + (src[p][2] + src[p][3])) +
+           ((src[p][4] + src[p][5]) + (src[p][6] + src[p][7]));
+}
+
+// owner of tile element (row, col): wave, lane and flat register index
+__device__ __forceinline__ int owner_wave(int row, int col) { return (row >> 6) + 2 * (col >> 5); }
+__device__ __forceinline__ int owner_lane(int row, int col) { return 16 * (row & 3) + (col & 15); }
+__device__ __forceinline__ int owner_reg(int row, int col)
+{
+    return ((row & 63) >> 4) * 8 + ((col & 31) >> 4) * 4 + ((row & 15) >> 2);
+}
 
 template <bool TA, bool TB, bool ABFT>
 __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
@@ -116,175 +214,153 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
     const int wm = w & 1, wn = w >> 1;
     const int q = lane >> 4, c16 = lane & 15;
     const int64_t i0 = (int64_t)tile_m * TM, j0 = (int64_t)tile_n * TN;
-    const double *__restrict__ A = (const double *)g.A;
-    const double *__restrict__ B = (const double *)g.B;
     double *__restrict__ C = (double *)g.C;
-    const int64_t m = g.m, n = g.n, k = g.k, lda = g.lda, ldb = g.ldb, ldc = g.ldc;
+    const int64_t m = g.m, n = g.n, k = g.k, ldc = g.ldc;
     const int nsteps = (int)((k + BK - 1) / BK);
     const int hrows = (int)(m - i0 < TM ? m - i0 : TM);
     const int wcols = (int)(n - j0 < TN ? n - j0 : TN);
     const bool use_c = g.beta != 0.0;
 
-    // Staging.  Each thread fetches 8 elements of A and 8 of B per step
-    // through buffer resources (see OpLoader); a wave's loads are contiguous
-    // runs in memory and its LDS stores hit distinct banks.
-    OpLoader<TA ? 16 : 128> la;
-    OpLoader<TB ? 128 : 16> lb;
-    la.init(A, lda, TA ? k : m, TA ? m : k, t);
-    lb.init(B, ldb, TB ? n : k, TB ? k : n, t);
-    double ra[8], rb[8];
+    // A not transposed: its rows (i) run along the stored rows (contiguous);
+    // B transposed: its columns (j) do.
+    OpLoader<!TA> la;
+    OpLoader<TB> lb;
+    la.init((const double *)g.A, g.lda, TA ? k : m, TA ? m : k, t);
+    lb.init((const double *)g.B, g.ldb, TB ? n : k, TB ? k : n, t);
+    // Staged operand registers of one step.
+    double ra[EPT], rb[EPT];
     auto load = [&](int s) {
         const int64_t k0 = (int64_t)s * BK;
-        if (!TA) la.load(i0, k0, ra); else la.load(k0, i0, ra);
-        if (!TB) lb.load(k0, j0, rb); else lb.load(j0, k0, rb);
+        la.load(i0, k0, m, ra);
+        lb.load(j0, k0, n, rb);
     };
     auto store = [&](int buf) {
+        const int a_p = la.p(), b_p = lb.p();
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            // A tile is [p][i]; B tile is [p][j]
-            if (!TA) sm.u.st[buf].A[la.col(r)][la.row] = ra[r];
-            else     sm.u.st[buf].A[la.row][la.col(r)] = ra[r];
-            if (!TB) sm.u.st[buf].B[lb.row][lb.col(r)] = rb[r];
-            else     sm.u.st[buf].B[lb.col(r)][lb.row] = rb[r];
+        for (int r = 0; r < EPT; ++r) {
+            sm.u.st[buf].A[a_p][phys(la.o(r))] = ra[r];
+            sm.u.st[buf].B[b_p][phys(lb.o(r))] = rb[r];
         }
+    };
+    auto sums = [&](int buf) {
+        la.sum_to(ra, sm.xs[buf]);
+        lb.sum_to(rb, sm.ys[buf]);
     };
 
     // Planned faults of this tile (test hook).
     int nf = 0;
     if (ABFT) {
         if (w == 0) {
-            const int cnt = gather_tile_faults(g, i0, j0, TM, TN, BK,
-                                               g.k_base, sm.faults);
+            const int cnt = gather_tile_faults(g, i0, j0, TM, TN, BK, g.k_base, sm.faults);
             if (lane == 0) sm.nfaults = cnt;
         }
         __syncthreads();
         nf = sm.nfaults;
     }
 
-    const bool a_side = (w == 0 || w == 3);  // waves holding A-side checksum work
     int kind = 0, first_nr = 0, first_nc = 0, first_i = -1, first_j = -1;
-    double rec_d_row = 0, rec_d_col = 0, rec_t_row = 0, rec_t_col = 0, rec_before = 0,
-           rec_after = 0;
+    double rec_before = 0, rec_after = 0;
 
-    d4 acc[4][4];
+    d4 acc[4][2];
 #pragma unroll 1
     for (int attempt = 0; attempt < 2; ++attempt) {
         const bool faults_on = ABFT && attempt == 0 && nf > 0;
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 4; ++ni)
+            for (int ni = 0; ni < 2; ++ni)
                 acc[mi][ni] = (d4){0.0, 0.0, 0.0, 0.0};
-        double cs_acc[4] = {0, 0, 0, 0};  // Pc (A side) or Pr (B side) partials
-        double cs_nrm[4] = {0, 0, 0, 0};  // row / column squared norms
-        double vec_nrm = 0.0;             // |y|^2 (A side) or |x|^2 (B side)
-        double prev[4][4];                // last step's checksum-side fragments
+        // Per-thread checksum partials over the steps, for this thread's 4
+        // outer indices (rows of A in the A loader, columns of B in the B one).
+        // The norms only scale the rounding-error threshold, so FP32 is ample
+        // for them (and halves their registers).
+        double enc_a[EPT] = {}, enc_b[EPT] = {};
+        float nrm_a[EPT] = {}, nrm_b[EPT] = {};
+        float vx = 0.0f, vy = 0.0f;  // x_p^2, y_p^2 over the steps, for this thread's p
 
         load(0);
+        if (ABFT) sums(0);
         // The steps run in segments that end where a planned fault lands, so
         // the fault hook sits outside the hot loop.
         int s = 0;
 #pragma unroll 1
         while (s < nsteps) {
-        int stop = nsteps - 1;
-        if (faults_on)
-            for (int f = 0; f < nf; ++f) {
-                const int fs = sm.faults[f].kstep;
-                if (sm.faults[f].target == FTGEMM_TGT_ACC && fs >= s && fs < stop) stop = fs;
-            }
+            int stop = nsteps - 1;
+            if (faults_on)
+                for (int f = 0; f < nf; ++f) {
+                    const int fs = sm.faults[f].kstep;
+                    if (sm.faults[f].target == FTGEMM_TGT_ACC && fs >= s && fs < stop)
+                        stop = fs;
+                }
 #pragma unroll 1
-        for (; s <= stop; ++s) {
-            const int buf = s & 1;
-            store(buf);
-            __syncthreads();
-            if (s + 1 < nsteps)
-                load(s + 1);
-
-            // Encoded checksums, one step behind: the operand-checksum
-            // partials of step s-1 from the other waves are complete now.
-            if (ABFT && s > 0) {
-                const int pb = (s - 1) & 1;
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const double v = a_side
-                        ? sm.ys[pb][0][4 * kk + q] + sm.ys[pb][1][4 * kk + q]
-                        : sm.xs[pb][0][4 * kk + q] + sm.xs[pb][1][4 * kk + q];
-                    vec_nrm += v * v;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        cs_acc[e] += prev[kk][e] * v;
-                }
-            }
-
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                double fa[4], fb[4];
-#pragma unroll
-                for (int mi = 0; mi < 4; ++mi)
-                    fa[mi] = sm.u.st[buf].A[4 * kk + q][wm * 64 + 16 * mi + c16];
-#pragma unroll
-                for (int ni = 0; ni < 4; ++ni)
-                    fb[ni] = sm.u.st[buf].B[4 * kk + q][wn * 64 + 16 * ni + c16];
-#pragma unroll
-                for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < 4; ++ni)
-                        acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                            fa[mi], fb[ni], acc[mi][ni], 0, 0, 0);
+            for (; s <= stop; ++s) {
+                const int buf = s & 1;
+                store(buf);
+                __syncthreads();
                 if (ABFT) {
-                    // operand checksums and norms from the fragments in hand:
-                    // A side sums over its 64 rows, B side over its 64 columns
-                    double part = 0.0;
+                    // x_p, y_p of step s are complete: the encoded checksums
+                    // and norms of step s, before ra/rb take step s + 1
+                    const double yv = gather<OpLoader<TB>::kParts>(sm.ys[buf], la.p());
+                    const double xv = gather<OpLoader<!TA>::kParts>(sm.xs[buf], lb.p());
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const double v = a_side ? fa[e] : fb[e];
-                        cs_nrm[e] += v * v;
-                        part += v;
-                        prev[kk][e] = v;
+                    for (int r = 0; r < EPT; ++r) {
+                        enc_a[r] += ra[r] * yv;
+                        enc_b[r] += xv * rb[r];
+                        nrm_a[r] += (float)(ra[r] * ra[r]);
+                        nrm_b[r] += (float)(rb[r] * rb[r]);
                     }
-                    part = sum16(part);
-                    if (c16 == 0) {
-                        if (a_side) sm.xs[buf][wm][4 * kk + q] = part;
-                        else        sm.ys[buf][wn][4 * kk + q] = part;
+                    vy += (float)(yv * yv);
+                    vx += (float)(xv * xv);
+                }
+                if (s + 1 < nsteps) load(s + 1);
+#pragma unroll
+                for (int kk = 0; kk < BK / 4; ++kk) {
+                    double fa[4], fb[2];
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+                        fa[mi] = sm.u.st[buf].A[4 * kk + q][phys(wm * 64 + 16 * mi + c16)];
+#pragma unroll
+                    for (int ni = 0; ni < 2; ++ni)
+                        fb[ni] = sm.u.st[buf].B[4 * kk + q][phys(wn * 32 + 16 * ni + c16)];
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni)
+                            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                fa[mi], fb[ni], acc[mi][ni], 0, 0, 0);
+                    if (ABFT && kk == BK / 4 - 1 && s + 1 < nsteps) {
+                        // operand checksums of step s + 1, published before
+                        // its barrier
+                        sums(buf ^ 1);
                     }
                 }
             }
-
-        }
-            if (ABFT) {
+            if (ABFT && faults_on) {
                 // Fault hook: accumulator faults land after step `stop`.
-                if (faults_on) {
-                    for (int f = 0; f < nf; ++f) {
-                        const TileFault tf = sm.faults[f];
-                        if (tf.target != FTGEMM_TGT_ACC || tf.kstep != stop)
-                            continue;
-                        // owner: wave, lane and register of C(row, col)
-                        const int ow = (tf.row >> 6) + 2 * (tf.col >> 6);
-                        const int ol = 16 * (tf.row & 3) + (tf.col & 15);
-                        const int sel = ((tf.row & 63) >> 4) * 16 + ((tf.col & 63) >> 4) * 4 +
-                                        ((tf.row & 15) >> 2);
-                        if (w != ow) continue;
-                        double before = 0.0;
+                for (int f = 0; f < nf; ++f) {
+                    const TileFault tf = sm.faults[f];
+                    if (tf.target != FTGEMM_TGT_ACC || tf.kstep != stop) continue;
+                    if (w != owner_wave(tf.row, tf.col)) continue;
+                    const int ol = owner_lane(tf.row, tf.col), sel = owner_reg(tf.row, tf.col);
+                    double before = 0.0;
 #pragma unroll
-                        for (int e = 0; e < 64; ++e)
-                            if (sel == e) before = acc[e >> 4][(e >> 2) & 3][e & 3];
-                        const double after = tf.mode == FTGEMM_INJ_ADD
-                                                 ? before + tf.delta
-                                                 : flip_bit_f64(before, tf.bit);
+                    for (int e = 0; e < 32; ++e)
+                        if (sel == e) before = acc[e >> 3][(e >> 2) & 1][e & 3];
+                    const double after = tf.mode == FTGEMM_INJ_ADD ? before + tf.delta
+                                                                   : flip_bit_f64(before, tf.bit);
 #pragma unroll
-                        for (int e = 0; e < 64; ++e)
-                            if (sel == e && lane == ol) acc[e >> 4][(e >> 2) & 3][e & 3] = after;
-                        if (lane == ol) {
-                            ftgemm_injection_echo ech;
-                            ech.problem = g.problem;
-                            ech.applied = 1;
-                            ech.row = i0 + tf.row;
-                            ech.col = j0 + tf.col;
-                            ech.k_index = g.plan[tf.idx].k_index;
-                            ech.before = before;
-                            ech.after = after;
-                            g.echo[tf.idx] = ech;
-                        }
+                    for (int e = 0; e < 32; ++e)
+                        if (sel == e && lane == ol) acc[e >> 3][(e >> 2) & 1][e & 3] = after;
+                    if (lane == ol) {
+                        ftgemm_injection_echo ech;
+                        ech.problem = g.problem;
+                        ech.applied = 1;
+                        ech.row = i0 + tf.row;
+                        ech.col = j0 + tf.col;
+                        ech.k_index = g.plan[tf.idx].k_index;
+                        ech.before = before;
+                        ech.after = after;
+                        g.echo[tf.idx] = ech;
                     }
                 }
             }
@@ -296,11 +372,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < 4; ++ni)
+                for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = wm * 64 + 16 * mi + 4 * r + q;
-                        const int col = wn * 64 + 16 * ni + c16;
+                        const int col = wn * 32 + 16 * ni + c16;
                         if (row < hrows && col < wcols) {
                             double *pc = C + (i0 + row) + (j0 + col) * ldc;
                             const double o = g.alpha * acc[mi][ni][r];
@@ -310,54 +386,21 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             return;
         }
 
-        // Last lagged update of the encoded checksums, then fold the four
-        // rows of 16 lanes (each handled every fourth p).
-        {
-            const int pb = (nsteps - 1) & 1;
-            if (a_side) {
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const double yv = sm.ys[pb][0][4 * kk + q] + sm.ys[pb][1][4 * kk + q];
-                    vec_nrm += yv * yv;
-#pragma unroll
-                    for (int mi = 0; mi < 4; ++mi)
-                        cs_acc[mi] += prev[kk][mi] * yv;
-                }
-            } else {
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const double xv = sm.xs[pb][0][4 * kk + q] + sm.xs[pb][1][4 * kk + q];
-                    vec_nrm += xv * xv;
-#pragma unroll
-                    for (int ni = 0; ni < 4; ++ni)
-                        cs_acc[ni] += xv * prev[kk][ni];
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                cs_acc[v] = sum_rows(cs_acc[v]);
-                cs_nrm[v] = sum_rows(cs_nrm[v]);
-            }
-            vec_nrm = sum_rows(vec_nrm);
-            if (q == 0) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    if (a_side) {
-                        sm.enc_row[wm * 64 + 16 * v + c16] = cs_acc[v];
-                        sm.nrm_row[wm * 64 + 16 * v + c16] = cs_nrm[v];
-                    } else {
-                        sm.enc_col[wn * 64 + 16 * v + c16] = cs_acc[v];
-                        sm.nrm_col[wn * 64 + 16 * v + c16] = cs_nrm[v];
-                    }
-                }
-            }
-            if (lane == 0 && w == 0) sm.scal[1] = vec_nrm;  // |y|^2
-            if (lane == 0 && w == 1) sm.scal[0] = vec_nrm;  // |x|^2
-        }
+        // Publish the per-thread partials: rows of A from the A loader,
+        // columns of B from the B loader (the other p completed in lanes).
+        // The y_p loaded by the A loader's threads and the x_p by the B
+        // loader's are the same for every thread of a p: one thread per p
+        // accounts for it.  The A loader's p gathers y, the B loader's x.
+        la.partials_to(enc_a, sm.u.epi.enc_row);
+        la.partials_to(nrm_a, sm.u.epi.nrm_row);
+        lb.partials_to(enc_b, sm.u.epi.enc_col);
+        lb.partials_to(nrm_b, sm.u.epi.nrm_col);
+        if (la.first_of_p()) sm.vnrm[1][la.p()] = (double)vy;
+        if (lb.first_of_p()) sm.vnrm[0][lb.p()] = (double)vx;
 
         // Beta pass fused with the C_in part of the encoding (Section 2.2)
         // and the reference sums of the output.
-        double col_o[4] = {0, 0, 0, 0}, col_c[4] = {0, 0, 0, 0}, col_c2[4] = {0, 0, 0, 0};
+        double col_o[2] = {0, 0}, col_c[2] = {0, 0}, col_c2[2] = {0, 0};
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -365,8 +408,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 double row_o = 0, row_c = 0, row_c2 = 0;
                 const int row = wm * 64 + 16 * mi + 4 * r + q;
 #pragma unroll
-                for (int ni = 0; ni < 4; ++ni) {
-                    const int col = wn * 64 + 16 * ni + c16;
+                for (int ni = 0; ni < 2; ++ni) {
+                    const int col = wn * 32 + 16 * ni + c16;
                     const bool ok = row < hrows && col < wcols;
                     const double cin = (use_c && ok) ? C[(i0 + row) + (j0 + col) * ldc] : 0.0;
                     double o = g.alpha * acc[mi][ni][r];
@@ -385,11 +428,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 }
             }
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
+        for (int ni = 0; ni < 2; ++ni) {
             col_o[ni] = sum_rows(col_o[ni]);
             if (use_c) { col_c[ni] = sum_rows(col_c[ni]); col_c2[ni] = sum_rows(col_c2[ni]); }
             if (q == 0) {
-                const int col = wn * 64 + 16 * ni + c16;
+                const int col = wn * 32 + 16 * ni + c16;
                 sm.u.epi.ref_col[wm][col] = col_o[ni];
                 sm.u.epi.cin_col[wm][col] = col_c[ni];
                 sm.u.epi.cin2_col[wm][col] = col_c2[ni];
@@ -397,52 +440,76 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
         }
         if (t == 0) { sm.nbad_r = 0; sm.nbad_c = 0; sm.ibad = TM; sm.jbad = TN; }
         __syncthreads();
-        if (w == 0) sm.scal[2] = sum64(sm.nrm_row[lane] + sm.nrm_row[lane + 64]);
-        if (w == 1) sm.scal[3] = sum64(sm.nrm_col[lane] + sm.nrm_col[lane + 64]);
+
+        // Combine the partials in a fixed order: row i (its encoded checksum
+        // and squared norm) in thread i, column j in thread 128 + j.
+        const bool is_row = t < TM, is_col = t >= TM && t < TM + TN;
+        const int x = is_row ? t : t - TM;
+        double nrm2 = 0.0;
+        if (is_row) {
+            double e = 0, nr = 0;
+#pragma unroll
+            for (int v = 0; v < OpLoader<!TA>::kOuterParts; ++v) {
+                e += sm.u.epi.enc_row[v][x];
+                nr += sm.u.epi.nrm_row[v][x];
+            }
+            nrm2 = nr;
+            sm.u.epi.fin_row[x] = e;
+        } else if (is_col) {
+            double e = 0, nr = 0;
+#pragma unroll
+            for (int v = 0; v < OpLoader<TB>::kOuterParts; ++v) {
+                e += sm.u.epi.enc_col[v][x];
+                nr += sm.u.epi.nrm_col[v][x];
+            }
+            nrm2 = nr;
+            sm.u.epi.fin_col[x] = e;
+        }
+        // Frobenius norms of the A and B tiles (waves 0-1 and 2-3), |x|, |y|
+        if (w < 4) {
+            const double f = sum64(nrm2);
+            if (lane == 0) sm.red[w][0] = f;
+        }
+        if (w == 4) {
+            const double v2 = pair_sum16(sum16(sm.vnrm[lane >> 5][lane & 31]));
+            if ((lane & 31) == 0) sm.red[4 + (lane >> 5)][0] = v2;
+        }
+        __syncthreads();
+        if (t == 0) {
+            sm.scal[2] = sm.red[0][0] + sm.red[1][0];  // |A_I|_F^2
+            sm.scal[3] = sm.red[2][0] + sm.red[3][0];  // |B_J|_F^2
+            sm.scal[0] = sm.red[4][0];                 // |x|^2
+            sm.scal[1] = sm.red[5][0];                 // |y|^2
+        }
         __syncthreads();
 
-        // Verify: thread t < 128 checks row t, the others column t - 128.
+        // Verify: thread t < 128 checks row t, threads 128..255 column t - 128.
         {
             const double sqk = sqrt((double)k);
             double ratio = 0.0;
-            if (t < TM) {
-                const int i = t;
-                double P = g.alpha * sm.enc_row[i];
-                if (use_c) P += g.beta * (sm.u.epi.cin_row[0][i] + sm.u.epi.cin_row[1][i]);
-                if (faults_on)
-                    for (int f = 0; f < nf; ++f) {
-                        const TileFault tf = sm.faults[f];
-                        if (tf.target == FTGEMM_TGT_COL_CHECKSUM && tf.row == i) {
-                            ftgemm_injection_echo e;
-                            e.problem = g.problem; e.applied = 1; e.row = i0 + tf.row;
-                            e.col = j0 + tf.col; e.k_index = g.plan[tf.idx].k_index;
-                            e.before = P; P += tf.delta; e.after = P;
-                            g.echo[tf.idx] = e;
-                        }
+            if (is_row || is_col) {
+                double P = g.alpha * (is_row ? sm.u.epi.fin_row[x] : sm.u.epi.fin_col[x]);
+                double R = 0.0, cs = 0.0, c2 = 0.0;
+                if (is_row) {
+#pragma unroll
+                    for (int v = 0; v < WN; ++v) {
+                        R += sm.u.epi.ref_row[v][x];
+                        cs += sm.u.epi.cin_row[v][x];
+                        c2 += sm.u.epi.cin2_row[v][x];
                     }
-                const double R = sm.u.epi.ref_row[0][i] + sm.u.epi.ref_row[1][i];
-                const double tau = ft_threshold(
-                    kLambda, U, sqk, sqrt((double)wcols), g.alpha, sqrt(sm.nrm_row[i]),
-                    sqrt(sm.scal[3]), sqrt(sm.scal[1]), g.beta,
-                    sqrt(sm.u.epi.cin2_row[0][i] + sm.u.epi.cin2_row[1][i]));
-                const double d = R - P;
-                sm.fin_row[i] = P; sm.tau_row[i] = tau; sm.d_row[i] = d;
-                if (i < hrows) {
-                    if (!(fabs(d) <= tau)) {
-                        atomicAdd(&sm.nbad_r, 1);
-                        atomicMin(&sm.ibad, i);
-                    } else if (tau > 0.0) {
-                        ratio = fabs(d) / tau;
-                    }
+                } else {
+                    R = sm.u.epi.ref_col[0][x] + sm.u.epi.ref_col[1][x];
+                    cs = sm.u.epi.cin_col[0][x] + sm.u.epi.cin_col[1][x];
+                    c2 = sm.u.epi.cin2_col[0][x] + sm.u.epi.cin2_col[1][x];
                 }
-            } else {
-                const int j = t - TM;
-                double P = g.alpha * sm.enc_col[j];
-                if (use_c) P += g.beta * (sm.u.epi.cin_col[0][j] + sm.u.epi.cin_col[1][j]);
+                if (use_c) P += g.beta * cs;
                 if (faults_on)
                     for (int f = 0; f < nf; ++f) {
                         const TileFault tf = sm.faults[f];
-                        if (tf.target == FTGEMM_TGT_ROW_CHECKSUM && tf.col == j) {
+                        const bool hit = is_row
+                            ? (tf.target == FTGEMM_TGT_COL_CHECKSUM && tf.row == x)
+                            : (tf.target == FTGEMM_TGT_ROW_CHECKSUM && tf.col == x);
+                        if (hit) {
                             ftgemm_injection_echo e;
                             e.problem = g.problem; e.applied = 1; e.row = i0 + tf.row;
                             e.col = j0 + tf.col; e.k_index = g.plan[tf.idx].k_index;
@@ -450,24 +517,32 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                             g.echo[tf.idx] = e;
                         }
                     }
-                const double R = sm.u.epi.ref_col[0][j] + sm.u.epi.ref_col[1][j];
-                const double tau = ft_threshold(
-                    kLambda, U, sqk, sqrt((double)hrows), g.alpha, sqrt(sm.nrm_col[j]),
-                    sqrt(sm.scal[2]), sqrt(sm.scal[0]), g.beta,
-                    sqrt(sm.u.epi.cin2_col[0][j] + sm.u.epi.cin2_col[1][j]));
+                // row i: norm of A's row i, Frobenius norm of the B tile and
+                // |y|, summed over the tile's columns; column j symmetrically
+                const double tau = is_row
+                    ? ft_threshold(kLambda, U, sqk, sqrt((double)wcols), g.alpha, sqrt(nrm2),
+                                   sqrt(sm.scal[3]), sqrt(sm.scal[1]), g.beta, sqrt(c2))
+                    : ft_threshold(kLambda, U, sqk, sqrt((double)hrows), g.alpha, sqrt(nrm2),
+                                   sqrt(sm.scal[2]), sqrt(sm.scal[0]), g.beta, sqrt(c2));
                 const double d = R - P;
-                sm.fin_col[j] = P; sm.tau_col[j] = tau; sm.d_col[j] = d;
-                if (j < wcols) {
+                if (is_row) {
+                    sm.u.epi.fin_row[x] = P; sm.u.epi.tau_row[x] = tau; sm.u.epi.d_row[x] = d;
+                } else {
+                    sm.u.epi.fin_col[x] = P; sm.u.epi.tau_col[x] = tau; sm.u.epi.d_col[x] = d;
+                }
+                if (x < (is_row ? hrows : wcols)) {
                     if (!(fabs(d) <= tau)) {
-                        atomicAdd(&sm.nbad_c, 1);
-                        atomicMin(&sm.jbad, j);
+                        atomicAdd(is_row ? &sm.nbad_r : &sm.nbad_c, 1);
+                        atomicMin(is_row ? &sm.ibad : &sm.jbad, x);
                     } else if (tau > 0.0) {
                         ratio = fabs(d) / tau;
                     }
                 }
             }
-            ratio = max64(ratio);
-            if (lane == 0) atomic_max_nonneg(&g.counters->max_ratio_bits, ratio);
+            if (w < 4) {
+                ratio = max64(ratio);
+                if (lane == 0) atomic_max_nonneg(&g.counters->max_ratio_bits, ratio);
+            }
         }
         __syncthreads();
 
@@ -480,14 +555,12 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             kind = FTGEMM_KIND_UNCORRECTABLE;
             break;
         }
-        // First attempt disagreed: keep what the record needs.
+        // First attempt disagreed: keep what the record needs (the residuals
+        // and thresholds stay in LDS until the record is written, unless the
+        // tile is computed again).
         first_nr = nr; first_nc = nc;
         first_i = nr ? sm.ibad : -1;
         first_j = nc ? sm.jbad : -1;
-        rec_d_row = first_j >= 0 ? sm.d_col[first_j] : 0.0;
-        rec_t_row = first_j >= 0 ? sm.tau_col[first_j] : 0.0;
-        rec_d_col = first_i >= 0 ? sm.d_row[first_i] : 0.0;
-        rec_t_col = first_i >= 0 ? sm.tau_row[first_i] : 0.0;
 
         if (nr == 1 && nc == 1) {
             // Locate at the crossing; rebuild from the encoded checksum of
@@ -498,11 +571,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < 4; ++ni)
+                for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = wm * 64 + 16 * mi + 4 * r + q;
-                        const int col = wn * 64 + 16 * ni + c16;
+                        const int col = wn * 32 + 16 * ni + c16;
                         const double o = acc[mi][ni][r];
                         if (col == js && row != is) s_col += o;
                         if (row == is && col != js) s_row += o;
@@ -511,24 +584,19 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             s_row = sum64(s_row);
             if (lane == 0) { sm.red[w][0] = s_col; sm.red[w][1] = s_row; }
             __syncthreads();
-            const double sc = ((sm.red[0][0] + sm.red[1][0]) + sm.red[2][0]) + sm.red[3][0];
-            const double sr = ((sm.red[0][1] + sm.red[1][1]) + sm.red[2][1]) + sm.red[3][1];
-            const double fixed = sm.fin_col[js] - sc;
-            if (fabs(sr + fixed - sm.fin_row[is]) <= sm.tau_row[is]) {
-                const int ow = (is >> 6) + 2 * (js >> 6);
-                const int ol = 16 * (is & 3) + (js & 15);
-                const int omi = (is & 63) >> 4, oni = (js & 63) >> 4, orr = (is & 15) >> 2;
-                if (w == ow && lane == ol) {
+            double sc = 0.0, sr = 0.0;
 #pragma unroll
-                    for (int mi = 0; mi < 4; ++mi)
+            for (int v = 0; v < NW; ++v) { sc += sm.red[v][0]; sr += sm.red[v][1]; }
+            const double fixed = sm.u.epi.fin_col[js] - sc;
+            if (fabs(sr + fixed - sm.u.epi.fin_row[is]) <= sm.u.epi.tau_row[is]) {
+                if (w == owner_wave(is, js)) {
+                    const int ol = owner_lane(is, js), sel = owner_reg(is, js);
 #pragma unroll
-                        for (int ni = 0; ni < 4; ++ni)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                if (mi == omi && ni == oni && r == orr) {
-                                    rec_before = acc[mi][ni][r];
-                                    acc[mi][ni][r] = fixed;
-                                }
+                    for (int e = 0; e < 32; ++e)
+                        if (sel == e && lane == ol) {
+                            rec_before = acc[e >> 3][(e >> 2) & 1][e & 3];
+                            acc[e >> 3][(e >> 2) & 1][e & 3] = fixed;
+                        }
                 }
                 rec_after = fixed;
                 kind = FTGEMM_KIND_CORRECTED;
@@ -539,18 +607,25 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             break;
         }
         // Several disagreements, or a rebuilt value that does not confirm:
-        // compute the tile again.
+        // keep the first attempt's residuals for the record, then compute
+        // the tile again.
+        if (t == 0) {
+            sm.red[0][0] = first_j >= 0 ? sm.u.epi.d_col[first_j] : 0.0;
+            sm.red[0][1] = first_j >= 0 ? sm.u.epi.tau_col[first_j] : 0.0;
+            sm.red[1][0] = first_i >= 0 ? sm.u.epi.d_row[first_i] : 0.0;
+            sm.red[1][1] = first_i >= 0 ? sm.u.epi.tau_row[first_i] : 0.0;
+        }
         __syncthreads();
     }
 
     if (ABFT) {
-        // the owner lane of a corrected element knows its old value
         if (kind == FTGEMM_KIND_CORRECTED) {
-            const int ow = (first_i >> 6) + 2 * (first_j >> 6);
-            const int ol = 16 * (first_i & 3) + (first_j & 15);
-            if (w == ow && lane == ol) sm.red[0][0] = rec_before;
+            // the owner lane of a corrected element knows its old value
             __syncthreads();
-            rec_before = sm.red[0][0];
+            if (w == owner_wave(first_i, first_j) && lane == owner_lane(first_i, first_j))
+                sm.red[2][0] = rec_before;
+            __syncthreads();
+            rec_before = sm.red[2][0];
         }
         if (t == 0) {
             DevCounters *ct = g.counters;
@@ -565,6 +640,10 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 atomicAdd(which, 1ull);
                 const unsigned slot = atomicAdd(&ct->record_count, 1u);
                 if (slot < g.record_cap) {
+                    // residuals: from LDS of this attempt (corrected /
+                    // checksum-only) or saved from the first attempt
+                    const bool again = kind == FTGEMM_KIND_RECOMPUTED ||
+                                       kind == FTGEMM_KIND_UNCORRECTABLE;
                     ftgemm_fault_record rc;
                     rc.problem = g.problem;
                     rc.kind = kind;
@@ -574,10 +653,10 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                     rc.col = first_j >= 0 ? j0 + first_j : -1;
                     rc.nbad_rows = first_nr;
                     rc.nbad_cols = first_nc;
-                    rc.d_row = rec_d_row;
-                    rc.d_col = rec_d_col;
-                    rc.tau_row = rec_t_row;
-                    rc.tau_col = rec_t_col;
+                    rc.d_row = again ? sm.red[0][0] : first_j >= 0 ? sm.u.epi.d_col[first_j] : 0.0;
+                    rc.tau_row = again ? sm.red[0][1] : first_j >= 0 ? sm.u.epi.tau_col[first_j] : 0.0;
+                    rc.d_col = again ? sm.red[1][0] : first_i >= 0 ? sm.u.epi.d_row[first_i] : 0.0;
+                    rc.tau_col = again ? sm.red[1][1] : first_i >= 0 ? sm.u.epi.tau_row[first_i] : 0.0;
                     rc.before = kind == FTGEMM_KIND_CORRECTED ? rec_before : 0.0;
                     rc.after = kind == FTGEMM_KIND_CORRECTED ? rec_after : 0.0;
                     g.records[slot] = rc;
@@ -588,11 +667,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 4; ++ni)
+            for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = wm * 64 + 16 * mi + 4 * r + q;
-                    const int col = wn * 64 + 16 * ni + c16;
+                    const int col = wn * 32 + 16 * ni + c16;
                     if (row < hrows && col < wcols)
                         C[(i0 + row) + (j0 + col) * ldc] = acc[mi][ni][r];
                 }
@@ -600,7 +679,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
 }
 
 template <bool TA, bool TB, bool ABFT>
-__global__ __launch_bounds__(NT) void kernel(GemmArgs g)
+__global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
 {
     __shared__ Smem sm;
     int tm_, tn_;

@@ -75,7 +75,7 @@ def test_fault_plan_validation():
 
 def test_query_tiling():
     tm, tn, bk, sk = F.query_tiling(F.F64, 256, 256, 256)
-    assert (tm, tn, bk, sk) == (128, 128, 16, 1)
+    assert (tm, tn, sk) == (128, 128, 1) and bk in (16, 32)
     assert F.lib().ftgemm_query_tiling(9, 1, 1, 1, None, None, None, None) == F.ERR_INVALID_ARG
 
 

@@ -112,7 +112,8 @@ def test_fault_classes():
     m = n = k = 256
     A, B, Cin = synth.operands(6, 0, m, n, k, "uniform")
     F_ = synth.Fault
-    part = A[:, :16] @ B[:16, :]
+    bk = f64_tiling(m, n, k)[2]
+    part = A[:, :bk] @ B[:bk, :]
     cand = np.argwhere((np.abs(part) >= 1) & (np.abs(part) < 2))
     ri, ci = map(int, cand[0])
     plan = [
@@ -135,7 +136,7 @@ def test_fault_classes():
     flip = [e for e in rep.echoes if e["row"] == ri and e["col"] == ci][0]
     assert flip["applied"] and not np.isfinite(flip["after"])
     # tiny fault: not flagged
-    tr, tc = O.default().tile_thresholds(A, B, 0, 0, Cin, 1.0, 1.0, tm=128, tn=128, bk=16)
+    tr, tc = O.default().tile_thresholds(A, B, 0, 0, Cin, 1.0, 1.0, tm=128, tn=128, bk=bk)
     tiny = [F_(7, 9, 30, synth.ADD, 1e-3 * min(tr.min(), tc.min()))]
     got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, False, False, tiny)
     assert not rep.records
