@@ -191,6 +191,9 @@ typedef struct {
     int32_t acc_bits;          /* 64: FP64 accumulators; 32: FP32           */
     int32_t correct;           /* 0: detect and classify only               */
     double lambda;             /* threshold multiplier                      */
+    double mma_grid;           /* 0, or the truncation grid of a matrix     */
+    int32_t mma_group;         /* instruction's group sums (see threshold)  */
+    int32_t pad;
 } oracle_params;
 
 /* Flip one bit of an accumulator held at the given precision. */
@@ -227,7 +230,21 @@ static double flip_bit(double v, int bit, int acc_bits)
  * tile's operand checksum, and the four terms bound the accumulation of the
  * products, the rounding of the output, the encoding product x^T b_j, and
  * the rounding inside x.  The column checksum entry of row i swaps the roles
- * of A and B. */
+ * of A and B.
+ *
+ * Multiplier units that do not add their products exactly (mma_grid > 0):
+ * products are summed in groups of g = mma_group consecutive inner indices,
+ * each product cut to a multiple of mma_grid * 2^E, 2^E the binade of the
+ * group's largest product.  A product's error is then below mma_grid times
+ * that largest product, so the squared errors of a group are at most g times
+ * the sum of its squared products, and over the h entries of the checksum
+ * (the same random-walk reading)
+ *
+ *   sqrt(sum_i sum_p e_ip^2) <= mma_grid sqrt(g) sqrt(sum_i sum_p a_ip^2 b_pj^2)
+ *                            <= mma_grid sqrt(g) sqrt(h) max|A_I| ||b_j||,
+ *
+ * which adds lambda |alpha| mma_grid sqrt(g) sqrt(h) max|A_I| ||b_j|| to
+ * tau_j (and the mirror image, with max|B_J| and ||a_i||, to tau_i). */
 static double threshold(double lambda, double u, int64_t k, int64_t h,
                         double alpha, double nrm_vec, double frob_tile,
                         double nrm_chk, double beta, double nrm_cin)
@@ -344,6 +361,16 @@ static void tile_encode(const oracle_params *P, const double *A, const double *B
         ny += y[p] * y[p];
     }
     fa = sqrt(fa); fb = sqrt(fb); nx = sqrt(nx); ny = sqrt(ny);
+    double ma = 0.0, mb = 0.0;  /* largest magnitudes of the tile's operands */
+    if (P->mma_grid > 0.0) {
+        for (int64_t p = 0; p < k; ++p) {
+            for (int64_t ii = 0; ii < h; ++ii)
+                ma = fmax(ma, fabs(opA(A, P->lda, P->ta, i0 + ii, p)));
+            for (int64_t jj = 0; jj < w; ++jj)
+                mb = fmax(mb, fabs(opB(B, P->ldb, P->tb, p, j0 + jj)));
+        }
+    }
+    const double trunc = P->mma_grid * sqrt((double)(P->mma_group > 0 ? P->mma_group : 1));
     for (int64_t jj = 0; jj < w; ++jj) {
         double s = 0.0;
         if (beta != 0.0)
@@ -363,9 +390,11 @@ static void tile_encode(const oracle_params *P, const double *A, const double *B
         gr[ii] = sqrt(s);
     }
     for (int64_t jj = 0; jj < w; ++jj)
-        tr[jj] = threshold(P->lambda, u, k, h, alpha, nb[jj], fa, nx, beta, gc[jj]);
+        tr[jj] = threshold(P->lambda, u, k, h, alpha, nb[jj], fa, nx, beta, gc[jj]) +
+                 P->lambda * fabs(alpha) * trunc * sqrt((double)h) * ma * nb[jj];
     for (int64_t ii = 0; ii < h; ++ii)
-        tc[ii] = threshold(P->lambda, u, k, w, alpha, na[ii], fb, ny, beta, gr[ii]);
+        tc[ii] = threshold(P->lambda, u, k, w, alpha, na[ii], fb, ny, beta, gr[ii]) +
+                 P->lambda * fabs(alpha) * trunc * sqrt((double)w) * mb * na[ii];
 
     free(x); free(y); free(nb); free(na); free(gc); free(gr);
 }

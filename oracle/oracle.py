@@ -69,7 +69,8 @@ class _Params(C.Structure):
                 ("k", C.c_int64), ("lda", C.c_int64), ("ldb", C.c_int64), ("ldc", C.c_int64),
                 ("alpha", C.c_double), ("beta", C.c_double), ("tm", C.c_int64),
                 ("tn", C.c_int64), ("bk", C.c_int64), ("acc_bits", C.c_int32),
-                ("correct", C.c_int32), ("lam", C.c_double)]
+                ("correct", C.c_int32), ("lam", C.c_double), ("mma_grid", C.c_double),
+                ("mma_group", C.c_int32), ("pad", C.c_int32)]
 
 
 @dataclass
@@ -186,20 +187,24 @@ class Oracle:
         return out
 
     # -- fault-tolerant GEMM ----------------------------------------------
-    def _params(self, A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, correct, lam):
+    def _params(self, A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, correct, lam,
+                mma=(0.0, 1)):
         m, n, k = _dims(A, B, ta, tb)
         return _Params(int(ta), int(tb), m, n, k, max(1, A.shape[0]), max(1, B.shape[0]),
                        max(1, Cin.shape[0]), alpha, beta, tm, tn, bk, acc_bits,
-                       int(correct), lam)
+                       int(correct), lam, float(mma[0]), int(mma[1]), 0)
 
     def ftgemm(self, A, B, Cin=None, alpha=1.0, beta=0.0, ta=False, tb=False, tm=128,
                tn=128, bk=16, acc_bits=64, injections=(), tiles=None, correct=True,
-               lam=DEFAULT_LAMBDA):
-        """Fault-tolerant GEMM, tile by tile (Sections 2.2 and 2.3)."""
+               lam=DEFAULT_LAMBDA, mma=(0.0, 1)):
+        """Fault-tolerant GEMM, tile by tile (Sections 2.2 and 2.3).  mma:
+        (grid, group) of a multiplier that truncates its in-instruction
+        sums, which widens the thresholds; (0, 1) for exact sums."""
         A, B = _f64(A), _f64(B)
         m, n, k = _dims(A, B, ta, tb)
         Cin = np.zeros((max(m, 1), max(n, 1)), order="F") if Cin is None else _f64(Cin)
-        P = self._params(A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, correct, lam)
+        P = self._params(A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, correct, lam,
+                         mma)
         out = np.full((m, n), np.nan, order="F")
         raw = np.full((m, n), np.nan, order="F")
         inj = list(injections)
@@ -231,12 +236,12 @@ class Oracle:
 
     def tile_thresholds(self, A, B, tile_m, tile_n, Cin=None, alpha=1.0, beta=0.0,
                         ta=False, tb=False, tm=128, tn=128, bk=16, acc_bits=64,
-                        lam=DEFAULT_LAMBDA):
+                        lam=DEFAULT_LAMBDA, mma=(0.0, 1)):
         """(tau_row[w], tau_col[h]) of one tile."""
         A, B = _f64(A), _f64(B)
         m, n, k = _dims(A, B, ta, tb)
         Cin = np.zeros((max(m, 1), max(n, 1)), order="F") if Cin is None else _f64(Cin)
-        P = self._params(A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, True, lam)
+        P = self._params(A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, True, lam, mma)
         h = min(tm, m - tile_m * tm)
         w = min(tn, n - tile_n * tn)
         tr, tc = np.empty(w), np.empty(h)

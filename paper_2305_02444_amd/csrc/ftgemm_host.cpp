@@ -240,14 +240,18 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
         HIP_TRY(ftg::launch_scale(d.C, c_is_f64, d.m, d.n, d.ldc, d.beta, stream));
         return FTGEMM_OK;
     }
-    if (d.dtype != FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
-
     std::lock_guard<std::mutex> lock(g_mu);
+    if (d.dtype != FTGEMM_F64 && d.abft)
+        for (const ftgemm_injection &f : g_plan)  // FP32 accumulators have 32 bits
+            if (f.mode == FTGEMM_INJ_BITFLIP && f.bit >= 32) return invalid(14);
     DeviceWs *ws = nullptr;
     if (ftgemm_status st = workspace(&ws, 1)) return st;
 
     int tm, tn, bk;
-    ftg::tiling_f64(&tm, &tn, &bk);
+    if (d.dtype == FTGEMM_F64)
+        ftg::tiling_f64(&tm, &tn, &bk);
+    else
+        ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, &tm, &tn, &bk);
     GemmArgs g = base_args(d, tm, tn);
     g.counters = ws->counters;
     g.records = ws->records;
@@ -256,8 +260,11 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
     g.plan = ws->plan;
     g.echo = ws->echo;
     if (rep && d.abft) HIP_TRY(ftg::launch_clear_report(ws->counters, 1, ws->echo, ws->nplan, stream));
-    HIP_TRY(ftg::launch_f64(g, d.transA == FTGEMM_OP_T, d.transB == FTGEMM_OP_T, d.abft != 0,
-                            stream));
+    const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
+    if (d.dtype == FTGEMM_F64)
+        HIP_TRY(ftg::launch_f64(g, ta, tb, d.abft != 0, stream));
+    else
+        HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft != 0, stream));
     if (rep && d.abft) {
         HIP_TRY(hipMemcpyAsync(ws->h_counters, ws->counters, sizeof(DevCounters),
                                hipMemcpyDeviceToHost, stream));
@@ -357,8 +364,10 @@ ftgemm_status ftgemm_query_tiling(ftgemm_dtype dtype, int64_t m, int64_t n, int6
     if (k < 0) return invalid(4);
     if (!tm || !tn || !bk || !split_k) return invalid(5);
     int a = 0, b = 0, c = 0;
-    if (dtype != FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
-    ftg::tiling_f64(&a, &b, &c);
+    if (dtype == FTGEMM_F64)
+        ftg::tiling_f64(&a, &b, &c);
+    else
+        ftg::tiling_lp(dtype == FTGEMM_FP8_E4M3, &a, &b, &c);
     *tm = a;
     *tn = b;
     *bk = c;

@@ -11,6 +11,12 @@ namespace ftg {
 hipError_t launch_f64(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream);
 void tiling_f64(int *tm, int *tn, int *bk);
 
+// BF16 / FP8 E4M3 tile kernel (FP32 accumulation and output, one 128 x 128
+// output tile per workgroup).
+hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, bool abft,
+                     hipStream_t stream);
+void tiling_lp(bool fp8, int *tm, int *tn, int *bk);
+
 // C = beta * C over an m x n column-major matrix of double (f64) or float.
 hipError_t launch_scale(void *C, bool f64, int64_t m, int64_t n, int64_t ldc, double beta,
                         hipStream_t stream);

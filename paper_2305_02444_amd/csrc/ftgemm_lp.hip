@@ -1,0 +1,863 @@
+// ftgemm_lp.hip -- low-precision (BF16, FP8 E4M3) fault-tolerant GEMM tile
+// for gfx950: matrix-core products accumulated in FP32, FP32 checksums,
+// verification, location and correction in FP64, FP32 output.
+//
+// One workgroup (8 waves, 2 x 4) owns a 128 x 128 output tile and walks the
+// inner dimension in steps of 128 bytes per row (64 BF16 or 128 FP8 values).
+// Both operand tiles live in LDS with the inner index contiguous, the layout
+// the MFMA operands want: v_mfma_f32_16x16x32_bf16 and
+// v_mfma_f32_16x16x128_f8f6f4 (E4M3, unit block scales) read 8 / 32
+// consecutive inner values per lane.  Operands whose outer index is the
+// contiguous one in memory (A not transposed, B transposed) are transposed
+// in registers while staged (pairs / quads of inner values per dword).
+//
+// Fault tolerance follows the FP64 kernel (FT-GEMM, Section 2.2): the staged
+// operand registers feed the operand checksums x_p = sum_i A(i,p),
+// y_p = sum_j B(p,j) and the norms before the step's barrier, and the
+// encoded checksums Pc_i += A(i,p) y_p, Pr_j += x_p B(p,j) after it, all in
+// FP32; the epilogue encodes C_in in the beta pass, sums the FP32 outputs in
+// FP64, and verifies, locates, rebuilds and confirms in FP64.  The
+// threshold's unit roundoff is FP32's.
+#include "ftgemm_device.h"
+#include "ftgemm_kernels.h"
+
+namespace ftg {
+namespace lp {
+
+constexpr int TM = 128, TN = 128, BKB = 128;  // tile, inner step in bytes per row
+constexpr int WM = 2, WN = 4, NW = WM * WN, NT = 64 * NW;
+constexpr int SROW = BKB + 16;                // LDS row stride in bytes
+constexpr double U = 5.9604644775390625e-08;  // 2^-24, unit roundoff of FP32
+// The FP8 matrix instructions do not add their products exactly: products
+// are summed in groups of 8 consecutive inner indices, each cut (toward
+// zero) to a multiple of 2^-14 times the binade of the group's largest
+// product (measured on gfx950; BF16 products are added as in FP32).  The
+// thresholds of the FP8 path carry the matching term
+// lambda |alpha| 2^-14 sqrt(8) sqrt(h) max|A_I| ||b_j|| (rows: the mirror).
+constexpr double kTruncGrid = 6.103515625e-05;  // 2^-14
+constexpr int kTruncGroup = 8;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+// Result layout of both MFMAs (measured on gfx950): lane l = 16 q + c,
+// register r holds D[4 q + r][c].  Wave w = wm + 2 wn holds rows
+// 64 wm .. +63 and columns 32 wn .. +31 as acc[mi][ni][r] =
+// C(64 wm + 16 mi + 4 q + r, 32 wn + 16 ni + c).
+
+template <bool FP8>
+struct Elem {
+    static constexpr int EB = FP8 ? 1 : 2;       // bytes per element
+    static constexpr int BK = BKB / EB;          // inner values per step
+    static constexpr int KV = 16 / EB;           // values per 16 bytes
+    static constexpr int KPI = FP8 ? 128 : 32;   // inner values per MFMA
+    static constexpr int NKK = BK / KPI;         // MFMAs along the inner step
+};
+
+struct Stage {
+    unsigned char A[TM][SROW];  // A tile, [i][inner bytes]
+    unsigned char B[TN][SROW];  // B tile, [j][inner bytes]
+};
+
+struct Epi {
+    double ref_row[WN][TM], ref_col[WM][TN];
+    double cin_row[WN][TM], cin_col[WM][TN];
+    double cin2_row[WN][TM], cin2_col[WM][TN];
+    double enc_row[NW][TM], enc_col[NW][TN];
+    double nrm_row[NW][TM], nrm_col[NW][TN];
+    double fin_row[TM], fin_col[TN];
+    double tau_row[TM], tau_col[TN];
+    double d_row[TM], d_col[TN];
+};
+
+struct Smem {
+    union {
+        Stage st[2];
+        Epi epi;
+    } u;
+    float xs[2][128][NW];  // [buffer][p][partial]: column sums of the A tile
+    float ys[2][128][NW];  // [buffer][p][partial]: row sums of the B tile
+    double red[NW][2];
+    double wsum[NW][5];    // per wave: |x|^2, |y|^2, row / column norms^2, max|A|, max|B|
+    double scal[6];
+    TileFault faults[kMaxTileFaults];
+    int nfaults;
+    int nbad_r, nbad_c, ibad, jbad;
+};
+
+// E4M3 byte b (a constant after unrolling) of a dword, exactly widened
+__device__ __forceinline__ float fp8_byte(int d, int b)
+{
+    switch (b & 3) {
+    case 0: return __builtin_amdgcn_cvt_f32_fp8(d, 0);
+    case 1: return __builtin_amdgcn_cvt_f32_fp8(d, 1);
+    case 2: return __builtin_amdgcn_cvt_f32_fp8(d, 2);
+    default: return __builtin_amdgcn_cvt_f32_fp8(d, 3);
+    }
+}
+
+// element e of a dword (two BF16 or four E4M3 values), exactly widened
+template <bool FP8>
+__device__ __forceinline__ float elem_dw(int d, int e)
+{
+    if (FP8) return fp8_byte(d, e);
+    return __uint_as_float((e & 1) ? ((unsigned)d & 0xffff0000u) : ((unsigned)d << 16));
+}
+
+// element e (0 .. KV-1) of a 16-byte chunk held in 4 dwords
+template <bool FP8>
+__device__ __forceinline__ float elem(const i4v &w, int e)
+{
+    return FP8 ? elem_dw<true>(w[e >> 2], e & 3) : elem_dw<false>(w[e >> 1], e & 1);
+}
+
+// Staging of one operand for one step; every thread handles 32 bytes.
+//   kInner (the inner index runs along the stored rows: A transposed, B not
+//   transposed): thread t fetches 16 bytes (KV consecutive inner values) at
+//   outer indices o = t / 8 + 64 r (r = 0, 1), inner chunk t % 8, and
+//   stores them unchanged.
+//   otherwise (the outer index runs along the stored rows): thread t fetches
+//   the 8 outer indices 8 (t % 16) .. +7 at the PG (2 for BF16, 4 for FP8)
+//   consecutive inner indices PG (t / 16) .. +PG-1 and regroups them into one
+//   dword per outer index (its inner pair or quad), the LDS layout.
+template <bool FP8, bool kInner>
+struct LpLoader {
+    using E = Elem<FP8>;
+    static constexpr int PG = 4 / E::EB;               // inner values per dword
+    static constexpr int kNP = kInner ? E::KV : PG;    // inner values per thread
+    static constexpr int kParts = kInner ? NW : 1;     // partials of an operand checksum
+    static constexpr int kOuter = kInner ? 2 : 8;      // outer indices per thread
+    static constexpr int kOuterParts = kInner ? 1 : NW;  // partials of a per-outer sum
+    const char *X;
+    int64_t ld, R, total_bytes;  // stored rows R, leading dimension ld (elements)
+    int t;
+    i4v w[2];  // kInner: two raw 16-byte chunks; otherwise: 8 regrouped dwords
+
+    __device__ __forceinline__ void init(const void *x, int64_t ld_, int64_t rows, int64_t cols,
+                                         int t_)
+    {
+        X = (const char *)x;
+        ld = ld_;
+        R = rows;
+        total_bytes = (rows > 0 && cols > 0) ? (ld_ * (cols - 1) + rows) * E::EB : 0;
+        t = t_;
+    }
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int64_t r0, int64_t c0) const
+    {
+        const int64_t first = r0 + c0 * ld;
+        int64_t ext = total_bytes - first * E::EB;
+        if (ext < 0) ext = 0;
+        if (ext > 0x7FFFFFFF) ext = 0x7FFFFFFF;
+        return make_rsrc(X + first * E::EB, (uint64_t)ext);
+    }
+    __device__ __forceinline__ int outer(int r) const
+    {
+        return kInner ? (t >> 3) + 64 * r : 8 * (t & 15) + r;
+    }
+    __device__ __forceinline__ int p0() const { return kInner ? E::KV * (t & 7) : PG * (t >> 4); }
+
+    // one element of the operand, zero outside the resource
+    __device__ __forceinline__ unsigned load_elem(__amdgpu_buffer_rsrc_t rs, uint32_t off) const
+    {
+        if (FP8) return (unsigned)__builtin_amdgcn_raw_buffer_load_b8(rs, (int)off, 0, 0);
+        return (unsigned)__builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0);
+    }
+
+    __device__ __forceinline__ void load(int64_t o0, int64_t k0, int64_t nouter, int64_t k)
+    {
+        if (kInner) {
+            const __amdgpu_buffer_rsrc_t rs = rsrc(k0, o0);
+            const int valid = (int)((k - k0) < E::BK ? (k - k0) : E::BK) - p0();
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const uint32_t off =
+                    valid > 0 ? (uint32_t)((p0() + (int64_t)outer(r) * ld) * E::EB) : kOob;
+                w[r] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+            }
+            if (valid > 0 && valid < E::KV) {
+                // a chunk that crosses the end of the inner dimension: element
+                // by element, so nothing past the matrix is read into it
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const uint32_t base = (uint32_t)((p0() + (int64_t)outer(r) * ld) * E::EB);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        unsigned v = 0;
+#pragma unroll
+                        for (int e = 0; e < PG; ++e) {
+                            const int idx = d * PG + e;
+                            if (idx < valid)
+                                v |= load_elem(rs, base + idx * E::EB) << (8 * E::EB * e);
+                        }
+                        w[r][d] = (int)v;
+                    }
+                }
+            }
+        } else {
+            const __amdgpu_buffer_rsrc_t rs = rsrc(o0, k0);
+            const uint32_t base = (uint32_t)((outer(0) + (int64_t)p0() * ld) * E::EB);
+            const uint32_t col = (uint32_t)(ld * E::EB);
+            // raw columns: PG columns of 8 outer indices (16 or 8 bytes each)
+            int c[4][4];
+            if (!FP8) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const i4v v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(base + b * col), 0, 0);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) c[b][d] = v[d];
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(base + b * col), 0, 0);
+                    c[b][0] = (int)v[0];
+                    c[b][1] = (int)v[1];
+                }
+            }
+            const int live = (int)(nouter - o0) - outer(0);  // outer indices inside
+            if (live < 8) {
+                // the tile's last rows: element by element (a chunk that
+                // crosses the end of the matrix), zero past it
+#pragma unroll
+                for (int b = 0; b < PG; ++b)
+#pragma unroll
+                    for (int d = 0; d < 8 / PG; ++d) {
+                        unsigned v = 0;
+#pragma unroll
+                        for (int e = 0; e < PG; ++e) {
+                            const int idx = d * PG + e;
+                            if (idx < live)
+                                v |= load_elem(rs, base + b * col + idx * E::EB) << (8 * E::EB * e);
+                        }
+                        c[b][d] = (int)v;
+                    }
+            }
+            if (!FP8) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    // dword d of a column holds outer 2d (low half), 2d + 1 (high)
+                    w[d >> 1][(2 * d) & 3] =
+                        (int)__builtin_amdgcn_perm((unsigned)c[1][d], (unsigned)c[0][d], 0x05040100u);
+                    w[d >> 1][(2 * d + 1) & 3] =
+                        (int)__builtin_amdgcn_perm((unsigned)c[1][d], (unsigned)c[0][d], 0x07060302u);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int h = e >> 2, sb = e & 3;  // dword and byte of outer e in a column
+                    const unsigned sel = (unsigned)(sb | ((sb + 4) << 8)) | 0x0c0c0000u;
+                    const unsigned p01 = __builtin_amdgcn_perm((unsigned)c[1][h], (unsigned)c[0][h], sel);
+                    const unsigned p23 = __builtin_amdgcn_perm((unsigned)c[3][h], (unsigned)c[2][h], sel);
+                    w[e >> 2][e & 3] = (int)__builtin_amdgcn_perm(p23, p01, 0x05040100u);
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void store(unsigned char (*dst)[SROW]) const
+    {
+        if (kInner) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                *(i4v *)&dst[outer(r)][E::EB * p0()] = w[r];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                *(int *)&dst[outer(e)][E::EB * p0()] = w[e >> 2][e & 3];
+        }
+    }
+    // value of inner e (0 .. kNP-1) at outer slot r (0 .. kOuter-1)
+    __device__ __forceinline__ float val(int r, int e) const
+    {
+        if (kInner) return elem<FP8>(w[r], e);
+        return elem_dw<FP8>(w[r >> 2][r & 3], e);
+    }
+    // This step's operand checksum over the tile's outer indices, into
+    // dst[p][slot]: complete (otherwise, slot 0, the 16 lanes of a row share
+    // p) or one partial per wave (kInner, slot = wave, over the 8 lanes
+    // sharing the inner chunk).
+    __device__ __forceinline__ void sum_to(float (*dst)[NW]) const
+    {
+#pragma unroll
+        for (int e = 0; e < kNP; ++e) {
+            float s = 0.0f;
+#pragma unroll
+            for (int r = 0; r < kOuter; ++r) s += val(r, e);
+            if (kInner) {
+                s = dpp_f32<0x128>(s) + s;  // row_ror:8, lanes l and l ^ 8
+                s = pair_sum32f(pair_sum16f(s));
+                if ((t & 63) < 8) dst[p0() + e][t >> 6] = s;
+            } else {
+                s = sum16f(s);
+                if ((t & 15) == 0) dst[p0() + e][0] = s;
+            }
+        }
+    }
+    // Encoded checksum (with the other operand's checksum v, indexed like
+    // this thread's inner values) and squared norms over this step.
+    // (FP8: amx tracks the largest magnitude for the truncation term.)
+    __device__ __forceinline__ void encode(const float (&v)[kNP], float (&enc)[kOuter],
+                                           float (&nrm)[kOuter], float &amx) const
+    {
+#pragma unroll
+        for (int r = 0; r < kOuter; ++r)
+#pragma unroll
+            for (int e = 0; e < kNP; ++e) {
+                const float a = val(r, e);
+                enc[r] = fmaf(a, v[e], enc[r]);
+                nrm[r] = fmaf(a, a, nrm[r]);
+                if (FP8) amx = fmaxf(amx, fabsf(a));
+            }
+    }
+    // Per-outer sums completed over the threads holding the same outer
+    // index, into dst[part][outer].
+    __device__ __forceinline__ void partials_to(const float (&a_in)[kOuter], double (*dst)[128]) const
+    {
+#pragma unroll
+        for (int r = 0; r < kOuter; ++r) {
+            double a = (double)a_in[r];
+            if (kInner) {
+                // the 8 consecutive lanes holding the 8 inner chunks
+                a += dpp_f64<kQuadXor1>(a);
+                a += dpp_f64<kQuadXor2>(a);
+                a += dpp_f64<kRowHalfMirror>(a);
+                if ((t & 7) == 0) dst[0][outer(r)] = a;
+            } else {
+                a = sum_rows(a);  // the 4 inner groups of a wave
+                if ((t & 48) == 0) dst[t >> 6][outer(r)] = a;
+            }
+        }
+    }
+    // one thread per group of inner indices accounts for their checksum
+    __device__ __forceinline__ bool first_of_p() const { return kInner ? t < 8 : (t & 15) == 0; }
+};
+
+template <int kParts>
+__device__ __forceinline__ float gather_lp(const float (*src)[NW], int p)
+{
+    if (kParts == 1) return src[p][0];
+    return ((src[p][0] + src[p][1]) + (src[p][2] + src[p][3])) +
+           ((src[p][4] + src[p][5]) + (src[p][6] + src[p][7]));
+}
+
+__device__ __forceinline__ int owner_wave(int row, int col) { return (row >> 6) + 2 * (col >> 5); }
+__device__ __forceinline__ int owner_lane(int row, int col)
+{
+    return 16 * ((row & 15) >> 2) + (col & 15);
+}
+__device__ __forceinline__ int owner_reg(int row, int col)
+{
+    return ((row & 63) >> 4) * 8 + ((col & 31) >> 4) * 4 + (row & 3);
+}
+
+template <bool FP8, bool TA, bool TB, bool ABFT>
+__device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
+{
+    using E = Elem<FP8>;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int q = lane >> 4, c16 = lane & 15;
+    const int64_t i0 = (int64_t)tile_m * TM, j0 = (int64_t)tile_n * TN;
+    float *__restrict__ C = (float *)g.C;
+    const int64_t m = g.m, n = g.n, k = g.k, ldc = g.ldc;
+    const int nsteps = (int)((k + E::BK - 1) / E::BK);
+    const int hrows = (int)(m - i0 < TM ? m - i0 : TM);
+    const int wcols = (int)(n - j0 < TN ? n - j0 : TN);
+    const bool use_c = g.beta != 0.0;
+
+    // inner index along the stored rows: A transposed, B not transposed
+    using LA = LpLoader<FP8, TA>;
+    using LB = LpLoader<FP8, !TB>;
+    LA la;
+    LB lb;
+    la.init(g.A, g.lda, TA ? k : m, TA ? m : k, t);
+    lb.init(g.B, g.ldb, TB ? n : k, TB ? k : n, t);
+    auto load = [&](int s) {
+        const int64_t k0 = (int64_t)s * E::BK;
+        la.load(i0, k0, m, k);
+        lb.load(j0, k0, n, k);
+    };
+
+    int nf = 0;
+    if (ABFT) {
+        if (w == 0) {
+            const int cnt = gather_tile_faults(g, i0, j0, TM, TN, E::BK, g.k_base, sm.faults);
+            if (lane == 0) sm.nfaults = cnt;
+        }
+        __syncthreads();
+        nf = sm.nfaults;
+    }
+
+    int kind = 0, first_nr = 0, first_nc = 0, first_i = -1, first_j = -1;
+    double rec_before = 0, rec_after = 0;
+
+    f4 acc[4][2];
+#pragma unroll 1
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        const bool faults_on = ABFT && attempt == 0 && nf > 0;
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+                acc[mi][ni] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+        float enc_a[LA::kOuter] = {}, nrm_a[LA::kOuter] = {};
+        float enc_b[LB::kOuter] = {}, nrm_b[LB::kOuter] = {};
+        float vx = 0.0f, vy = 0.0f, amx_a = 0.0f, amx_b = 0.0f;
+        float yv[LA::kNP], xv[LB::kNP];  // y at the A loader's p, x at the B loader's
+
+        load(0);
+        if (ABFT) {
+            la.sum_to(sm.xs[0]);
+            lb.sum_to(sm.ys[0]);
+        }
+        int s = 0;
+#pragma unroll 1
+        while (s < nsteps) {
+            int stop = nsteps - 1;
+            if (faults_on)
+                for (int f = 0; f < nf; ++f) {
+                    const int fs = sm.faults[f].kstep;
+                    if (sm.faults[f].target == FTGEMM_TGT_ACC && fs >= s && fs < stop) stop = fs;
+                }
+#pragma unroll 1
+            for (; s <= stop; ++s) {
+                const int buf = s & 1;
+                la.store(sm.u.st[buf].A);
+                lb.store(sm.u.st[buf].B);
+                __syncthreads();
+                if (ABFT) {
+                    // x_p, y_p of step s are complete: the encoded checksums
+                    // and norms of step s, before the registers take step s + 1
+#pragma unroll
+                    for (int e = 0; e < LA::kNP; ++e) yv[e] = gather_lp<LB::kParts>(sm.ys[buf], la.p0() + e);
+#pragma unroll
+                    for (int e = 0; e < LB::kNP; ++e) xv[e] = gather_lp<LA::kParts>(sm.xs[buf], lb.p0() + e);
+                    la.encode(yv, enc_a, nrm_a, amx_a);
+                    lb.encode(xv, enc_b, nrm_b, amx_b);
+                    if (la.first_of_p())
+#pragma unroll
+                        for (int e = 0; e < LA::kNP; ++e) vy = fmaf(yv[e], yv[e], vy);
+                    if (lb.first_of_p())
+#pragma unroll
+                        for (int e = 0; e < LB::kNP; ++e) vx = fmaf(xv[e], xv[e], vx);
+                }
+                if (s + 1 < nsteps) load(s + 1);
+#pragma unroll
+                for (int kk = 0; kk < E::NKK; ++kk) {
+                    const int kb = kk * E::KPI * E::EB;  // byte offset of this MFMA's inner range
+                    if (!FP8) {
+                        bf8v fa[4], fb[2];
+#pragma unroll
+                        for (int mi = 0; mi < 4; ++mi)
+                            fa[mi] = *(const bf8v *)&sm.u.st[buf].A[wm * 64 + 16 * mi + c16][kb + 16 * q];
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni)
+                            fb[ni] = *(const bf8v *)&sm.u.st[buf].B[wn * 32 + 16 * ni + c16][kb + 16 * q];
+#pragma unroll
+                        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                            for (int ni = 0; ni < 2; ++ni)
+                                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    fa[mi], fb[ni], acc[mi][ni], 0, 0, 0);
+                    } else {
+                        i8v fa[4], fb[2];
+#pragma unroll
+                        for (int mi = 0; mi < 4; ++mi)
+                            fa[mi] = *(const i8v *)&sm.u.st[buf].A[wm * 64 + 16 * mi + c16][kb + 32 * q];
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni)
+                            fb[ni] = *(const i8v *)&sm.u.st[buf].B[wn * 32 + 16 * ni + c16][kb + 32 * q];
+#pragma unroll
+                        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                            for (int ni = 0; ni < 2; ++ni)
+                                acc[mi][ni] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                                    fa[mi], fb[ni], acc[mi][ni], 0, 0, 0, 127, 0, 127);
+                    }
+                }
+                if (ABFT && s + 1 < nsteps) {
+                    // operand checksums of step s + 1, published before its barrier
+                    la.sum_to(sm.xs[buf ^ 1]);
+                    lb.sum_to(sm.ys[buf ^ 1]);
+                }
+            }
+            if (ABFT && faults_on) {
+                for (int f = 0; f < nf; ++f) {
+                    const TileFault tf = sm.faults[f];
+                    if (tf.target != FTGEMM_TGT_ACC || tf.kstep != stop) continue;
+                    if (w != owner_wave(tf.row, tf.col)) continue;
+                    const int ol = owner_lane(tf.row, tf.col), sel = owner_reg(tf.row, tf.col);
+                    float before = 0.0f;
+#pragma unroll
+                    for (int e = 0; e < 32; ++e)
+                        if (sel == e) before = acc[e >> 3][(e >> 2) & 1][e & 3];
+                    const float after = tf.mode == FTGEMM_INJ_ADD ? (float)((double)before + tf.delta)
+                                                                  : flip_bit_f32(before, tf.bit & 31);
+#pragma unroll
+                    for (int e = 0; e < 32; ++e)
+                        if (sel == e && lane == ol) acc[e >> 3][(e >> 2) & 1][e & 3] = after;
+                    if (lane == ol) {
+                        ftgemm_injection_echo ech;
+                        ech.problem = g.problem;
+                        ech.applied = 1;
+                        ech.row = i0 + tf.row;
+                        ech.col = j0 + tf.col;
+                        ech.k_index = g.plan[tf.idx].k_index;
+                        ech.before = before;
+                        ech.after = after;
+                        g.echo[tf.idx] = ech;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        if (!ABFT) {
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wm * 64 + 16 * mi + 4 * q + r;
+                        const int col = wn * 32 + 16 * ni + c16;
+                        if (row < hrows && col < wcols) {
+                            float *pc = C + (i0 + row) + (j0 + col) * ldc;
+                            const double o = g.alpha * (double)acc[mi][ni][r];
+                            *pc = (float)(use_c ? o + g.beta * (double)*pc : o);
+                        }
+                    }
+            return;
+        }
+
+        la.partials_to(enc_a, sm.u.epi.enc_row);
+        la.partials_to(nrm_a, sm.u.epi.nrm_row);
+        lb.partials_to(enc_b, sm.u.epi.enc_col);
+        lb.partials_to(nrm_b, sm.u.epi.nrm_col);
+        // |x|^2 (B loader) and |y|^2 (A loader): one thread per group of p
+        {
+            const double sx = sum64(lb.first_of_p() ? (double)vx : 0.0);
+            const double sy = sum64(la.first_of_p() ? (double)vy : 0.0);
+            const double ma = FP8 ? max64((double)amx_a) : 0.0;
+            const double mb = FP8 ? max64((double)amx_b) : 0.0;
+            if (lane == 0) {
+                sm.wsum[w][0] = sx; sm.wsum[w][1] = sy; sm.wsum[w][3] = ma; sm.wsum[w][4] = mb;
+            }
+        }
+
+        // Beta pass fused with the C_in part of the encoding; the output is
+        // rounded to FP32 and the reference sums are taken of what is stored.
+        double col_o[2] = {0, 0}, col_c[2] = {0, 0}, col_c2[2] = {0, 0};
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double row_o = 0, row_c = 0, row_c2 = 0;
+                const int row = wm * 64 + 16 * mi + 4 * q + r;
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni) {
+                    const int col = wn * 32 + 16 * ni + c16;
+                    const bool ok = row < hrows && col < wcols;
+                    const double cin = (use_c && ok) ? (double)C[(i0 + row) + (j0 + col) * ldc] : 0.0;
+                    double o = g.alpha * (double)acc[mi][ni][r];
+                    if (use_c) o = o + g.beta * cin;
+                    const float of = ok ? (float)o : 0.0f;
+                    acc[mi][ni][r] = of;
+                    row_o += (double)of; row_c += cin; row_c2 += cin * cin;
+                    col_o[ni] += (double)of; col_c[ni] += cin; col_c2[ni] += cin * cin;
+                }
+                row_o = sum16(row_o);
+                if (use_c) { row_c = sum16(row_c); row_c2 = sum16(row_c2); }
+                if (c16 == 0) {
+                    sm.u.epi.ref_row[wn][row] = row_o;
+                    sm.u.epi.cin_row[wn][row] = row_c;
+                    sm.u.epi.cin2_row[wn][row] = row_c2;
+                }
+            }
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) {
+            col_o[ni] = sum_rows(col_o[ni]);
+            if (use_c) { col_c[ni] = sum_rows(col_c[ni]); col_c2[ni] = sum_rows(col_c2[ni]); }
+            if (q == 0) {
+                const int col = wn * 32 + 16 * ni + c16;
+                sm.u.epi.ref_col[wm][col] = col_o[ni];
+                sm.u.epi.cin_col[wm][col] = col_c[ni];
+                sm.u.epi.cin2_col[wm][col] = col_c2[ni];
+            }
+        }
+        if (t == 0) { sm.nbad_r = 0; sm.nbad_c = 0; sm.ibad = TM; sm.jbad = TN; }
+        __syncthreads();
+
+        const bool is_row = t < TM, is_col = t >= TM && t < TM + TN;
+        const int x = is_row ? t : t - TM;
+        double nrm2 = 0.0;
+        if (is_row) {
+            double e = 0, nr = 0;
+#pragma unroll
+            for (int v = 0; v < LA::kOuterParts; ++v) { e += sm.u.epi.enc_row[v][x]; nr += sm.u.epi.nrm_row[v][x]; }
+            nrm2 = nr;
+            sm.u.epi.fin_row[x] = e;
+        } else if (is_col) {
+            double e = 0, nr = 0;
+#pragma unroll
+            for (int v = 0; v < LB::kOuterParts; ++v) { e += sm.u.epi.enc_col[v][x]; nr += sm.u.epi.nrm_col[v][x]; }
+            nrm2 = nr;
+            sm.u.epi.fin_col[x] = e;
+        }
+        // Frobenius norms of the A and B tiles (waves 0-1 and 2-3), |x|, |y|
+        if (w < 4) {
+            const double f = sum64(nrm2);
+            if (lane == 0) sm.wsum[w][2] = f;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double sx = 0, sy = 0, ma = 0, mb = 0;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) {
+                sx += sm.wsum[v][0]; sy += sm.wsum[v][1];
+                ma = fmax(ma, sm.wsum[v][3]); mb = fmax(mb, sm.wsum[v][4]);
+            }
+            sm.scal[0] = sx;                                // |x|^2
+            sm.scal[1] = sy;                                // |y|^2
+            sm.scal[4] = ma;                                // max|A_I|
+            sm.scal[5] = mb;                                // max|B_J|
+            sm.scal[2] = sm.wsum[0][2] + sm.wsum[1][2];     // |A_I|_F^2
+            sm.scal[3] = sm.wsum[2][2] + sm.wsum[3][2];     // |B_J|_F^2
+        }
+        __syncthreads();
+
+        {
+            const double sqk = sqrt((double)k);
+            double ratio = 0.0;
+            if (is_row || is_col) {
+                double P = g.alpha * (is_row ? sm.u.epi.fin_row[x] : sm.u.epi.fin_col[x]);
+                double R = 0.0, cs = 0.0, c2 = 0.0;
+                if (is_row) {
+#pragma unroll
+                    for (int v = 0; v < WN; ++v) {
+                        R += sm.u.epi.ref_row[v][x];
+                        cs += sm.u.epi.cin_row[v][x];
+                        c2 += sm.u.epi.cin2_row[v][x];
+                    }
+                } else {
+                    R = sm.u.epi.ref_col[0][x] + sm.u.epi.ref_col[1][x];
+                    cs = sm.u.epi.cin_col[0][x] + sm.u.epi.cin_col[1][x];
+                    c2 = sm.u.epi.cin2_col[0][x] + sm.u.epi.cin2_col[1][x];
+                }
+                if (use_c) P += g.beta * cs;
+                if (faults_on)
+                    for (int f = 0; f < nf; ++f) {
+                        const TileFault tf = sm.faults[f];
+                        const bool hit = is_row
+                            ? (tf.target == FTGEMM_TGT_COL_CHECKSUM && tf.row == x)
+                            : (tf.target == FTGEMM_TGT_ROW_CHECKSUM && tf.col == x);
+                        if (hit) {
+                            ftgemm_injection_echo e;
+                            e.problem = g.problem; e.applied = 1; e.row = i0 + tf.row;
+                            e.col = j0 + tf.col; e.k_index = g.plan[tf.idx].k_index;
+                            e.before = P; P += tf.delta; e.after = P;
+                            g.echo[tf.idx] = e;
+                        }
+                    }
+                double tau = is_row
+                    ? ft_threshold(kLambda, U, sqk, sqrt((double)wcols), g.alpha, sqrt(nrm2),
+                                   sqrt(sm.scal[3]), sqrt(sm.scal[1]), g.beta, sqrt(c2))
+                    : ft_threshold(kLambda, U, sqk, sqrt((double)hrows), g.alpha, sqrt(nrm2),
+                                   sqrt(sm.scal[2]), sqrt(sm.scal[0]), g.beta, sqrt(c2));
+                if (FP8)
+                    tau += kLambda * fabs(g.alpha) * kTruncGrid * sqrt((double)kTruncGroup) *
+                           sqrt((double)(is_row ? wcols : hrows)) *
+                           (is_row ? sm.scal[5] : sm.scal[4]) * sqrt(nrm2);
+                const double d = R - P;
+                if (is_row) {
+                    sm.u.epi.fin_row[x] = P; sm.u.epi.tau_row[x] = tau; sm.u.epi.d_row[x] = d;
+                } else {
+                    sm.u.epi.fin_col[x] = P; sm.u.epi.tau_col[x] = tau; sm.u.epi.d_col[x] = d;
+                }
+                if (x < (is_row ? hrows : wcols)) {
+                    if (!(fabs(d) <= tau)) {
+                        atomicAdd(is_row ? &sm.nbad_r : &sm.nbad_c, 1);
+                        atomicMin(is_row ? &sm.ibad : &sm.jbad, x);
+                    } else if (tau > 0.0) {
+                        ratio = fabs(d) / tau;
+                    }
+                }
+            }
+            if (w < 4) {
+                ratio = max64(ratio);
+                if (lane == 0) atomic_max_nonneg(&g.counters->max_ratio_bits, ratio);
+            }
+        }
+        __syncthreads();
+
+        const int nr = sm.nbad_r, nc = sm.nbad_c;
+        if (nr == 0 && nc == 0) {
+            if (attempt == 1) kind = FTGEMM_KIND_RECOMPUTED;
+            break;
+        }
+        if (attempt == 1) {
+            kind = FTGEMM_KIND_UNCORRECTABLE;
+            break;
+        }
+        first_nr = nr; first_nc = nc;
+        first_i = nr ? sm.ibad : -1;
+        first_j = nc ? sm.jbad : -1;
+
+        if (nr == 1 && nc == 1) {
+            const int is = first_i, js = first_j;
+            double s_col = 0.0, s_row = 0.0;
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wm * 64 + 16 * mi + 4 * q + r;
+                        const int col = wn * 32 + 16 * ni + c16;
+                        const double o = (double)acc[mi][ni][r];
+                        if (col == js && row != is) s_col += o;
+                        if (row == is && col != js) s_row += o;
+                    }
+            s_col = sum64(s_col);
+            s_row = sum64(s_row);
+            __syncthreads();
+            if (lane == 0) { sm.red[w][0] = s_col; sm.red[w][1] = s_row; }
+            __syncthreads();
+            double sc = 0.0, sr = 0.0;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) { sc += sm.red[v][0]; sr += sm.red[v][1]; }
+            const double fixed = sm.u.epi.fin_col[js] - sc;
+            const float fixed_f = (float)fixed;
+            if (fabs(sr + (double)fixed_f - sm.u.epi.fin_row[is]) <= sm.u.epi.tau_row[is]) {
+                if (w == owner_wave(is, js)) {
+                    const int ol = owner_lane(is, js), sel = owner_reg(is, js);
+#pragma unroll
+                    for (int e = 0; e < 32; ++e)
+                        if (sel == e && lane == ol) {
+                            rec_before = (double)acc[e >> 3][(e >> 2) & 1][e & 3];
+                            acc[e >> 3][(e >> 2) & 1][e & 3] = fixed_f;
+                        }
+                }
+                rec_after = (double)fixed_f;
+                kind = FTGEMM_KIND_CORRECTED;
+                break;
+            }
+        } else if (nr + nc == 1) {
+            kind = FTGEMM_KIND_CHECKSUM_ONLY;
+            break;
+        }
+        __syncthreads();
+        if (t == 0) {
+            sm.red[0][0] = first_j >= 0 ? sm.u.epi.d_col[first_j] : 0.0;
+            sm.red[0][1] = first_j >= 0 ? sm.u.epi.tau_col[first_j] : 0.0;
+            sm.red[1][0] = first_i >= 0 ? sm.u.epi.d_row[first_i] : 0.0;
+            sm.red[1][1] = first_i >= 0 ? sm.u.epi.tau_row[first_i] : 0.0;
+        }
+        __syncthreads();
+    }
+
+    if (ABFT) {
+        if (kind == FTGEMM_KIND_CORRECTED) {
+            __syncthreads();
+            if (w == owner_wave(first_i, first_j) && lane == owner_lane(first_i, first_j))
+                sm.red[2][0] = rec_before;
+            __syncthreads();
+            rec_before = sm.red[2][0];
+        }
+        if (t == 0) {
+            DevCounters *ct = g.counters;
+            atomicAdd(&ct->tiles_verified, 1ull);
+            if (kind != 0) {
+                atomicAdd(&ct->detected, 1ull);
+                unsigned long long *which =
+                    kind == FTGEMM_KIND_CORRECTED ? &ct->corrected
+                    : kind == FTGEMM_KIND_CHECKSUM_ONLY ? &ct->checksum_only
+                    : kind == FTGEMM_KIND_RECOMPUTED ? &ct->recomputed
+                                                     : &ct->uncorrectable;
+                atomicAdd(which, 1ull);
+                const unsigned slot = atomicAdd(&ct->record_count, 1u);
+                if (slot < g.record_cap) {
+                    const bool again = kind == FTGEMM_KIND_RECOMPUTED ||
+                                       kind == FTGEMM_KIND_UNCORRECTABLE;
+                    ftgemm_fault_record rc;
+                    rc.problem = g.problem;
+                    rc.kind = kind;
+                    rc.tile_m = tile_m;
+                    rc.tile_n = tile_n;
+                    rc.row = first_i >= 0 ? i0 + first_i : -1;
+                    rc.col = first_j >= 0 ? j0 + first_j : -1;
+                    rc.nbad_rows = first_nr;
+                    rc.nbad_cols = first_nc;
+                    rc.d_row = again ? sm.red[0][0] : first_j >= 0 ? sm.u.epi.d_col[first_j] : 0.0;
+                    rc.tau_row = again ? sm.red[0][1] : first_j >= 0 ? sm.u.epi.tau_col[first_j] : 0.0;
+                    rc.d_col = again ? sm.red[1][0] : first_i >= 0 ? sm.u.epi.d_row[first_i] : 0.0;
+                    rc.tau_col = again ? sm.red[1][1] : first_i >= 0 ? sm.u.epi.tau_row[first_i] : 0.0;
+                    rc.before = kind == FTGEMM_KIND_CORRECTED ? rec_before : 0.0;
+                    rc.after = kind == FTGEMM_KIND_CORRECTED ? rec_after : 0.0;
+                    g.records[slot] = rc;
+                }
+            }
+        }
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wm * 64 + 16 * mi + 4 * q + r;
+                    const int col = wn * 32 + 16 * ni + c16;
+                    if (row < hrows && col < wcols)
+                        C[(i0 + row) + (j0 + col) * ldc] = acc[mi][ni][r];
+                }
+    }
+}
+
+template <bool FP8, bool TA, bool TB, bool ABFT>
+__global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
+{
+    __shared__ Smem sm;
+    int tm_, tn_;
+    map_tile(blockIdx.x, g.tiles_m, g.tiles_n, tm_, tn_);
+    tile<FP8, TA, TB, ABFT>(g, tm_, tn_, sm);
+}
+
+template <bool FP8>
+hipError_t launch(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream)
+{
+    const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n;
+    if (grid == 0) return hipSuccess;
+#define FTG_LP_CASE(a, b, c) \
+    hipLaunchKernelGGL((kernel<FP8, a, b, c>), dim3(grid), dim3(NT), 0, stream, g)
+    if (abft) {
+        if (!ta && !tb) FTG_LP_CASE(false, false, true);
+        else if (!ta && tb) FTG_LP_CASE(false, true, true);
+        else if (ta && !tb) FTG_LP_CASE(true, false, true);
+        else FTG_LP_CASE(true, true, true);
+    } else {
+        if (!ta && !tb) FTG_LP_CASE(false, false, false);
+        else if (!ta && tb) FTG_LP_CASE(false, true, false);
+        else if (ta && !tb) FTG_LP_CASE(true, false, false);
+        else FTG_LP_CASE(true, true, false);
+    }
+#undef FTG_LP_CASE
+    return hipGetLastError();
+}
+
+}  // namespace lp
+
+hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, bool abft,
+                     hipStream_t stream)
+{
+    return fp8 ? lp::launch<true>(g, ta, tb, abft, stream)
+               : lp::launch<false>(g, ta, tb, abft, stream);
+}
+
+void tiling_lp(bool fp8, int *tm, int *tn, int *bk)
+{
+    *tm = lp::TM;
+    *tn = lp::TN;
+    *bk = fp8 ? lp::Elem<true>::BK : lp::Elem<false>::BK;
+}
+
+}  // namespace ftg

@@ -48,3 +48,65 @@ def flagged(records):
 def f64_tiling(m, n, k):
     tm, tn, bk, sk = F.query_tiling(F.F64, m, n, k)
     return tm, tn, bk
+
+
+# -- low precision (BF16, FP8 E4M3) ---------------------------------------------
+
+def lp_inputs(A, B, dtype):
+    """Quantise float64 operands to the input format: (codes_A, codes_B,
+    scale_A, scale_B, decoded_A, decoded_B).  The decoded values come from
+    the oracle's own decoders, so the oracle sees exactly the GPU's inputs."""
+    orc = O.default()
+    if dtype == F.BF16:
+        ca, cb = synth.to_bf16_bits(A), synth.to_bf16_bits(B)
+        return ca, cb, 1.0, 1.0, _fortran(orc.decode_bf16(ca), A), _fortran(orc.decode_bf16(cb), B)
+    sa, sb = synth.e4m3_scale(A), synth.e4m3_scale(B)
+    ca, cb = synth.to_e4m3_bits(A, sa), synth.to_e4m3_bits(B, sb)
+    return ca, cb, sa, sb, _fortran(orc.decode_e4m3(ca), A), _fortran(orc.decode_e4m3(cb), B)
+
+
+def _fortran(dec, like):
+    assert dec.shape == like.shape
+    return np.asfortranarray(dec)
+
+
+def codes_to_device(codes, dtype):
+    import torch
+    if dtype == F.BF16:
+        t = F.to_device(codes.view(np.int16))
+        return t.view(torch.bfloat16)
+    return F.to_device(codes.view(np.uint8))
+
+
+def gpu_lp(codes_a, codes_b, Cin, alpha, beta, dtype, ta=False, tb=False, plan=(), abft=True,
+           scale_a=1.0, scale_b=1.0, ldc_pad=0):
+    """Run the BF16 / FP8 fault-tolerant GEMM; Cin is float32-representable."""
+    import torch
+    dA, dB = codes_to_device(codes_a, dtype), codes_to_device(codes_b, dtype)
+    m, n = Cin.shape
+    dC = F.to_device(np.asfortranarray(Cin, dtype=np.float32),
+                     ld=m + ldc_pad if ldc_pad else None)
+    F.set_fault_plan(plan)
+    rb = F.ReportBuffer()
+    d = F.make_desc(dA, dB, dC, alpha, beta, ta, tb, abft=abft, scaleA=scale_a, scaleB=scale_b,
+                    dtype=dtype)
+    F.gemm_ex(d, report=rb)
+    torch.cuda.synchronize()
+    F.clear_fault_plan()
+    out = np.asfortranarray(dC.cpu().numpy().astype(np.float64))
+    return out, rb.view()
+
+
+# The FP8 matrix instructions cut each product to 2^-14 of its group's
+# largest product binade, in groups of 8 inner indices; the oracle's
+# thresholds take that as (grid, group).  BF16 products are added exactly.
+FP8_MMA = (2.0 ** -14, 8)
+
+
+def lp_mma(dtype):
+    return FP8_MMA if dtype == F.FP8_E4M3 else (0.0, 1)
+
+
+def lp_tiling(dtype, m, n, k):
+    tm, tn, bk, sk = F.query_tiling(dtype, m, n, k)
+    return tm, tn, bk

@@ -1,0 +1,250 @@
+"""BF16 and FP8 (E4M3, per-tensor scale) fault-tolerant GEMM on the GPU
+against the CPU oracle.
+
+The oracle runs in FP64 on the same quantised inputs (decoded by its own
+decoders), with alpha' = alpha * sA * sB, FP32 accumulators for bit flips
+and u = 2^-24 in its thresholds; for FP8 its thresholds also carry the
+term of the matrix instructions' truncated group sums (grid 2^-14 of the
+group's largest product, groups of 8 inner indices).
+
+Tolerance on C, normwise max|C - C_oracle| / max|C_oracle|: 1e-5 for BF16
+and 5e-4 for FP8.  BF16 products are exact in FP32 and added as in FP32, so
+the only errors are the FP32 accumulation (a random walk of unit roundoffs
+of the partial sums, below 1e-6 normwise for k <= 8192 with these inputs)
+and the FP32 rounding of the output (2^-24 relative); 1e-5 leaves a margin
+of ten.  The FP8 instructions cut every product to a multiple of 2^-14 times
+its group's largest product: a group of 8 errs by at most 8 * 2^-14 M_g
+(M_g about 3 sigma_a sigma_b for normal inputs), and the k / 8 groups of an
+element add like a random walk, against max|C| of about 4.5 sqrt(k)
+sigma_a sigma_b -- about 2^-11 * 3 / (4.5 sqrt(8)) = 1.2e-4 normwise at
+worst (1e-5 .. 3e-5 measured); 5e-4 keeps a margin of four.  An element rebuilt by
+the correction carries the rounding error of the FP32 encoded checksum it
+is rebuilt from, which that entry's threshold bounds: rebuilt elements are
+compared with the oracle within that threshold instead.
+
+Flagged (row, col, kind) sets must agree exactly with the oracle's; planned
+bit flips are kept only when their effect is at least 8 times the larger
+threshold of their row and column (or not finite), so that both sides'
+decisions are far from the threshold."""
+import numpy as np
+import pytest
+
+from gpu_util import flagged, gpu_lp, lp_inputs, lp_mma, lp_tiling, normwise, say, to_oracle
+from oracle import oracle as O
+from paper_2305_02444_amd import ftgemm as F
+from paper_2305_02444_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = {F.BF16: 1e-5, F.FP8_E4M3: 5e-4}
+DTYPES = [pytest.param(F.BF16, id="bf16"), pytest.param(F.FP8_E4M3, id="fp8")]
+
+
+def _c32(Cin):
+    return np.asfortranarray(Cin.astype(np.float32).astype(np.float64))
+
+
+def _flip32(v, bit):
+    b = np.array([v], dtype=np.float32).view(np.uint32)
+    b ^= np.uint32(1 << bit)
+    return float(b.view(np.float32)[0])
+
+
+def _compare(A, B, Cin, alpha, beta, dtype, ta=False, tb=False, plan=(), tiles=None, q=None):
+    """Quantise, run both sides, compare C and the flagged sets."""
+    m, n = Cin.shape
+    k = A.shape[0] if ta else A.shape[1]
+    tm, tn, bk = lp_tiling(dtype, m, n, k)
+    ca, cb, sa, sb, dA, dB = lp_inputs(A, B, dtype) if q is None else q
+    Cin = _c32(Cin)
+    say("case dtype=%d m=%d n=%d k=%d ta=%d tb=%d faults=%d" % (dtype, m, n, k, ta, tb,
+                                                               len(plan)))
+    got, rep = gpu_lp(ca, cb, Cin, alpha, beta, dtype, ta, tb, plan, scale_a=sa, scale_b=sb)
+    ref = O.default().ftgemm(dA, dB, Cin, alpha * sa * sb, beta, ta, tb, tm, tn, bk, 32,
+                             to_oracle(plan), tiles=tiles, mma=lp_mma(dtype))
+    recs = rep.records
+    tiles_m = -(-m // tm)
+    if tiles is not None:
+        keep = set(int(t) for t in tiles)
+        recs = [r for r in recs if r["tile_m"] + r["tile_n"] * tiles_m in keep]
+    assert flagged(recs) == flagged(ref.records)
+    mask = ~np.isnan(ref.C)
+    for r in recs:
+        if r["kind"] == F.KIND_CORRECTED:
+            i, j = r["row"], r["col"]
+            bound = max(r["tau_row"], r["tau_col"])
+            assert abs(got[i, j] - ref.C[i, j]) <= bound, (i, j, got[i, j], ref.C[i, j], bound)
+            mask[i, j] = False
+    err = normwise(got[mask], ref.C[mask])
+    assert err <= TOL[dtype], err
+    return got, rep, ref
+
+
+def _guarded_flips(A, B, dA, dB, sa, sb, alpha, beta, Cin, dtype, count, g, ta=False, tb=False):
+    """Bit flips on FP32 accumulators (exponent and high fraction bits) in
+    distinct tiles, kept when their effect is far above the thresholds."""
+    m, n = Cin.shape
+    k = A.shape[0] if ta else A.shape[1]
+    tm, tn, bk = lp_tiling(dtype, m, n, k)
+    orc = O.default()
+    cand = synth.bitflip_plan(g, m, n, k, tm, tn, min(4 * count, (-(-m // tm)) * (-(-n // tn))))
+    kept = []
+    for f in cand:
+        kend = min(k, (f.k_index // bk + 1) * bk)
+        before = float(orc.gemm_entries(dA, dB, [f.row], [f.col], ta=ta, tb=tb, k=kend)[0])
+        before = float(np.float32(before))
+        after = _flip32(before, f.bit)
+        tr, tc = orc.tile_thresholds(dA, dB, f.row // tm, f.col // tn, _c32(Cin),
+                                     alpha * sa * sb, beta, ta, tb, tm, tn, bk, 32,
+                                     mma=lp_mma(dtype))
+        tau = max(tr[f.col % tn], tc[f.row % tm])
+        if not np.isfinite(after) or abs(alpha * sa * sb * (after - before)) >= 8 * tau:
+            kept.append(f)
+        if len(kept) == count:
+            break
+    return kept
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+def test_lp_ragged_transposes(dtype, ta, tb):
+    """Ragged in every dimension (m, n not multiples of 8; k not a multiple
+    of the 16-byte load), beta != 0, additive faults on accumulators."""
+    m, n, k = 203, 141, 301
+    A, B, Cin = synth.operands(30, 1, m, n, k, "normal", ta, tb)
+    q = lp_inputs(A, B, dtype)
+    g = synth.rng(30, 1, synth.STREAM_PLAN)
+    tm, tn, bk = lp_tiling(dtype, m, n, k)
+    # accumulator deltas of 1e3 .. 1e5 in output units (accumulators carry
+    # the FP8 scales out)
+    plan = synth.additive_plan(g, m, n, k, tm, tn, 4,
+                               synth.log_magnitude(1e3 / (q[2] * q[3]), 0.0, 2.0))
+    got, rep, ref = _compare(A, B, Cin, -0.7, 1.3, dtype, ta, tb, plan, q=q)
+    assert rep.corrected == 4 == rep.detected
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 3, 5), (128, 128, 64), (129, 127, 65),
+                                   (64, 300, 129), (300, 17, 1000), (8, 9, 16)])
+def test_lp_small_and_edge_shapes(dtype, m, n, k):
+    A, B, Cin = synth.operands(31, m * 1000 + n, m, n, k, "uniform")
+    got, rep, ref = _compare(A, B, Cin, 1.0, 0.5, dtype)
+    assert not rep.records and rep.tiles_verified == (-(-m // 128)) * (-(-n // 128))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_lp_plain_kernel_bitwise_equals_ft(dtype):
+    """With no faults the checksum-free kernel writes the same bits."""
+    A, B, Cin = synth.operands(32, 0, 333, 222, 111, "normal")
+    ca, cb, sa, sb, dA, dB = lp_inputs(A, B, dtype)
+    C32 = _c32(Cin)
+    ft, rep = gpu_lp(ca, cb, C32, 1.5, -0.5, dtype, scale_a=sa, scale_b=sb)
+    plain, _ = gpu_lp(ca, cb, C32, 1.5, -0.5, dtype, abft=False, scale_a=sa, scale_b=sb)
+    assert np.array_equal(ft, plain) and not rep.records
+    ref = O.default().gemm(dA, dB, C32, 1.5 * sa * sb, -0.5)
+    assert normwise(plain, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_lp_special_cases(dtype):
+    A, B, Cin = synth.operands(33, 0, 70, 50, 40, "uniform")
+    ca, cb, sa, sb, dA, dB = lp_inputs(A, B, dtype)
+    C32 = _c32(Cin)
+    got, rep = gpu_lp(ca, cb, C32, 0.0, 0.5, dtype, scale_a=sa, scale_b=sb)
+    assert np.array_equal(got, _c32(0.5 * C32))
+    nanC = np.full_like(C32, np.nan)
+    got, rep = gpu_lp(ca, cb, nanC, 1.0, 0.0, dtype, scale_a=sa, scale_b=sb)
+    ref = O.default().gemm(dA, dB, None, sa * sb, 0.0)
+    assert normwise(got, ref) <= TOL[dtype] and not rep.records
+    got, rep = gpu_lp(ca, cb, C32, 0.0, 1.0, dtype, scale_a=sa, scale_b=sb)
+    assert np.array_equal(got, C32)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_lp_padded_leading_dimension_of_c(dtype):
+    A, B, Cin = synth.operands(34, 0, 130, 140, 33, "uniform")
+    ca, cb, sa, sb, dA, dB = lp_inputs(A, B, dtype)
+    C32 = _c32(Cin)
+    got, rep = gpu_lp(ca, cb, C32, 1.0, 1.0, dtype, scale_a=sa, scale_b=sb, ldc_pad=5)
+    assert normwise(got, O.default().gemm(dA, dB, C32, sa * sb, 1.0)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_lp_bitflips_and_fault_classes(dtype):
+    """FP32 accumulator bit flips (exponent / high fraction bits) located
+    and rebuilt; a checksum-only fault; two faults in one tile recomputed."""
+    m = n = 512
+    k = 1024
+    A, B, Cin = synth.operands(35, 0, m, n, k, "normal")
+    q = lp_inputs(A, B, dtype)
+    ca, cb, sa, sb, dA, dB = q
+    g = synth.rng(35, 0, synth.STREAM_PLAN)
+    flips = _guarded_flips(A, B, dA, dB, sa, sb, 1.0, 1.0, Cin, dtype, 8, g)
+    assert len(flips) >= 6
+    got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, dtype, plan=flips, q=q)
+    assert rep.corrected == len(flips) == rep.detected
+    for e, f in zip(rep.echoes, flips):
+        assert e["applied"] and (e["row"], e["col"]) == (f.row, f.col)
+        assert np.float32(e["after"]).view(np.uint32) == \
+            np.float32(e["before"]).view(np.uint32) ^ np.uint32(1 << f.bit)
+    # fault classes in tiles the flips left alone
+    used = {(f.row // 128, f.col // 128) for f in flips}
+    free = [(a, b) for b in range(4) for a in range(4) if (a, b) not in used]
+    (a0, b0), (a1, b1) = free[0], free[1]
+    Fa = synth.Fault
+    unit = 1.0 / (sa * sb)  # accumulator units per output unit
+    plan = [Fa(128 * a0 + 3, 128 * b0 + 5, 10, synth.ADD, 5e4 * unit),
+            Fa(128 * a0 + 40, 128 * b0 + 90, 900, synth.ADD, -3e4 * unit),
+            Fa(128 * a1 + 7, 128 * b1 + 1, 0, synth.ADD, 1e5, target=synth.TGT_ROW_CHECKSUM)]
+    got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, dtype, plan=plan, q=q)
+    assert sorted(r["kind"] for r in rep.records) == sorted([F.KIND_RECOMPUTED,
+                                                            F.KIND_CHECKSUM_ONLY])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_lp_8192_sampled_tiles(dtype):
+    """m = n = k = 8192, normal inputs, as timed by the benchmark.  Error-free:
+    no tile flagged (false-positive rate 0 of 4096).  With one guarded FP32
+    bit flip per 64 tiles: every one located and rebuilt; the oracle checks
+    the tiles holding a fault plus sampled clean and corner tiles."""
+    size = 8192
+    A, B, Cin = synth.operands(40, size, size, size, size, "normal")
+    q = lp_inputs(A, B, dtype)
+    ca, cb, sa, sb, dA, dB = q
+    tiles_m = size // 128
+    extra = [0, tiles_m * tiles_m - 1, tiles_m - 1] + [int(t) for t in synth.rng(40, 1, 9).choice(
+        tiles_m * tiles_m, 5, replace=False)]
+    got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, dtype, tiles=sorted(set(extra)), q=q)
+    assert rep.detected == 0 and rep.tiles_verified == tiles_m * tiles_m
+    assert 0 < rep.max_ratio < 1
+    g = synth.rng(40, size, synth.STREAM_PLAN)
+    flips = _guarded_flips(A, B, dA, dB, sa, sb, 1.0, 1.0, Cin, dtype, tiles_m * tiles_m // 64, g)
+    assert len(flips) == tiles_m * tiles_m // 64
+    faulty = sorted({(f.row // 128) + (f.col // 128) * tiles_m for f in flips})
+    tiles = sorted(set(faulty[:12]) | set(extra))
+    got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, dtype, plan=flips, tiles=tiles, q=q)
+    assert rep.corrected == len(flips) == rep.detected
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_group_sums_of_the_matrix_instructions(dtype):
+    """The arithmetic the thresholds assume, observed through the library:
+    448 * 448 + 7 * 1 within one group of 8 inner indices comes out as
+    448^2 in FP8 (7 is below 2^-14 of the product's binade 2^17 and is cut),
+    but exactly when the two products sit in different groups, and always
+    exactly in BF16.  The fault-tolerant call flags nothing."""
+    k = 16
+    for pos, exact_expected in ((1, dtype != F.FP8_E4M3), (8, True)):
+        A = np.zeros((1, k), order="F")
+        B = np.zeros((k, 1), order="F")
+        A[0, 0], B[0, 0] = 448.0, 448.0
+        A[0, pos], B[pos, 0] = 7.0, 1.0
+        if dtype == F.BF16:
+            ca, cb = synth.to_bf16_bits(A), synth.to_bf16_bits(B)
+        else:
+            ca, cb = synth.to_e4m3_bits(A, 1.0), synth.to_e4m3_bits(B, 1.0)
+        C0 = np.zeros((1, 1), order="F")
+        for abft in (False, True):
+            got, rep = gpu_lp(ca, cb, C0, 1.0, 0.0, dtype, abft=abft)
+            want = 200711.0 if exact_expected else 200704.0
+            assert got[0, 0] == want, (dtype, pos, abft, got[0, 0])
+            assert not rep.records
