@@ -6,6 +6,7 @@ kernel with every checksum operation compiled out, at 8192^3 in FP64 (the
 headline) and BF16 / FP8 (extra legs), with and without injected faults.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --profile {f64,bf16,fp8,copy}   (for rocprofv3 passes)
 
 A step is one full fault-tolerant GEMM call C = alpha*A*B + beta*C
 (alpha = beta = 1, inputs uniform on [-1, 1], column-major N/N) on inputs
@@ -104,6 +105,138 @@ def cpu_baseline(A, B, Cin, m, n, k, budget_s=12.0):
                                                                            n, k, dt)}
 
 
+def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
+    """One low-precision leg at size^3: normal(0,1) inputs quantised to the
+    format (FP8: per-tensor scales amax / 448), FP32 C, alpha = beta = 1."""
+    m = n = k = size
+    flops = 2.0 * m * n * k
+    wid = 41 if dtype == F.BF16 else 42
+    A, B, Cin = synth.operands(wid, size, m, n, k, "normal")
+    if dtype == F.BF16:
+        ca, cb, sa, sb = synth.to_bf16_bits(A), synth.to_bf16_bits(B), 1.0, 1.0
+        dA = F.to_device(ca.view(np.int16)).view(torch.bfloat16)
+        dB = F.to_device(cb.view(np.int16)).view(torch.bfloat16)
+        deq = lambda t, s_: t.to(torch.float64)
+    else:
+        sa, sb = synth.e4m3_scale(A), synth.e4m3_scale(B)
+        ca, cb = synth.to_e4m3_bits(A, sa), synth.to_e4m3_bits(B, sb)
+        dA, dB = F.to_device(ca.view(np.uint8)), F.to_device(cb.view(np.uint8))
+        deq = lambda t, s_: t.view(torch.float8_e4m3fn).to(torch.float64) * s_
+    dC0 = F.to_device(np.asfortranarray(Cin, dtype=np.float32))
+    dC = dC0.clone()
+    del A, B
+
+    def call(abft):
+        d = F.make_desc(dA, dB, dC, 1.0, 1.0, abft=abft, scaleA=sa, scaleB=sb, dtype=dtype)
+        return lambda: F.gemm_ex(d)
+
+    F.clear_fault_plan()
+    rb = F.ReportBuffer()
+    dC.copy_(dC0)
+    F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype), report=rb)
+    clean = rb.view()
+    # accuracy on sampled 256 x 256 blocks against an FP64 product of the
+    # decoded inputs (the quantisation itself is not counted)
+    g = synth.rng(wid, size, 9)
+    errs = []
+    for _ in range(4):
+        i0 = int(g.integers(0, m - 256)) if m > 256 else 0
+        j0 = int(g.integers(0, n - 256)) if n > 256 else 0
+        ref = deq(dA[i0:i0 + 256, :], sa).contiguous() @ deq(dB[:, j0:j0 + 256], sb).contiguous() + \
+            dC0[i0:i0 + 256, j0:j0 + 256].to(torch.float64)
+        got = dC[i0:i0 + 256, j0:j0 + 256].to(torch.float64)
+        errs.append(float((got - ref).abs().max() / ref.abs().max()))
+    t_ft, t_ft_ev = timed(torch, call(True), steps, warmup)
+    t_plain, _ = timed(torch, call(False), steps, warmup)
+    tm, tn, bk, _ = F.query_tiling(dtype, m, n, k)
+    tiles = (-(-m // tm)) * (-(-n // tn))
+    gp = synth.rng(wid, size, synth.STREAM_PLAN)
+    # exponent flips (bits 27..30) of FP32 accumulators: always far above
+    # the rounding threshold unless the accumulator is exactly zero
+    plan = synth.bitflip_plan(gp, m, n, k, tm, tn, -(-tiles // 64), bits=[27, 28, 29, 30])
+    F.set_fault_plan(plan)
+    t_inj, _ = timed(torch, call(True), steps, warmup)
+    rb = F.ReportBuffer()
+    F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype), report=rb)
+    inj = rb.view()
+    F.clear_fault_plan()
+    name = "bf16" if dtype == F.BF16 else "fp8"
+    # flips the verification did not see: the change they made to the
+    # output against the thresholds of the flagged tiles
+    hit = {(r["row"], r["col"]) for r in inj.records}
+    taus = sorted(max(r["tau_row"], r["tau_col"]) for r in inj.records)
+    alpha_p = sa * sb
+    missed = [abs(alpha_p * (e["after"] - e["before"])) for e in inj.echoes
+              if (e["row"], e["col"]) not in hit]
+    achieved = flops / (t_ft_ev * 1e-3) / 1e12
+    return {
+        "tflops": round(flops / (t_ft * 1e-3) / 1e12, 3),
+        "ms_per_call": round(t_ft, 4),
+        "plain_tflops": round(flops / (t_plain * 1e-3) / 1e12, 3),
+        "abft_overhead_pct": round(100.0 * (t_ft / t_plain - 1.0), 2),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[name],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK[name], 4),
+                     "traffic": read_traffic("ftgemm_%s_8192_counters.txt" % name,
+                                             ["ftgemm_lp.hip", "ftgemm_device.h"])
+                     if size == 8192 else None},
+        "injected": {"faults_per_call": len(plan), "kind": "FP32 exponent bit flip",
+                     "tflops": round(flops / (t_inj * 1e-3) / 1e12, 3),
+                     "overhead_pct": round(100.0 * (t_inj / t_plain - 1.0), 2),
+                     "corrected": int(inj.corrected), "detected": int(inj.detected),
+                     "undetected_output_change": [float("%.4g" % d) for d in missed],
+                     "median_threshold": float("%.4g" % taus[len(taus) // 2]) if taus else None},
+        "error_free_check": {"detected": int(clean.detected), "max_ratio": clean.max_ratio,
+                             "tiles_verified": int(clean.tiles_verified)},
+        "max_rel_err_vs_fp64": max(errs),
+        "config": "m=n=k=%d, normal(0,1) inputs%s, FP32 C, alpha=beta=1, tile %dx%dx%d" % (
+            size, " with per-tensor scales" if name == "fp8" else "", tm, tn, bk),
+    }
+
+
+def profile_run(kind, size, calls=3):
+    """A short fixed workload for counter passes: `calls` fault-tolerant
+    GEMMs of one format at size^3 (alpha = beta = 1, no report), or, for
+    `copy`, device copies of a 512 MiB buffer (the scale of the traffic
+    counters)."""
+    import torch
+    from paper_2305_02444_amd import ftgemm as F
+    torch.cuda.set_device(0)
+    if kind == "copy":
+        src = torch.empty(64 << 20, dtype=torch.float64, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(calls):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copy of %d bytes x %d" % (src.numel() * 8, calls), flush=True)
+        return
+    m = n = k = size
+    g = torch.Generator(device="cuda").manual_seed(5)
+    if kind == "f64":
+        A = F.colmajor_empty(m, k, torch.float64)
+        B = F.colmajor_empty(k, n, torch.float64)
+        A.uniform_(-1, 1, generator=g)
+        B.uniform_(-1, 1, generator=g)
+        Cm = F.colmajor_empty(m, n, torch.float64).uniform_(-1, 1, generator=g)
+        d = F.make_desc(A, B, Cm, 1.0, 1.0)
+    else:
+        dt = torch.bfloat16 if kind == "bf16" else torch.float8_e4m3fn
+        A = F.colmajor_empty(m, k, torch.float32).normal_(generator=g)
+        B = F.colmajor_empty(k, n, torch.float32).normal_(generator=g)
+        scale = 1.0 if kind == "bf16" else 1.0 / 64.0
+        A8, B8 = (A / scale).to(dt), (B / scale).to(dt)
+        del A, B
+        Cm = F.colmajor_empty(m, n, torch.float32).normal_(generator=g)
+        code = F.BF16 if kind == "bf16" else F.FP8_E4M3
+        if kind == "fp8":
+            A8, B8 = A8.view(torch.uint8), B8.view(torch.uint8)
+        d = F.make_desc(A8, B8, Cm, 1.0, 1.0, scaleA=scale, scaleB=scale, dtype=code)
+    F.clear_fault_plan()
+    for _ in range(calls):
+        F.gemm_ex(d)
+    torch.cuda.synchronize()
+    print("%s fault-tolerant GEMM %d^3 x %d" % (kind, size, calls), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[1])
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +244,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-low-precision", action="store_true")
+    ap.add_argument("--profile", choices=["f64", "bf16", "fp8", "copy"])
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -118,6 +253,9 @@ def main():
               "no cross-GPU exchange, and this build runs on a single MI355X; use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+    if args.profile:
+        profile_run(args.profile, args.size)
+        return
 
     import numpy as np
     import torch
@@ -167,7 +305,7 @@ def main():
     value = flops / (t_ft * 1e-3) / 1e12
     achieved = flops / (t_ft_ev * 1e-3) / 1e12
     traffic = read_traffic("ftgemm_f64_8192_counters.txt",
-                           ["ftgemm_f64.hip", "ftgemm_device.h"])
+                           ["ftgemm_f64.hip", "ftgemm_device.h"]) if m == 8192 else None
     out = {
         "metric": "FT-GEMM TFLOP/s and ABFT overhead vs plain GEMM at 8192^3 FP64/BF16",
         "value": round(value, 3),
@@ -183,7 +321,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "fault-tolerant DGEMM, FP64, m=n=k=%d, column-major N/N, "
                                "alpha=beta=1, inputs uniform[-1,1], error-free" % m,
-                   "m": m, "n": n, "k": k, "tile": [128, 128, 16]},
+                   "m": m, "n": n, "k": k, "tile": list(F.query_tiling(F.F64, m, n, k)[:3])},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64"], 4),
                      "traffic": traffic},
@@ -196,6 +334,18 @@ def main():
         "error_free_check": {"detected": int(clean.detected), "max_ratio": clean.max_ratio,
                              "tiles_verified": int(clean.tiles_verified)},
     }
+    if not args.no_low_precision:
+        del dA, dB, dC, dC0
+        torch.cuda.empty_cache()
+        lp = {}
+        for dt in (F.BF16, F.FP8_E4M3):
+            lp["bf16" if dt == F.BF16 else "fp8"] = lp_leg(torch, F, synth, np, dt, m,
+                                                          args.steps, args.warmup)
+            print("# leg done: %s" % ("bf16" if dt == F.BF16 else "fp8"), file=sys.stderr,
+                  flush=True)
+        lp["bf16"]["speedup_vs_fp64"] = round(lp["bf16"]["tflops"] / value, 2)
+        lp["fp8"]["speedup_vs_fp64"] = round(lp["fp8"]["tflops"] / value, 2)
+        out["low_precision"] = lp
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, Cin, m, n, k)
     print(json.dumps(out), flush=True)
