@@ -43,7 +43,26 @@ struct GemmArgs {
     int32_t nplan;
     const ftgemm_injection *plan;
     ftgemm_injection_echo *echo;        // one slot per plan entry
+    // split inner dimension (FP64): nslices > 1 runs slice s of every tile
+    // in workgroup s * tiles + tile; the slice covers inner indices
+    // [s * slice_k, min(k, (s + 1) * slice_k)), writes its verified partial
+    // product to wsp + s * m * n (leading dimension m) and its encoded
+    // checksums and thresholds to chk (layout: see slice_chk_index).
+    int32_t nslices;
+    int32_t slice_last;                 // set per workgroup: last slice
+    int64_t slice_k;
+    double *wsp;
+    double *chk;
 };
+
+// Slice checksum workspace: for slice s and tile t (tile_m + tile_n *
+// tiles_m), 2 * (tm + tn) doubles: encoded checksums of the tile's rows
+// (tm) and columns (tn), then their thresholds.
+__device__ __host__ __forceinline__ int64_t slice_chk_index(int64_t s, int64_t tile,
+                                                            int64_t ntiles, int tm, int tn)
+{
+    return (s * ntiles + tile) * 2 * (tm + tn);
+}
 
 // ---------------------------------------------------------------------------
 // Lane reductions.  DPP moves only exchange 32-bit values, so doubles go
@@ -252,10 +271,15 @@ __device__ __forceinline__ int gather_tile_faults(const GemmArgs &g, int64_t i0,
         bool hit = false;
         if (idx < g.nplan) {
             const ftgemm_injection f = g.plan[idx];
+            // accumulator faults land in the slice holding their inner
+            // index; with a split inner dimension, so do checksum faults
+            // (the last slice takes indices past the end)
+            const bool in_slice = f.k_index >= k_base &&
+                                  (f.k_index < k_base + g.k ||
+                                   (f.target != FTGEMM_TGT_ACC && g.slice_last));
             hit = f.problem == g.problem && f.row >= i0 && f.row < i0 + tm && f.col >= j0 &&
                   f.col < j0 + tn && f.row < g.m && f.col < g.n &&
-                  (f.target != FTGEMM_TGT_ACC ||
-                   (f.k_index >= k_base && f.k_index < k_base + g.k));
+                  ((f.target != FTGEMM_TGT_ACC && g.nslices <= 1) || in_slice);
         }
         unsigned long long mask = __ballot(hit);
         while (mask && n < kMaxTileFaults) {

@@ -663,6 +663,22 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 }
             }
         }
+        // Split inner dimension: publish this slice's encoded checksums and
+        // thresholds for the verified reduction.  An entry that disagreed
+        // alone (checksum-only) is replaced by the reference sum of the
+        // verified data.
+        if (g.nslices > 1 && t < TM + TN) {
+            const bool row = t < TM;
+            const int x = row ? t : t - TM;
+            double P = row ? sm.u.epi.fin_row[x] : sm.u.epi.fin_col[x];
+            const double tau = row ? sm.u.epi.tau_row[x] : sm.u.epi.tau_col[x];
+            if (kind == FTGEMM_KIND_CHECKSUM_ONLY && x == (row ? first_i : first_j))
+                P += row ? sm.u.epi.d_row[x] : sm.u.epi.d_col[x];
+            double *dst = g.chk + slice_chk_index(0, tile_m + (int64_t)tile_n * g.tiles_m,
+                                                  (int64_t)g.tiles_m * g.tiles_n, TM, TN);
+            dst[t] = P;
+            dst[TM + TN + t] = tau;
+        }
         // Store the verified tile.
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
@@ -683,8 +699,29 @@ __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
 {
     __shared__ Smem sm;
     int tm_, tn_;
-    map_tile(blockIdx.x, g.tiles_m, g.tiles_n, tm_, tn_);
-    tile<TA, TB, ABFT>(g, tm_, tn_, sm);
+    if (g.nslices <= 1) {
+        map_tile(blockIdx.x, g.tiles_m, g.tiles_n, tm_, tn_);
+        tile<TA, TB, ABFT>(g, tm_, tn_, sm);
+        return;
+    }
+    // Slice s of a split inner dimension: the partial product of the
+    // slice's inner range (alpha 1, beta 0) into the workspace.
+    const int ntiles = g.tiles_m * g.tiles_n;
+    const int s = blockIdx.x / ntiles;
+    map_tile(blockIdx.x - s * ntiles, g.tiles_m, g.tiles_n, tm_, tn_);
+    GemmArgs gs = g;
+    const int64_t kb = (int64_t)s * g.slice_k;
+    gs.k = (g.k - kb < g.slice_k) ? g.k - kb : g.slice_k;
+    gs.k_base = g.k_base + kb;
+    gs.slice_last = s == g.nslices - 1;
+    gs.A = (const double *)g.A + kb * (TA ? 1 : g.lda);
+    gs.B = (const double *)g.B + kb * (TB ? g.ldb : 1);
+    gs.C = g.wsp + s * g.m * g.n;
+    gs.ldc = g.m;
+    gs.alpha = 1.0;
+    gs.beta = 0.0;
+    gs.chk = g.chk + slice_chk_index(s, 0, ntiles, TM, TN);
+    tile<TA, TB, ABFT>(gs, tm_, tn_, sm);
 }
 
 }  // namespace f64
@@ -694,7 +731,8 @@ __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
 
 hipError_t launch_f64(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream)
 {
-    const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n;
+    const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n *
+                          (unsigned)(g.nslices > 1 ? g.nslices : 1);
     if (grid == 0) return hipSuccess;
     if (abft) {
         if (!ta && !tb) FTG_F64_CASE(false, false, true);

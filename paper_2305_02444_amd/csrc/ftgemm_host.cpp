@@ -41,6 +41,9 @@ struct DeviceWs {
     ftgemm_fault_record *h_records = nullptr;
     ftgemm_injection_echo *h_echo = nullptr;
     int h_echo_cap = 0;
+    // split inner dimension: partial products, slice checksums
+    double *split = nullptr;
+    size_t split_bytes = 0;
 };
 
 std::unordered_map<int, DeviceWs> g_ws;
@@ -121,6 +124,47 @@ ftgemm_status workspace(DeviceWs **out, int ncounters)
     }
     *out = &ws;
     return FTGEMM_OK;
+}
+
+// Device scratch for a split inner dimension, grown on demand (the device is
+// synchronised first: an earlier call may still be using it).
+ftgemm_status split_space(DeviceWs &ws, size_t bytes)
+{
+    if (bytes <= ws.split_bytes) return FTGEMM_OK;
+    if (ws.split) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(ws.split));
+        ws.split = nullptr;
+        ws.split_bytes = 0;
+    }
+    HIP_TRY(hipMalloc((void **)&ws.split, bytes));
+    ws.split_bytes = bytes;
+    return FTGEMM_OK;
+}
+
+// Number of inner-dimension slices for an FP64 problem: enough workgroups
+// for two per compute unit when the output alone has fewer tiles than
+// compute units and the inner dimension is at least 32 steps long, each
+// slice at least 8 steps long and the partial products within 1 GiB.
+// *slice_k is a multiple of bk.
+constexpr int64_t kSplitTargetWgs = 512;
+constexpr int64_t kSplitMaxSlices = 16;
+constexpr int64_t kSplitMaxBytes = int64_t(1) << 30;
+
+int choose_split(int64_t m, int64_t n, int64_t k, int tm, int tn, int bk, int64_t *slice_k)
+{
+    *slice_k = k;
+    const int64_t tiles = ((m + tm - 1) / tm) * ((n + tn - 1) / tn);
+    if (tiles == 0 || tiles >= 256 || k < 32 * bk) return 1;
+    int64_t s = (kSplitTargetWgs + tiles - 1) / tiles;
+    if (s > k / (8 * bk)) s = k / (8 * bk);
+    if (s > kSplitMaxSlices) s = kSplitMaxSlices;
+    while (s > 1 && s * m * n * 8 > kSplitMaxBytes) --s;
+    if (s <= 1) return 1;
+    const int64_t steps = (k + bk - 1) / bk;
+    const int64_t per = (steps + s - 1) / s;
+    *slice_k = per * bk;
+    return (int)((k + *slice_k - 1) / *slice_k);
 }
 
 double unpack_ratio(unsigned long long bits)
@@ -253,6 +297,19 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
     else
         ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, &tm, &tn, &bk);
     GemmArgs g = base_args(d, tm, tn);
+    int64_t slice_k = d.k;
+    const int nslices =
+        d.dtype == FTGEMM_F64 ? choose_split(d.m, d.n, d.k, tm, tn, bk, &slice_k) : 1;
+    if (nslices > 1) {
+        const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
+        const size_t wbytes = sizeof(double) * (size_t)nslices * d.m * d.n;
+        const size_t cbytes = sizeof(double) * (size_t)nslices * ntiles * 2 * (tm + tn);
+        if (ftgemm_status st = split_space(*ws, wbytes + cbytes)) return st;
+        g.nslices = nslices;
+        g.slice_k = slice_k;
+        g.wsp = ws->split;
+        g.chk = ws->split + (size_t)nslices * d.m * d.n;
+    }
     g.counters = ws->counters;
     g.records = ws->records;
     g.record_cap = kDevRecordCap;
@@ -261,9 +318,28 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
     g.echo = ws->echo;
     if (rep && d.abft) HIP_TRY(ftg::launch_clear_report(ws->counters, 1, ws->echo, ws->nplan, stream));
     const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
-    if (d.dtype == FTGEMM_F64)
+    if (d.dtype == FTGEMM_F64) {
         HIP_TRY(ftg::launch_f64(g, ta, tb, d.abft != 0, stream));
-    else
+        if (nslices > 1) {
+            ftg::ReduceArgs r{};
+            r.C = (double *)d.C;
+            r.wsp = g.wsp;
+            r.chk = g.chk;
+            r.m = d.m;
+            r.n = d.n;
+            r.ldc = d.ldc;
+            r.alpha = g.alpha;
+            r.beta = d.beta;
+            r.nslices = nslices;
+            r.tiles_m = g.tiles_m;
+            r.tiles_n = g.tiles_n;
+            r.problem = 0;
+            r.counters = ws->counters;
+            r.records = ws->records;
+            r.record_cap = kDevRecordCap;
+            HIP_TRY(ftg::launch_splitk_reduce(r, d.abft != 0, stream));
+        }
+    } else
         HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft != 0, stream));
     if (rep && d.abft) {
         HIP_TRY(hipMemcpyAsync(ws->h_counters, ws->counters, sizeof(DevCounters),
@@ -364,14 +440,18 @@ ftgemm_status ftgemm_query_tiling(ftgemm_dtype dtype, int64_t m, int64_t n, int6
     if (k < 0) return invalid(4);
     if (!tm || !tn || !bk || !split_k) return invalid(5);
     int a = 0, b = 0, c = 0;
-    if (dtype == FTGEMM_F64)
+    int64_t slice_k = k;
+    int s = 1;
+    if (dtype == FTGEMM_F64) {
         ftg::tiling_f64(&a, &b, &c);
-    else
+        s = choose_split(m, n, k, a, b, c, &slice_k);
+    } else {
         ftg::tiling_lp(dtype == FTGEMM_FP8_E4M3, &a, &b, &c);
+    }
     *tm = a;
     *tn = b;
     *bk = c;
-    *split_k = 1;
+    *split_k = s;
     return FTGEMM_OK;
 }
 
@@ -405,6 +485,7 @@ void ftgemm_finalize(void)
         if (ws.h_counters) (void)hipHostFree(ws.h_counters);
         if (ws.h_records) (void)hipHostFree(ws.h_records);
         if (ws.h_echo) (void)hipHostFree(ws.h_echo);
+        if (ws.split) (void)hipFree(ws.split);
     }
     g_ws.clear();
     g_plan_version++;

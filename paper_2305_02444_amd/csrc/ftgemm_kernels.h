@@ -17,6 +17,21 @@ hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, bool abft,
                      hipStream_t stream);
 void tiling_lp(bool fp8, int *tm, int *tn, int *bk);
 
+// Verified reduction of a split inner dimension (FP64): C = alpha * sum_s
+// W_s + beta * C, checked against the slices' encoded checksums.
+struct ReduceArgs {
+    double *C;
+    const double *wsp;   // nslices partial products, each m x n, leading dimension m
+    const double *chk;   // the slices' encoded checksums and thresholds
+    int64_t m, n, ldc;
+    double alpha, beta;
+    int32_t nslices, tiles_m, tiles_n, problem;
+    DevCounters *counters;
+    ftgemm_fault_record *records;
+    uint32_t record_cap;
+};
+hipError_t launch_splitk_reduce(const ReduceArgs &r, bool abft, hipStream_t stream);
+
 // C = beta * C over an m x n column-major matrix of double (f64) or float.
 hipError_t launch_scale(void *C, bool f64, int64_t m, int64_t n, int64_t ldc, double beta,
                         hipStream_t stream);
