@@ -40,6 +40,7 @@ struct GemmArgs {
     DevCounters *counters;
     ftgemm_fault_record *records;
     uint32_t record_cap;
+    unsigned int *rec_slot;             // record slots, shared by all problems
     int32_t nplan;
     const ftgemm_injection *plan;
     ftgemm_injection_echo *echo;        // one slot per plan entry

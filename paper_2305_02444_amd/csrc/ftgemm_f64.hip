@@ -638,7 +638,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                     : kind == FTGEMM_KIND_RECOMPUTED ? &ct->recomputed
                                                      : &ct->uncorrectable;
                 atomicAdd(which, 1ull);
-                const unsigned slot = atomicAdd(&ct->record_count, 1u);
+                atomicAdd(&ct->record_count, 1u);
+                const unsigned slot = atomicAdd(g.rec_slot, 1u);
                 if (slot < g.record_cap) {
                     // residuals: from LDS of this attempt (corrected /
                     // checksum-only) or saved from the first attempt
@@ -724,6 +725,33 @@ __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
     tile<TA, TB, ABFT>(gs, tm_, tn_, sm);
 }
 
+
+// Persistent batched kernel: workgroup w starts on queue w mod nqueues (with
+// one queue per XCD, the XCD it runs on) and moves on to the others when it
+// runs dry; every workgroup leaves once all queues are drained.
+template <bool TA, bool TB, bool ABFT>
+__global__ __launch_bounds__(NT, 2) void batched_kernel(BatchArgs b)
+{
+    __shared__ Smem sm;
+    __shared__ int next;
+    const int first = (int)(blockIdx.x % (unsigned)b.nqueues);
+    for (int qi = 0; qi < b.nqueues; ++qi) {
+        const int qq = (first + qi) % b.nqueues;
+        const int end = b.qbegin[qq + 1];
+        for (;;) {
+            if (threadIdx.x == 0) next = b.qbegin[qq] + (int)atomicAdd(&b.queue[qq], 1u);
+            __syncthreads();
+            const int it = __builtin_amdgcn_readfirstlane(next);
+            __syncthreads();
+            if (it >= end) break;
+            const WorkItem w = b.items[it];
+            const GemmArgs g = b.probs[w.problem];
+            tile<TA, TB, ABFT>(g, w.tile_m, w.tile_n, sm);
+            __syncthreads();
+        }
+    }
+}
+
 }  // namespace f64
 
 #define FTG_F64_CASE(ta, tb, ab) \
@@ -753,6 +781,26 @@ void tiling_f64(int *tm, int *tn, int *bk)
     *tm = f64::TM;
     *tn = f64::TN;
     *bk = f64::BK;
+}
+
+hipError_t launch_f64_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int grid,
+                              hipStream_t stream)
+{
+#define FTG_F64_BCASE(x, y, z) \
+    hipLaunchKernelGGL((f64::batched_kernel<x, y, z>), dim3(grid), dim3(f64::NT), 0, stream, b)
+    if (abft) {
+        if (!ta && !tb) FTG_F64_BCASE(false, false, true);
+        else if (!ta && tb) FTG_F64_BCASE(false, true, true);
+        else if (ta && !tb) FTG_F64_BCASE(true, false, true);
+        else FTG_F64_BCASE(true, true, true);
+    } else {
+        if (!ta && !tb) FTG_F64_BCASE(false, false, false);
+        else if (!ta && tb) FTG_F64_BCASE(false, true, false);
+        else if (ta && !tb) FTG_F64_BCASE(true, false, false);
+        else FTG_F64_BCASE(true, true, false);
+    }
+#undef FTG_F64_BCASE
+    return hipGetLastError();
 }
 
 }  // namespace ftg

@@ -3,6 +3,7 @@
 // copy-back.  Declarations and the contract are in include/ftgemm.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -44,7 +45,24 @@ struct DeviceWs {
     // split inner dimension: partial products, slice checksums
     double *split = nullptr;
     size_t split_bytes = 0;
+    // auxiliary counters: [0] record slots, [1 ..] batched work queues
+    unsigned int *aux = nullptr;
+    unsigned int *h_aux = nullptr;
+    // batched launches: per-problem arguments, work items, captured graph
+    ftg::GemmArgs *d_probs = nullptr, *h_probs = nullptr;
+    int probs_cap = 0;
+    ftg::WorkItem *d_items = nullptr, *h_items = nullptr;
+    int items_cap = 0;
+    hipEvent_t staged = nullptr;  // the last upload from the host staging
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> graph_key;
+    std::unordered_map<uint64_t, int> tuned;  // batch signature -> schedule
+    int cus = 0;
 };
+
+constexpr int kAuxWords = 16;
 
 std::unordered_map<int, DeviceWs> g_ws;
 
@@ -85,6 +103,11 @@ ftgemm_status workspace(DeviceWs **out, int ncounters)
         HIP_TRY(hipMalloc((void **)&ws.records, sizeof(ftgemm_fault_record) * kDevRecordCap));
         HIP_TRY(hipHostMalloc((void **)&ws.h_records,
                               sizeof(ftgemm_fault_record) * kDevRecordCap, hipHostMallocDefault));
+        HIP_TRY(hipMalloc((void **)&ws.aux, sizeof(unsigned int) * kAuxWords));
+        HIP_TRY(hipMemset(ws.aux, 0, sizeof(unsigned int) * kAuxWords));
+        HIP_TRY(hipHostMalloc((void **)&ws.h_aux, sizeof(unsigned int) * kAuxWords,
+                              hipHostMallocDefault));
+        HIP_TRY(hipDeviceGetAttribute(&ws.cus, hipDeviceAttributeMultiprocessorCount, dev));
     }
     if (ws.counters_cap < ncounters) {
         if (ws.counters) {
@@ -188,15 +211,16 @@ void fill_report(const DeviceWs &ws, int p, ftgemm_report *rep, int32_t problem)
     rep->max_ratio = unpack_ratio(c.max_ratio_bits);
     rep->record_count = 0;
     rep->echo_count = 0;
-    const uint32_t nrec = c.record_count < kDevRecordCap ? c.record_count : kDevRecordCap;
-    for (uint32_t r = 0; r < nrec; ++r) {
+    // record slots are shared by the problems of a call (h_aux[0] taken)
+    const uint32_t nslot = ws.h_aux[0] < kDevRecordCap ? ws.h_aux[0] : kDevRecordCap;
+    uint32_t kept = 0;
+    for (uint32_t r = 0; r < nslot; ++r) {
         const ftgemm_fault_record &src = ws.h_records[r];
         if (src.problem != problem) continue;
-        if (rep->records && rep->record_count < rep->record_capacity)
-            rep->records[rep->record_count] = src;
-        rep->record_count++;
+        if (rep->records && kept < rep->record_capacity) rep->records[kept] = src;
+        kept++;
     }
-    if (c.record_count > kDevRecordCap) rep->record_count += c.record_count - kDevRecordCap;
+    rep->record_count = c.record_count;  // also those that found no slot
     for (int q = 0; q < ws.nplan; ++q) {
         if (g_plan[q].problem != problem) continue;
         if (rep->echoes && rep->echo_count < rep->echo_capacity) {
@@ -268,7 +292,8 @@ GemmArgs base_args(const ftgemm_gemm_desc &d, int tm, int tn)
     return g;
 }
 
-ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t stream)
+ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t stream,
+                      int32_t problem = 0)
 {
     t_last_invalid = 0;
     if (int pos = check_args(d)) return invalid(pos);
@@ -310,13 +335,17 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
         g.wsp = ws->split;
         g.chk = ws->split + (size_t)nslices * d.m * d.n;
     }
+    g.problem = problem;
     g.counters = ws->counters;
     g.records = ws->records;
     g.record_cap = kDevRecordCap;
+    g.rec_slot = ws->aux;
     g.nplan = d.abft ? ws->nplan : 0;
     g.plan = ws->plan;
     g.echo = ws->echo;
-    if (rep && d.abft) HIP_TRY(ftg::launch_clear_report(ws->counters, 1, ws->echo, ws->nplan, stream));
+    if (rep && d.abft)
+        HIP_TRY(ftg::launch_clear_report(ws->counters, 1, ws->echo, ws->nplan, ws->aux, 1,
+                                         stream));
     const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
     if (d.dtype == FTGEMM_F64) {
         HIP_TRY(ftg::launch_f64(g, ta, tb, d.abft != 0, stream));
@@ -333,16 +362,19 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
             r.nslices = nslices;
             r.tiles_m = g.tiles_m;
             r.tiles_n = g.tiles_n;
-            r.problem = 0;
+            r.problem = problem;
             r.counters = ws->counters;
             r.records = ws->records;
             r.record_cap = kDevRecordCap;
+            r.rec_slot = ws->aux;
             HIP_TRY(ftg::launch_splitk_reduce(r, d.abft != 0, stream));
         }
     } else
         HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft != 0, stream));
     if (rep && d.abft) {
         HIP_TRY(hipMemcpyAsync(ws->h_counters, ws->counters, sizeof(DevCounters),
+                               hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(ws->h_aux, ws->aux, sizeof(unsigned int),
                                hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipMemcpyAsync(ws->h_records, ws->records,
                                sizeof(ftgemm_fault_record) * kDevRecordCap,
@@ -352,7 +384,299 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
                                    sizeof(ftgemm_injection_echo) * ws->nplan,
                                    hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
-        fill_report(*ws, 0, rep, 0);
+        fill_report(*ws, 0, rep, problem);
+    }
+    return FTGEMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches.
+//
+// All tiles of all problems become work items handed out by device work
+// queues to a persistent grid of one workgroup per compute unit.  The
+// schedule -- the order of the items and whether there is one queue or one
+// per XCD (problems spread over the XCDs, so a problem's operand panels stay
+// in one L2) -- is chosen by timing the candidates on the batch itself the
+// first time a batch of that shape is seen (when its C is write-only, beta
+// == 0 everywhere, so the trial runs change nothing), and remembered.  The
+// clearing of the report area and the persistent launch are captured once
+// into a HIP graph and replayed; a new batch only re-uploads the per-problem
+// arguments and the work items.
+// ---------------------------------------------------------------------------
+enum Schedule { kLptOneQueue = 0, kGivenOneQueue = 1, kLptPerXcd = 2, kNumSchedules = 3 };
+
+uint64_t fnv1a(uint64_t h, uint64_t v)
+{
+    for (int b = 0; b < 8; ++b) {
+        h ^= (v >> (8 * b)) & 0xff;
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+struct BatchPlan {
+    std::vector<ftg::WorkItem> items;
+    int nqueues = 1;
+    int32_t qbegin[ftg::kMaxQueues + 1] = {};
+};
+
+// Work items of the live problems under a schedule.  A tile's cost is taken
+// as its inner length (every tile computes a full TM x TN block).
+void plan_items(const std::vector<ftg::GemmArgs> &probs, const std::vector<int> &live,
+                int sched, BatchPlan *plan)
+{
+    std::vector<int> order(live);
+    if (sched != kGivenOneQueue)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return probs[a].k > probs[b].k; });
+    auto emit = [&](int p) {
+        const ftg::GemmArgs &g = probs[p];
+        for (int tn = 0; tn < g.tiles_n; ++tn)
+            for (int tm = 0; tm < g.tiles_m; ++tm)
+                plan->items.push_back(ftg::WorkItem{p, tm, tn, 0});
+    };
+    plan->items.clear();
+    if (sched != kLptPerXcd) {
+        for (int p : order) emit(p);
+        plan->nqueues = 1;
+        plan->qbegin[0] = 0;
+        plan->qbegin[1] = (int32_t)plan->items.size();
+        return;
+    }
+    // largest problems first onto the least loaded of the XCDs
+    const int nq = ftg::kMaxQueues;
+    std::vector<double> load(nq, 0.0);
+    std::vector<std::vector<int>> bins(nq);
+    for (int p : order) {
+        const ftg::GemmArgs &g = probs[p];
+        const double cost = (double)g.tiles_m * g.tiles_n * (double)g.k;
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[b] += cost;
+        bins[b].push_back(p);
+    }
+    plan->nqueues = nq;
+    for (int q = 0; q < nq; ++q) {
+        plan->qbegin[q] = (int32_t)plan->items.size();
+        for (int p : bins[q]) emit(p);
+    }
+    plan->qbegin[nq] = (int32_t)plan->items.size();
+}
+
+// Upload the per-problem arguments and the work items (host staging is
+// reused only after its previous upload has completed).
+ftgemm_status upload_batch(DeviceWs &ws, const std::vector<ftg::GemmArgs> &probs,
+                           const BatchPlan &plan, hipStream_t stream)
+{
+    const int np = (int)probs.size(), ni = (int)plan.items.size();
+    if (!ws.staged) HIP_TRY(hipEventCreateWithFlags(&ws.staged, hipEventDisableTiming));
+    if (!ws.capture) HIP_TRY(hipStreamCreateWithFlags(&ws.capture, hipStreamNonBlocking));
+    HIP_TRY(hipEventSynchronize(ws.staged));
+    if (np > ws.probs_cap || ni > ws.items_cap) {
+        HIP_TRY(hipDeviceSynchronize());
+        if (np > ws.probs_cap) {
+            if (ws.d_probs) {
+                HIP_TRY(hipFree(ws.d_probs));
+                HIP_TRY(hipHostFree(ws.h_probs));
+            }
+            const int cap = np < 64 ? 64 : np;
+            HIP_TRY(hipMalloc((void **)&ws.d_probs, sizeof(ftg::GemmArgs) * cap));
+            HIP_TRY(hipHostMalloc((void **)&ws.h_probs, sizeof(ftg::GemmArgs) * cap,
+                                  hipHostMallocDefault));
+            ws.probs_cap = cap;
+        }
+        if (ni > ws.items_cap) {
+            if (ws.d_items) {
+                HIP_TRY(hipFree(ws.d_items));
+                HIP_TRY(hipHostFree(ws.h_items));
+            }
+            const int cap = ni < 1024 ? 1024 : ni;
+            HIP_TRY(hipMalloc((void **)&ws.d_items, sizeof(ftg::WorkItem) * cap));
+            HIP_TRY(hipHostMalloc((void **)&ws.h_items, sizeof(ftg::WorkItem) * cap,
+                                  hipHostMallocDefault));
+            ws.items_cap = cap;
+        }
+    }
+    std::memcpy(ws.h_probs, probs.data(), sizeof(ftg::GemmArgs) * np);
+    if (ni) std::memcpy(ws.h_items, plan.items.data(), sizeof(ftg::WorkItem) * ni);
+    HIP_TRY(hipMemcpyAsync(ws.d_probs, ws.h_probs, sizeof(ftg::GemmArgs) * np,
+                           hipMemcpyHostToDevice, stream));
+    if (ni)
+        HIP_TRY(hipMemcpyAsync(ws.d_items, ws.h_items, sizeof(ftg::WorkItem) * ni,
+                               hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(ws.staged, stream));
+    return FTGEMM_OK;
+}
+
+ftg::BatchArgs batch_args(const DeviceWs &ws, const BatchPlan &plan)
+{
+    ftg::BatchArgs b{};
+    b.probs = ws.d_probs;
+    b.items = ws.d_items;
+    b.queue = ws.aux + 1;
+    b.nqueues = plan.nqueues;
+    for (int q = 0; q <= plan.nqueues; ++q) b.qbegin[q] = plan.qbegin[q];
+    return b;
+}
+
+// Clear the report area and run the persistent kernel, on `stream`.
+ftgemm_status launch_batch(DeviceWs &ws, const ftgemm_gemm_desc &d0, int count,
+                           const BatchPlan &plan, hipStream_t stream)
+{
+    const ftg::BatchArgs b = batch_args(ws, plan);
+    const bool ta = d0.transA == FTGEMM_OP_T, tb = d0.transB == FTGEMM_OP_T;
+    HIP_TRY(ftg::launch_clear_report(ws.counters, count, ws.echo, d0.abft ? ws.nplan : 0,
+                                     ws.aux, 1 + plan.nqueues, stream));
+    if (plan.items.empty()) return FTGEMM_OK;
+    if (d0.dtype == FTGEMM_F64)
+        HIP_TRY(ftg::launch_f64_batched(b, ta, tb, d0.abft != 0, ws.cus, stream));
+    else
+        HIP_TRY(ftg::launch_lp_batched(b, d0.dtype == FTGEMM_FP8_E4M3, ta, tb, d0.abft != 0,
+                                       ws.cus, stream));
+    return FTGEMM_OK;
+}
+
+ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_report *reps,
+                          hipStream_t stream)
+{
+    t_last_invalid = 0;
+    if (count < 0) return invalid(1);
+    if (count > 0 && !descs) return invalid(2);
+    for (int32_t p = 0; p < count; ++p) {
+        if (int pos = check_args(descs[p])) return invalid(pos);
+        const ftgemm_gemm_desc &d = descs[p];
+        if (d.dtype != descs[0].dtype || (d.abft != 0) != (descs[0].abft != 0) ||
+            d.transA != descs[0].transA || d.transB != descs[0].transB)
+            return FTGEMM_ERR_UNSUPPORTED;
+        if (reps && ((reps[p].record_capacity && !reps[p].records) ||
+                     (reps[p].echo_capacity && !reps[p].echoes)))
+            return invalid(14);
+    }
+    for (int32_t p = 0; reps && p < count; ++p)
+        std::memset(&reps[p], 0, offsetof(ftgemm_report, record_capacity));
+    if (count == 0) return FTGEMM_OK;
+    const ftgemm_gemm_desc &d0 = descs[0];
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (d0.dtype != FTGEMM_F64 && d0.abft)
+        for (const ftgemm_injection &f : g_plan)
+            if (f.mode == FTGEMM_INJ_BITFLIP && f.bit >= 32) return invalid(14);
+    DeviceWs *ws = nullptr;
+    if (ftgemm_status st = workspace(&ws, count)) return st;
+
+    int tm, tn, bk;
+    if (d0.dtype == FTGEMM_F64)
+        ftg::tiling_f64(&tm, &tn, &bk);
+    else
+        ftg::tiling_lp(d0.dtype == FTGEMM_FP8_E4M3, &tm, &tn, &bk);
+    std::vector<ftg::GemmArgs> probs(count);
+    std::vector<int> live;
+    uint64_t sig = 0xcbf29ce484222325ull;
+    sig = fnv1a(sig, (uint64_t)count);
+    sig = fnv1a(sig, (uint64_t)d0.dtype * 16 + (d0.abft ? 8 : 0) + d0.transA * 2 + d0.transB);
+    bool write_only = true;
+    for (int32_t p = 0; p < count; ++p) {
+        const ftgemm_gemm_desc &d = descs[p];
+        ftg::GemmArgs g = base_args(d, tm, tn);
+        g.problem = p;
+        g.counters = ws->counters + p;
+        g.records = ws->records;
+        g.record_cap = kDevRecordCap;
+        g.rec_slot = ws->aux;
+        g.nplan = d.abft ? ws->nplan : 0;
+        g.plan = ws->plan;
+        g.echo = ws->echo;
+        probs[p] = g;
+        sig = fnv1a(fnv1a(fnv1a(sig, (uint64_t)d.m), (uint64_t)d.n), (uint64_t)d.k);
+        if (d.m == 0 || d.n == 0) continue;
+        if (d.alpha == 0.0 || d.k == 0) {
+            // no product: C <- beta C, outside the persistent launch
+            if (d.beta != 1.0)
+                HIP_TRY(ftg::launch_scale(d.C, d.dtype == FTGEMM_F64, d.m, d.n, d.ldc, d.beta,
+                                          stream));
+            continue;
+        }
+        if (d.beta != 0.0) write_only = false;
+        live.push_back(p);
+    }
+
+    // schedule: remembered, tuned now, or the default
+    int sched = kLptOneQueue;
+    auto known = ws->tuned.find(sig);
+    static const bool no_tune = std::getenv("FTGEMM_NO_TUNE") != nullptr;
+    BatchPlan plan;
+    if (known != ws->tuned.end()) {
+        sched = known->second;
+    } else if (write_only && !no_tune && !live.empty()) {
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        float best = 0.0f;
+        for (int c = 0; c < kNumSchedules; ++c) {
+            plan_items(probs, live, c, &plan);
+            if (ftgemm_status st = upload_batch(*ws, probs, plan, stream)) return st;
+            if (ftgemm_status st = launch_batch(*ws, d0, count, plan, stream)) return st;
+            HIP_TRY(hipEventRecord(e0, stream));
+            for (int r = 0; r < 2; ++r)
+                if (ftgemm_status st = launch_batch(*ws, d0, count, plan, stream)) return st;
+            HIP_TRY(hipEventRecord(e1, stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (c == 0 || ms < best) {
+                best = ms;
+                sched = c;
+            }
+        }
+        HIP_TRY(hipEventDestroy(e0));
+        HIP_TRY(hipEventDestroy(e1));
+        ws->tuned[sig] = sched;
+    }
+    plan_items(probs, live, sched, &plan);
+    if (ftgemm_status st = upload_batch(*ws, probs, plan, stream)) return st;
+
+    // the captured graph is reused while everything baked into it holds
+    std::vector<uint64_t> key = {
+        (uint64_t)d0.dtype, (uint64_t)d0.abft, (uint64_t)d0.transA, (uint64_t)d0.transB,
+        (uint64_t)count, (uint64_t)(d0.abft ? ws->nplan : 0), (uint64_t)(uintptr_t)ws->d_probs,
+        (uint64_t)(uintptr_t)ws->d_items, (uint64_t)(uintptr_t)ws->counters,
+        (uint64_t)(uintptr_t)ws->echo, (uint64_t)(uintptr_t)ws->aux, (uint64_t)plan.nqueues,
+        (uint64_t)ws->cus, (uint64_t)plan.items.size()};
+    for (int q = 0; q <= plan.nqueues; ++q) key.push_back((uint64_t)plan.qbegin[q]);
+    if (!ws->exec || key != ws->graph_key) {
+        if (ws->exec) {
+            HIP_TRY(hipGraphExecDestroy(ws->exec));
+            HIP_TRY(hipGraphDestroy(ws->graph));
+            ws->exec = nullptr;
+            ws->graph = nullptr;
+        }
+        HIP_TRY(hipStreamBeginCapture(ws->capture, hipStreamCaptureModeThreadLocal));
+        const ftgemm_status st = launch_batch(*ws, d0, count, plan, ws->capture);
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamEndCapture(ws->capture, &graph));
+        if (st != FTGEMM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        HIP_TRY(hipGraphInstantiate(&ws->exec, graph, nullptr, nullptr, 0));
+        ws->graph = graph;
+        ws->graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(ws->exec, stream));
+
+    if (reps && d0.abft) {
+        HIP_TRY(hipMemcpyAsync(ws->h_counters, ws->counters, sizeof(DevCounters) * count,
+                               hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(ws->h_aux, ws->aux, sizeof(unsigned int),
+                               hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(ws->h_records, ws->records,
+                               sizeof(ftgemm_fault_record) * kDevRecordCap,
+                               hipMemcpyDeviceToHost, stream));
+        if (ws->nplan)
+            HIP_TRY(hipMemcpyAsync(ws->h_echo, ws->echo,
+                                   sizeof(ftgemm_injection_echo) * ws->nplan,
+                                   hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (int32_t p = 0; p < count; ++p) fill_report(*ws, p, &reps[p], p);
     }
     return FTGEMM_OK;
 }
@@ -396,15 +720,20 @@ ftgemm_status ftgemm_gemm_ex(const ftgemm_gemm_desc *desc, ftgemm_report *report
 ftgemm_status ftgemm_gemm_batched(int32_t count, const ftgemm_gemm_desc *problems,
                                   ftgemm_report *reports, void *stream)
 {
-    (void)count; (void)problems; (void)reports; (void)stream;
-    return FTGEMM_ERR_UNSUPPORTED;
+    return run_batched(count, problems, reports, (hipStream_t)stream);
 }
 
 ftgemm_status ftgemm_gemm_batched_loop(int32_t count, const ftgemm_gemm_desc *problems,
                                        ftgemm_report *reports, void *stream)
 {
-    (void)count; (void)problems; (void)reports; (void)stream;
-    return FTGEMM_ERR_UNSUPPORTED;
+    t_last_invalid = 0;
+    if (count < 0) return invalid(1);
+    if (count > 0 && !problems) return invalid(2);
+    for (int32_t p = 0; p < count; ++p)
+        if (ftgemm_status st = run_one(problems[p], reports ? &reports[p] : nullptr,
+                                       (hipStream_t)stream, p))
+            return st;
+    return FTGEMM_OK;
 }
 
 ftgemm_status ftgemm_set_fault_plan(const ftgemm_injection *plan, int32_t n)
@@ -486,6 +815,16 @@ void ftgemm_finalize(void)
         if (ws.h_records) (void)hipHostFree(ws.h_records);
         if (ws.h_echo) (void)hipHostFree(ws.h_echo);
         if (ws.split) (void)hipFree(ws.split);
+        if (ws.aux) (void)hipFree(ws.aux);
+        if (ws.h_aux) (void)hipHostFree(ws.h_aux);
+        if (ws.exec) (void)hipGraphExecDestroy(ws.exec);
+        if (ws.graph) (void)hipGraphDestroy(ws.graph);
+        if (ws.d_probs) (void)hipFree(ws.d_probs);
+        if (ws.h_probs) (void)hipHostFree(ws.h_probs);
+        if (ws.d_items) (void)hipFree(ws.d_items);
+        if (ws.h_items) (void)hipHostFree(ws.h_items);
+        if (ws.staged) (void)hipEventDestroy(ws.staged);
+        if (ws.capture) (void)hipStreamDestroy(ws.capture);
     }
     g_ws.clear();
     g_plan_version++;

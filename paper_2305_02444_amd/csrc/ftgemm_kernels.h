@@ -29,6 +29,7 @@ struct ReduceArgs {
     DevCounters *counters;
     ftgemm_fault_record *records;
     uint32_t record_cap;
+    unsigned int *rec_slot;
 };
 hipError_t launch_splitk_reduce(const ReduceArgs &r, bool abft, hipStream_t stream);
 
@@ -36,8 +37,27 @@ hipError_t launch_splitk_reduce(const ReduceArgs &r, bool abft, hipStream_t stre
 hipError_t launch_scale(void *C, bool f64, int64_t m, int64_t n, int64_t ldc, double beta,
                         hipStream_t stream);
 
-// Clear a report area: counters and the first n echo slots.
+// Clear a report area: counters, the first n echo slots and naux words of
+// auxiliary counters (record slots, the batched work queue).
 hipError_t launch_clear_report(DevCounters *ct, int ncounters, ftgemm_injection_echo *echo,
-                               int nech, hipStream_t stream);
+                               int nech, unsigned int *aux, int naux, hipStream_t stream);
+
+// Batched persistent launch: the tiles of many problems, pulled from a work
+// queue by a fixed grid of workgroups.
+struct WorkItem {
+    int32_t problem, tile_m, tile_n, pad;
+};
+constexpr int kMaxQueues = 8;
+struct BatchArgs {
+    const GemmArgs *probs;   // one per problem (device)
+    const WorkItem *items;   // in the order they are handed out (device)
+    unsigned int *queue;     // per queue: next item to hand out; zero at launch
+    int32_t nqueues;         // 1, or one per XCD
+    int32_t qbegin[kMaxQueues + 1];  // queue q hands out items [qbegin[q], qbegin[q + 1])
+};
+hipError_t launch_f64_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int grid,
+                              hipStream_t stream);
+hipError_t launch_lp_batched(const BatchArgs &b, bool fp8, bool ta, bool tb, bool abft, int grid,
+                             hipStream_t stream);
 
 }  // namespace ftg

@@ -776,7 +776,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                     : kind == FTGEMM_KIND_RECOMPUTED ? &ct->recomputed
                                                      : &ct->uncorrectable;
                 atomicAdd(which, 1ull);
-                const unsigned slot = atomicAdd(&ct->record_count, 1u);
+                atomicAdd(&ct->record_count, 1u);
+                const unsigned slot = atomicAdd(g.rec_slot, 1u);
                 if (slot < g.record_cap) {
                     const bool again = kind == FTGEMM_KIND_RECOMPUTED ||
                                        kind == FTGEMM_KIND_UNCORRECTABLE;
@@ -822,6 +823,54 @@ __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
     tile<FP8, TA, TB, ABFT>(g, tm_, tn_, sm);
 }
 
+
+// Persistent batched kernel: workgroup w starts on queue w mod nqueues (with
+// one queue per XCD, the XCD it runs on) and moves on to the others when it
+// runs dry; every workgroup leaves once all queues are drained.
+template <bool FP8, bool TA, bool TB, bool ABFT>
+__global__ __launch_bounds__(NT, 2) void batched_kernel(BatchArgs b)
+{
+    __shared__ Smem sm;
+    __shared__ int next;
+    const int first = (int)(blockIdx.x % (unsigned)b.nqueues);
+    for (int qi = 0; qi < b.nqueues; ++qi) {
+        const int qq = (first + qi) % b.nqueues;
+        const int end = b.qbegin[qq + 1];
+        for (;;) {
+            if (threadIdx.x == 0) next = b.qbegin[qq] + (int)atomicAdd(&b.queue[qq], 1u);
+            __syncthreads();
+            const int it = __builtin_amdgcn_readfirstlane(next);
+            __syncthreads();
+            if (it >= end) break;
+            const WorkItem w = b.items[it];
+            const GemmArgs g = b.probs[w.problem];
+            tile<FP8, TA, TB, ABFT>(g, w.tile_m, w.tile_n, sm);
+            __syncthreads();
+        }
+    }
+}
+
+template <bool FP8>
+hipError_t launch_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int grid,
+                          hipStream_t stream)
+{
+#define FTG_LP_BCASE(x, y, z) \
+    hipLaunchKernelGGL((batched_kernel<FP8, x, y, z>), dim3(grid), dim3(NT), 0, stream, b)
+    if (abft) {
+        if (!ta && !tb) FTG_LP_BCASE(false, false, true);
+        else if (!ta && tb) FTG_LP_BCASE(false, true, true);
+        else if (ta && !tb) FTG_LP_BCASE(true, false, true);
+        else FTG_LP_BCASE(true, true, true);
+    } else {
+        if (!ta && !tb) FTG_LP_BCASE(false, false, false);
+        else if (!ta && tb) FTG_LP_BCASE(false, true, false);
+        else if (ta && !tb) FTG_LP_BCASE(true, false, false);
+        else FTG_LP_BCASE(true, true, false);
+    }
+#undef FTG_LP_BCASE
+    return hipGetLastError();
+}
+
 template <bool FP8>
 hipError_t launch(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream)
 {
@@ -851,6 +900,13 @@ hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, bool abft,
 {
     return fp8 ? lp::launch<true>(g, ta, tb, abft, stream)
                : lp::launch<false>(g, ta, tb, abft, stream);
+}
+
+hipError_t launch_lp_batched(const BatchArgs &b, bool fp8, bool ta, bool tb, bool abft, int grid,
+                             hipStream_t stream)
+{
+    return fp8 ? lp::launch_batched<true>(b, ta, tb, abft, grid, stream)
+               : lp::launch_batched<false>(b, ta, tb, abft, grid, stream);
 }
 
 void tiling_lp(bool fp8, int *tm, int *tn, int *bk)

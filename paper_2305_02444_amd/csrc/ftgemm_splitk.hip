@@ -188,7 +188,8 @@ __global__ __launch_bounds__(NT) void reduce_kernel(ReduceArgs r)
                 : kind == FTGEMM_KIND_RECOMPUTED ? &ct->recomputed
                                                  : &ct->uncorrectable;
             atomicAdd(which, 1ull);
-            const unsigned slot = atomicAdd(&ct->record_count, 1u);
+            atomicAdd(&ct->record_count, 1u);
+            const unsigned slot = atomicAdd(r.rec_slot, 1u);
             if (slot < r.record_cap) {
                 ftgemm_fault_record rc;
                 rc.problem = r.problem;

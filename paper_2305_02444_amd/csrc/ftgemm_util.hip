@@ -35,8 +35,9 @@ hipError_t launch_scale(void *C, bool f64, int64_t m, int64_t n, int64_t ldc, do
 }
 
 __global__ void clear_report_kernel(DevCounters *ct, int nct, ftgemm_injection_echo *echo,
-                                    int nech)
+                                    int nech, unsigned int *aux, int naux)
 {
+    for (int i = threadIdx.x; i < naux; i += blockDim.x) aux[i] = 0u;
     for (int i = threadIdx.x; i < nct; i += blockDim.x) {
         DevCounters z{};
         ct[i] = z;
@@ -48,9 +49,10 @@ __global__ void clear_report_kernel(DevCounters *ct, int nct, ftgemm_injection_e
 }
 
 hipError_t launch_clear_report(DevCounters *ct, int nct, ftgemm_injection_echo *echo, int nech,
-                               hipStream_t stream)
+                               unsigned int *aux, int naux, hipStream_t stream)
 {
-    hipLaunchKernelGGL(clear_report_kernel, dim3(1), dim3(256), 0, stream, ct, nct, echo, nech);
+    hipLaunchKernelGGL(clear_report_kernel, dim3(1), dim3(256), 0, stream, ct, nct, echo, nech,
+                       aux, naux);
     return hipGetLastError();
 }
 

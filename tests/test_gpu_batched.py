@@ -1,0 +1,188 @@
+"""Batched fault-tolerant GEMM (one persistent launch replayed from a HIP
+graph, schedule picked by the library's autotuner) against the CPU oracle,
+problem by problem, and against the loop of per-problem launches.
+
+Each problem has its own checksums, report and faults (the plan's `problem`
+field is the index in the batch).  Tolerances as for single calls: 1e-12
+normwise for FP64, 1e-5 for BF16.  The batched and the per-problem paths run
+the same tile code, so their outputs must be bitwise equal."""
+import numpy as np
+import pytest
+
+from gpu_util import flagged, lp_mma, normwise, say, to_oracle
+from oracle import oracle as O
+from paper_2305_02444_amd import ftgemm as F
+from paper_2305_02444_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = {F.F64: 1e-12, F.BF16: 1e-5}
+
+
+def _problem(wid, p, m, n, k, dtype, dist="uniform"):
+    A, B, Cin = synth.operands(wid, p, m, n, k, dist)
+    if dtype == F.F64:
+        return A, B, Cin, A, B
+    orc = O.default()
+    ca, cb = synth.to_bf16_bits(A), synth.to_bf16_bits(B)
+    return ca, cb, np.asfortranarray(Cin.astype(np.float32).astype(np.float64)), \
+        np.asfortranarray(orc.decode_bf16(ca)), np.asfortranarray(orc.decode_bf16(cb))
+
+
+def _device(x, dtype):
+    import torch
+    if dtype == F.F64:
+        return F.to_device(x)
+    return F.to_device(x.view(np.int16)).view(torch.bfloat16)
+
+
+def _batch(shapes, dtype, wid, alpha=1.0, beta=0.0):
+    """Host problems, device tensors and descriptors of a batch."""
+    import torch
+    host, dev, descs = [], [], []
+    for p, (m, n, k) in enumerate(shapes):
+        A, B, Cin, dA, dB = _problem(wid, p, m, n, k, dtype)
+        tA, tB = _device(A, dtype), _device(B, dtype)
+        tC = F.to_device(Cin, dtype=torch.float64 if dtype == F.F64 else torch.float32)
+        host.append((dA, dB, Cin))
+        dev.append((tA, tB, tC))
+        descs.append(F.make_desc(tA, tB, tC, alpha, beta, dtype=dtype))
+    return host, dev, descs
+
+
+def _plan(shapes, wid, dtype, lo_exp):
+    """Truncated Poisson(1) faults per problem (at most 3, one per tile),
+    additive, 10^U(lo, 6) times the typical |C|."""
+    g = synth.rng(wid, 0, synth.STREAM_PLAN)
+    plan = []
+    for p, (m, n, k) in enumerate(shapes):
+        tiles = (-(-m // 128)) * (-(-n // 128))
+        cnt = min(synth.truncated_poisson(g, 1.0, 3), tiles if k > 0 else 0)
+        sigma = np.sqrt(k / 9.0)
+        for f in synth.additive_plan(g, m, n, k, 128, 128, cnt,
+                                     synth.log_magnitude(sigma, lo_exp, 6.0)):
+            f.problem = p
+            plan.append(f)
+    return plan
+
+
+def _outputs(dev, dtype):
+    import torch
+    torch.cuda.synchronize()
+    return [np.asfortranarray(t[2].cpu().numpy().astype(np.float64)) for t in dev]
+
+
+def _check_problem(p, got, host, shapes, plan, rep, dtype, alpha, beta, tiles=None):
+    dA, dB, Cin = host[p]
+    m, n, k = shapes[p]
+    pp = [f for f in plan if f.problem == p]
+    ref = O.default().ftgemm(dA, dB, Cin, alpha, beta, tm=128, tn=128,
+                             bk=F.query_tiling(dtype, m, n, k)[2],
+                             acc_bits=64 if dtype == F.F64 else 32, injections=to_oracle(pp),
+                             tiles=tiles, mma=lp_mma(dtype))
+    mask = ~np.isnan(ref.C)
+    for r in rep.records:
+        if r["kind"] == F.KIND_CORRECTED and dtype != F.F64:
+            mask[r["row"], r["col"]] = False
+            assert abs(got[r["row"], r["col"]] - ref.C[r["row"], r["col"]]) <= \
+                max(r["tau_row"], r["tau_col"])
+    assert normwise(got[mask], ref.C[mask]) <= TOL[dtype], p
+    recs = rep.records
+    if tiles is not None:
+        tm_ = -(-m // 128)
+        keep = set(int(t) for t in tiles)
+        recs = [r for r in recs if r["tile_m"] + r["tile_n"] * tm_ in keep]
+    assert flagged(recs) == flagged(ref.records), p
+
+
+@pytest.mark.parametrize("dtype", [pytest.param(F.F64, id="f64"), pytest.param(F.BF16, id="bf16")])
+def test_small_batch_matches_oracle_and_loop(dtype):
+    g = synth.rng(60, dtype, 7)
+    shapes = [(int(g.integers(1, 300)), int(g.integers(1, 300)), int(g.integers(1, 400)))
+              for _ in range(40)]
+    shapes[3] = (0, 50, 10)        # empty
+    shapes[7] = (60, 70, 0)        # k == 0: C <- beta C (beta 0 here: zeros)
+    plan = _plan(shapes, 60, dtype, 1.0)
+    say("batch of %d, %d faults" % (len(shapes), len(plan)))
+    host, dev, descs = _batch(shapes, dtype, 60)
+    F.set_fault_plan(plan)
+    reps = [F.ReportBuffer() for _ in shapes]
+    F.gemm_batched(descs, reps)
+    got = _outputs(dev, dtype)
+    views = [r.view() for r in reps]
+    for p in range(len(shapes)):
+        if shapes[p][0] and shapes[p][1]:
+            _check_problem(p, got[p], host, shapes, plan, views[p], dtype, 1.0, 0.0)
+    assert sum(v.corrected for v in views) == len(plan)
+    # the same problems, one launch each
+    host2, dev2, descs2 = _batch(shapes, dtype, 60)
+    reps2 = [F.ReportBuffer() for _ in shapes]
+    F.gemm_batched(descs2, reps2, loop=True)
+    got2 = _outputs(dev2, dtype)
+    F.clear_fault_plan()
+    for p in range(len(shapes)):
+        assert np.array_equal(got[p], got2[p]), p
+        assert flagged(reps2[p].view().records) == flagged(views[p].records)
+
+
+def test_graph_replay_new_data_and_beta():
+    """Same shapes twice (the captured graph and the tuned schedule are
+    reused) with different data; then beta != 0 (no tuning: C is read)."""
+    shapes = [(130, 250, 64), (64, 64, 300), (257, 129, 33), (128, 128, 128)] * 3
+    for wid in (61, 62):
+        host, dev, descs = _batch(shapes, F.F64, wid)
+        reps = [F.ReportBuffer() for _ in shapes]
+        F.gemm_batched(descs, reps)
+        got = _outputs(dev, F.F64)
+        for p in range(len(shapes)):
+            _check_problem(p, got[p], host, shapes, [], reps[p].view(), F.F64, 1.0, 0.0)
+    host, dev, descs = _batch(shapes, F.F64, 63, alpha=-0.5, beta=2.0)
+    reps = [F.ReportBuffer() for _ in shapes]
+    F.gemm_batched(descs, reps)
+    got = _outputs(dev, F.F64)
+    for p in range(len(shapes)):
+        _check_problem(p, got[p], host, shapes, [], reps[p].view(), F.F64, -0.5, 2.0)
+
+
+def test_batch_argument_errors():
+    import torch
+    host, dev, descs = _batch([(10, 10, 10), (20, 20, 20)], F.F64, 64)
+    bad = F.make_desc(dev[0][0], dev[0][1], dev[0][2], 1.0, 0.0)
+    bad.lda = 1
+    with pytest.raises(F.FTGemmError) as e:
+        F.gemm_batched([descs[0], bad])
+    assert F.lib().ftgemm_last_invalid_arg() == 8
+    x = F.colmajor_empty(10, 10, torch.bfloat16).zero_()
+    y = F.colmajor_empty(10, 10, torch.float32).zero_()
+    other = F.make_desc(x, x, y, 1.0, 0.0, dtype=F.BF16)
+    with pytest.raises(F.FTGemmError):
+        F.gemm_batched([descs[0], other])
+
+
+@pytest.mark.parametrize("dtype", [pytest.param(F.F64, id="f64"), pytest.param(F.BF16, id="bf16")])
+def test_c5_512_problems(dtype):
+    """512 problems, m, n, k log-uniform in [64, 2048], U[-1,1], alpha = 1,
+    beta = 0, truncated Poisson(1) faults per problem.  Every fault located
+    and rebuilt in its own problem; the oracle checks every faulty tile and
+    a sample of whole problems."""
+    shapes = synth.batched_shapes(70, dtype, 512)
+    plan = _plan(shapes, 70 + dtype, dtype, 1.0)
+    host, dev, descs = _batch(shapes, dtype, 70)
+    F.set_fault_plan(plan)
+    reps = [F.ReportBuffer() for _ in shapes]
+    F.gemm_batched(descs, reps)
+    got = _outputs(dev, dtype)
+    F.clear_fault_plan()
+    views = [r.view() for r in reps]
+    for p, v in enumerate(views):
+        want = sorted((f.row, f.col) for f in plan if f.problem == p)
+        assert sorted((r["row"], r["col"]) for r in v.records) == want, p
+        assert v.corrected == len(want) and v.detected == len(want), p
+    small = sorted(range(512), key=lambda p: shapes[p][0] * shapes[p][1] * shapes[p][2])[:6]
+    for p in small:
+        _check_problem(p, got[p], host, shapes, plan, views[p], dtype, 1.0, 0.0)
+    faulty = sorted({f.problem for f in plan})[:12]
+    for p in faulty:
+        m, n, k = shapes[p]
+        tm_ = -(-m // 128)
+        tiles = sorted({(f.row // 128) + (f.col // 128) * tm_ for f in plan if f.problem == p})
+        _check_problem(p, got[p], host, shapes, plan, views[p], dtype, 1.0, 0.0, tiles=tiles)
