@@ -193,6 +193,94 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
     }
 
 
+def split_leg(torch, F, synth, steps, warmup):
+    """Small-output FP64 shapes (normal inputs, alpha = beta = 1): the split
+    inner dimension and its verified reduction, one fault per 32 tiles."""
+    out = []
+    for (m, n, k) in ((16384, 16384, 256), (16384, 64, 16384), (1024, 1024, 32768)):
+        g = torch.Generator(device="cuda").manual_seed(m + n + k)
+        A = F.colmajor_empty(m, k, torch.float64).normal_(generator=g)
+        B = F.colmajor_empty(k, n, torch.float64).normal_(generator=g)
+        C = F.colmajor_empty(m, n, torch.float64).normal_(generator=g)
+        flops = 2.0 * m * n * k
+        slices = F.query_tiling(F.F64, m, n, k)[3]
+        F.clear_fault_plan()
+        t_ft, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0)), steps, warmup)
+        t_pl, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0, abft=False)),
+                        steps, warmup)
+        tiles = (-(-m // 128)) * (-(-n // 128))
+        plan = synth.additive_plan(synth.rng(50, k, synth.STREAM_PLAN), m, n, k, 128, 128,
+                                   max(1, tiles // 32), synth.log_magnitude((k + 1.0) ** 0.5))
+        F.set_fault_plan(plan)
+        t_inj, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0)), steps, warmup)
+        rb = F.ReportBuffer()
+        F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0), report=rb)
+        v = rb.view()
+        F.clear_fault_plan()
+        out.append({"shape": [m, n, k], "slices": slices,
+                    "tflops": round(flops / (t_ft * 1e-3) / 1e12, 3),
+                    "plain_tflops": round(flops / (t_pl * 1e-3) / 1e12, 3),
+                    "abft_overhead_pct": round(100.0 * (t_ft / t_pl - 1.0), 2),
+                    "injected": {"faults_per_call": len(plan),
+                                 "overhead_pct": round(100.0 * (t_inj / t_pl - 1.0), 2),
+                                 "corrected": int(v.corrected), "detected": int(v.detected)}})
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out
+
+
+def batched_leg(torch, F, synth, np, dtype, steps, warmup):
+    """512 problems, m, n, k log-uniform in [64, 2048], U[-1,1], alpha = 1,
+    beta = 0: one persistent launch replayed from a graph against the loop
+    of per-problem launches; truncated Poisson(1) faults per problem."""
+    shapes = synth.batched_shapes(70, dtype, 512)
+    g = torch.Generator(device="cuda").manual_seed(70 + dtype)
+    tdt = torch.float64 if dtype == F.F64 else torch.bfloat16
+    cdt = torch.float64 if dtype == F.F64 else torch.float32
+    tens, descs, descs_plain = [], [], []
+    flops = 0.0
+    for (m, n, k) in shapes:
+        A = F.colmajor_empty(m, k, cdt).uniform_(-1, 1, generator=g).to(tdt)
+        B = F.colmajor_empty(k, n, cdt).uniform_(-1, 1, generator=g).to(tdt)
+        C = F.colmajor_empty(m, n, cdt).zero_()
+        tens.append((A, B, C))
+        descs.append(F.make_desc(A, B, C, 1.0, 0.0, dtype=dtype))
+        descs_plain.append(F.make_desc(A, B, C, 1.0, 0.0, abft=False, dtype=dtype))
+        flops += 2.0 * m * n * k
+    F.clear_fault_plan()
+    F.gemm_batched(descs)  # tunes the schedule and captures the graph
+    t_b, _ = timed(torch, lambda: F.gemm_batched(descs), steps, warmup)
+    F.gemm_batched(descs_plain)
+    t_bp, _ = timed(torch, lambda: F.gemm_batched(descs_plain), steps, warmup)
+    t_l, _ = timed(torch, lambda: F.gemm_batched(descs, loop=True), max(2, steps // 4), 1)
+    gp = synth.rng(70, dtype, synth.STREAM_PLAN)
+    plan = []
+    for p, (m, n, k) in enumerate(shapes):
+        tiles = (-(-m // 128)) * (-(-n // 128))
+        cnt = min(synth.truncated_poisson(gp, 1.0, 3), tiles)
+        for f in synth.additive_plan(gp, m, n, k, 128, 128, cnt,
+                                     synth.log_magnitude((k / 9.0) ** 0.5, 1.0, 6.0)):
+            f.problem = p
+            plan.append(f)
+    F.set_fault_plan(plan)
+    t_bi, _ = timed(torch, lambda: F.gemm_batched(descs), steps, warmup)
+    reps = [F.ReportBuffer(record_capacity=8, echo_capacity=8) for _ in shapes]
+    F.gemm_batched(descs, reps)
+    views = [r.view() for r in reps]
+    F.clear_fault_plan()
+    return {"problems": len(shapes), "gflop_per_call": round(flops / 1e9, 1),
+            "tflops": round(flops / (t_b * 1e-3) / 1e12, 3),
+            "ms_per_call": round(t_b, 4),
+            "plain_tflops": round(flops / (t_bp * 1e-3) / 1e12, 3),
+            "abft_overhead_pct": round(100.0 * (t_b / t_bp - 1.0), 2),
+            "loop_tflops": round(flops / (t_l * 1e-3) / 1e12, 3),
+            "speedup_vs_loop": round(t_l / t_b, 2),
+            "injected": {"faults_per_call": len(plan),
+                         "overhead_pct": round(100.0 * (t_bi / t_bp - 1.0), 2),
+                         "corrected": sum(int(v.corrected) for v in views),
+                         "detected": sum(int(v.detected) for v in views)}}
+
+
 def profile_run(kind, size, calls=3):
     """A short fixed workload for counter passes: `calls` fault-tolerant
     GEMMs of one format at size^3 (alpha = beta = 1, no report), or, for
@@ -245,6 +333,8 @@ def main():
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-low-precision", action="store_true")
+    ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--profile", choices=["f64", "bf16", "fp8", "copy"])
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -346,6 +436,15 @@ def main():
         lp["bf16"]["speedup_vs_fp64"] = round(lp["bf16"]["tflops"] / value, 2)
         lp["fp8"]["speedup_vs_fp64"] = round(lp["fp8"]["tflops"] / value, 2)
         out["low_precision"] = lp
+    if not args.no_split:
+        out["split_k"] = split_leg(torch, F, synth, args.steps, args.warmup)
+        print("# leg done: split", file=sys.stderr, flush=True)
+    if not args.no_batched:
+        out["batched"] = {}
+        for dt in (F.F64, F.BF16):
+            out["batched"]["f64" if dt == F.F64 else "bf16"] = batched_leg(
+                torch, F, synth, np, dt, args.steps, args.warmup)
+            print("# leg done: batched", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, Cin, m, n, k)
     print(json.dumps(out), flush=True)
