@@ -234,10 +234,25 @@ __device__ __forceinline__ double ft_threshold(double lambda, double u, double s
 
 constexpr double kLambda = 8.0;
 
+// threadIdx.x as a value the compiler cannot tie to earlier reads: indices
+// derived from it after a long loop are formed again from this rather than
+// kept alive (and spilled to scratch) across the loop.
+__device__ __forceinline__ int fresh_tid()
+{
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// Raise a non-negative double kept as bits (the order of the bit patterns is
+// the order of the values).  Many workgroups report into one address; most
+// values do not raise it, so the current value is read first and the atomic
+// is issued only when needed.
 __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *addr, double v)
 {
-    if (v > 0.0)
-        atomicMax(addr, (unsigned long long)__double_as_longlong(v));
+    if (!(v > 0.0)) return;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    if (__atomic_load_n(addr, __ATOMIC_RELAXED) < bits) atomicMax(addr, bits);
 }
 
 __device__ __forceinline__ double flip_bit_f64(double v, int bit)

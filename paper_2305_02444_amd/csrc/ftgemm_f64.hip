@@ -78,6 +78,7 @@ struct Smem {
     double scal[4];        // |x|^2, |y|^2, |A_I|_F^2, |B_J|_F^2
     TileFault faults[kMaxTileFaults];
     int nfaults;
+    double wratio[4];      // largest |d| / tau of the waves that verify
     int nbad_r, nbad_c, ibad, jbad;
 };
 
@@ -366,6 +367,12 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             }
         }
         __syncthreads();
+        // From here on the lane-derived indices are formed again instead of
+        // being carried across the main loop.
+        const int t = fresh_tid(), lane = t & 63, w = t >> 6;
+        const int wm = w & 1, wn = w >> 1, q = lane >> 4, c16 = lane & 15;
+        la.t = t;
+        lb.t = t;
 
         if (!ABFT) {
             // Plain GEMM epilogue: the beta pass and the store.
@@ -541,10 +548,14 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             }
             if (w < 4) {
                 ratio = max64(ratio);
-                if (lane == 0) atomic_max_nonneg(&g.counters->max_ratio_bits, ratio);
+                if (lane == 0) sm.wratio[w] = ratio;
             }
         }
         __syncthreads();
+        if (t == 0)
+            atomic_max_nonneg(&g.counters->max_ratio_bits,
+                              fmax(fmax(sm.wratio[0], sm.wratio[1]),
+                                   fmax(sm.wratio[2], sm.wratio[3])));
 
         const int nr = sm.nbad_r, nc = sm.nbad_c;
         if (nr == 0 && nc == 0) {
@@ -619,6 +630,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
     }
 
     if (ABFT) {
+        const int t = fresh_tid(), lane = t & 63, w = t >> 6;
+        const int wm = w & 1, wn = w >> 1, q = lane >> 4, c16 = lane & 15;
         if (kind == FTGEMM_KIND_CORRECTED) {
             // the owner lane of a corrected element knows its old value
             __syncthreads();

@@ -84,6 +84,7 @@ struct Smem {
     double scal[6];
     TileFault faults[kMaxTileFaults];
     int nfaults;
+    double wratio[4];      // largest |d| / tau of the waves that verify
     int nbad_r, nbad_c, ibad, jbad;
 };
 
@@ -512,6 +513,12 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             }
         }
         __syncthreads();
+        // From here on the lane-derived indices are formed again instead of
+        // being carried across the main loop.
+        const int t = fresh_tid(), lane = t & 63, w = t >> 6;
+        const int wm = w & 1, wn = w >> 1, q = lane >> 4, c16 = lane & 15;
+        la.t = t;
+        lb.t = t;
 
         if (!ABFT) {
 #pragma unroll
@@ -686,10 +693,14 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             }
             if (w < 4) {
                 ratio = max64(ratio);
-                if (lane == 0) atomic_max_nonneg(&g.counters->max_ratio_bits, ratio);
+                if (lane == 0) sm.wratio[w] = ratio;
             }
         }
         __syncthreads();
+        if (t == 0)
+            atomic_max_nonneg(&g.counters->max_ratio_bits,
+                              fmax(fmax(sm.wratio[0], sm.wratio[1]),
+                                   fmax(sm.wratio[2], sm.wratio[3])));
 
         const int nr = sm.nbad_r, nc = sm.nbad_c;
         if (nr == 0 && nc == 0) {
@@ -758,6 +769,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
     }
 
     if (ABFT) {
+        const int t = fresh_tid(), lane = t & 63, w = t >> 6;
+        const int wm = w & 1, wn = w >> 1, q = lane >> 4, c16 = lane & 15;
         if (kind == FTGEMM_KIND_CORRECTED) {
             __syncthreads();
             if (w == owner_wave(first_i, first_j) && lane == owner_lane(first_i, first_j))
