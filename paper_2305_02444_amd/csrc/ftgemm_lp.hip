@@ -56,6 +56,12 @@ struct Elem {
     static constexpr int NKK = BK / KPI;         // MFMAs along the inner step
 };
 
+// LDS rows hold 8 chunks of 16 bytes; chunk c of row r is stored at chunk
+// c ^ ((r / 16) % 8).  With that the transposed 4-byte stores (8 rows apart
+// per lane) spread over all banks instead of hitting 8 lanes per bank,
+// while the 16-byte fragment reads of both formats stay conflict-free.
+__device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 4) & 7); }
+
 struct Stage {
     unsigned char A[TM][SROW];  // A tile, [i][inner bytes]
     unsigned char B[TN][SROW];  // B tile, [j][inner bytes]
@@ -261,11 +267,12 @@ struct LpLoader {
         if (kInner) {
 #pragma unroll
             for (int r = 0; r < 2; ++r)
-                *(i4v *)&dst[outer(r)][E::EB * p0()] = w[r];
+                *(i4v *)&dst[outer(r)][16 * swz(outer(r), t & 7)] = w[r];
         } else {
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                *(int *)&dst[outer(e)][E::EB * p0()] = w[e >> 2][e & 3];
+                *(int *)&dst[outer(e)][16 * swz(outer(e), t >> 6) + 4 * ((t >> 4) & 3)] =
+                    w[e >> 2][e & 3];
         }
     }
     // value of inner e (0 .. kNP-1) at outer slot r (0 .. kOuter-1)
@@ -446,15 +453,16 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 if (s + 1 < nsteps) load(s + 1);
 #pragma unroll
                 for (int kk = 0; kk < E::NKK; ++kk) {
-                    const int kb = kk * E::KPI * E::EB;  // byte offset of this MFMA's inner range
                     if (!FP8) {
                         bf8v fa[4], fb[2];
 #pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
-                            fa[mi] = *(const bf8v *)&sm.u.st[buf].A[wm * 64 + 16 * mi + c16][kb + 16 * q];
+                            fa[mi] = *(const bf8v *)&sm.u.st[buf].A[wm * 64 + 16 * mi + c16]
+                                                                    [16 * swz(wm * 64 + 16 * mi + c16, 4 * kk + q)];
 #pragma unroll
                         for (int ni = 0; ni < 2; ++ni)
-                            fb[ni] = *(const bf8v *)&sm.u.st[buf].B[wn * 32 + 16 * ni + c16][kb + 16 * q];
+                            fb[ni] = *(const bf8v *)&sm.u.st[buf].B[wn * 32 + 16 * ni + c16]
+                                                                    [16 * swz(wn * 32 + 16 * ni + c16, 4 * kk + q)];
 #pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -465,10 +473,20 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                         i8v fa[4], fb[2];
 #pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
-                            fa[mi] = *(const i8v *)&sm.u.st[buf].A[wm * 64 + 16 * mi + c16][kb + 32 * q];
+                        {
+                            const int r = wm * 64 + 16 * mi + c16;
+                            const i4v lo = *(const i4v *)&sm.u.st[buf].A[r][16 * swz(r, 2 * q)];
+                            const i4v hi = *(const i4v *)&sm.u.st[buf].A[r][16 * swz(r, 2 * q + 1)];
+                            fa[mi] = (i8v){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+                        }
 #pragma unroll
                         for (int ni = 0; ni < 2; ++ni)
-                            fb[ni] = *(const i8v *)&sm.u.st[buf].B[wn * 32 + 16 * ni + c16][kb + 32 * q];
+                        {
+                            const int r = wn * 32 + 16 * ni + c16;
+                            const i4v lo = *(const i4v *)&sm.u.st[buf].B[r][16 * swz(r, 2 * q)];
+                            const i4v hi = *(const i4v *)&sm.u.st[buf].B[r][16 * swz(r, 2 * q + 1)];
+                            fb[ni] = (i8v){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+                        }
 #pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
