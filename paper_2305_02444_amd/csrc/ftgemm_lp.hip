@@ -62,9 +62,16 @@ struct Elem {
 // while the 16-byte fragment reads of both formats stay conflict-free.
 __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 4) & 7); }
 
+// BF16 encodes on the matrix cores: each step's operand checksums x (of the
+// A tile) and y (of the B tile), split exactly into three BF16 parts, are
+// kept as XR extra rows of the staged tiles, and every wave multiplies them
+// with its fragments of the other operand (x . B and A . y, accumulated in
+// FP32 like the product).
+constexpr int XR = 16;  // extra rows (3 parts, the rest zero)
+
 struct Stage {
-    unsigned char A[TM][SROW];  // A tile, [i][inner bytes]
-    unsigned char B[TN][SROW];  // B tile, [j][inner bytes]
+    unsigned char A[TM + XR][SROW];  // A tile, [i][inner bytes]; rows TM.. x parts
+    unsigned char B[TN + XR][SROW];  // B tile, [j][inner bytes]; rows TN.. y parts
 };
 
 struct Epi {
@@ -78,9 +85,13 @@ struct Epi {
     double d_row[TM], d_col[TN];
 };
 
-struct Smem {
+// NS staged steps: 2, or 3 when the checksum products trail the main
+// product by one step (BF16 with fault tolerance), so the stage a trailing
+// product reads is not the one being refilled.
+template <int NS>
+struct SmemT {
     union {
-        Stage st[2];
+        Stage st[NS];
         Epi epi;
     } u;
     float xs[2][128][NW];  // [buffer][p][partial]: column sums of the A tile
@@ -93,6 +104,8 @@ struct Smem {
     double wratio[4];      // largest |d| / tau of the waves that verify
     int nbad_r, nbad_c, ibad, jbad;
 };
+template <bool FP8, bool ABFT>
+using Smem = SmemT<(!FP8 && ABFT) ? 3 : 2>;
 
 // E4M3 byte b (a constant after unrolling) of a dword, exactly widened
 __device__ __forceinline__ float fp8_byte(int d, int b)
@@ -285,21 +298,59 @@ struct LpLoader {
     // dst[p][slot]: complete (otherwise, slot 0, the 16 lanes of a row share
     // p) or one partial per wave (kInner, slot = wave, over the 8 lanes
     // sharing the inner chunk).
-    __device__ __forceinline__ void sum_to(float (*dst)[NW]) const
+    // (kNorms: the squared norms of this thread's outer indices are
+    // accumulated in the same pass.)
+    template <bool kNorms = false>
+    __device__ __forceinline__ void sum_to(float (*dst)[NW], float (&nrm)[kOuter]) const
     {
+        float v[kNP];
 #pragma unroll
         for (int e = 0; e < kNP; ++e) {
             float s = 0.0f;
 #pragma unroll
-            for (int r = 0; r < kOuter; ++r) s += val(r, e);
-            if (kInner) {
-                s = dpp_f32<0x128>(s) + s;  // row_ror:8, lanes l and l ^ 8
-                s = pair_sum32f(pair_sum16f(s));
-                if ((t & 63) < 8) dst[p0() + e][t >> 6] = s;
-            } else {
-                s = sum16f(s);
+            for (int r = 0; r < kOuter; ++r) {
+                const float x = val(r, e);
+                s += x;
+                if (kNorms) nrm[r] = fmaf(x, x, nrm[r]);
+            }
+            v[e] = s;
+        }
+        if constexpr (!kInner) {
+#pragma unroll
+            for (int e = 0; e < kNP; ++e) {
+                const float s = sum16f(v[e]);
                 if ((t & 15) == 0) dst[p0() + e][0] = s;
             }
+        } else {
+        // The 8 lanes holding this inner chunk (lane bits 3..5) reduce kNP
+        // values by halving: each exchange step sends half of the values to
+        // the partner and keeps the other half, so every lane ends with
+        // kNP / 8 complete sums -- for inner index p0 + e_lane + i, e_lane =
+        // (kNP / 2) b5 + (kNP / 4) b4 + (kNP / 8) b3.
+        constexpr int H1 = kNP / 2, H2 = kNP / 4, H3 = kNP / 8;
+        float u[H1], z[H2], f[H3];
+#pragma unroll
+        for (int i = 0; i < H1; ++i) {  // lanes l, l ^ 32
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v[i]),
+                                                            __float_as_int(v[i + H1]), false, false);
+            u[i] = __int_as_float(r[0]) + __int_as_float(r[1]);
+        }
+#pragma unroll
+        for (int i = 0; i < H2; ++i) {  // lanes l, l ^ 16
+            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(u[i]),
+                                                            __float_as_int(u[i + H2]), false, false);
+            z[i] = __int_as_float(r[0]) + __int_as_float(r[1]);
+        }
+        const bool b3 = (t & 8) != 0;
+#pragma unroll
+        for (int i = 0; i < H3; ++i) {  // lanes l, l ^ 8 (row_ror:8)
+            const float keep = b3 ? z[i + H3] : z[i];
+            const float send = b3 ? z[i] : z[i + H3];
+            f[i] = keep + dpp_f32<0x128>(send);
+        }
+        const int e0 = ((t & 32) ? H1 : 0) + ((t & 16) ? H2 : 0) + (b3 ? H3 : 0);
+#pragma unroll
+        for (int i = 0; i < H3; ++i) dst[p0() + e0 + i][t >> 6] = f[i];
         }
     }
     // Encoded checksum (with the other operand's checksum v, indexed like
@@ -341,6 +392,22 @@ struct LpLoader {
     __device__ __forceinline__ bool first_of_p() const { return kInner ? t < 8 : (t & 15) == 0; }
 };
 
+// v as hi + mid + lo, three BF16 values (exact: each part takes the next
+// 8 significant bits of the FP32 value), stored as element p of the extra
+// rows first_row .. first_row + 2 of a staged tile.
+__device__ __forceinline__ void put_parts(unsigned char (*tile)[SROW], int first_row, int p,
+                                          float v)
+{
+    float r = v;
+#pragma unroll
+    for (int part = 0; part < 3; ++part) {
+        const __bf16 h = (__bf16)r;
+        r -= (float)h;
+        const int row = first_row + part;
+        *(__bf16 *)&tile[row][16 * swz(row, p >> 3) + 2 * (p & 7)] = h;
+    }
+}
+
 template <int kParts>
 __device__ __forceinline__ float gather_lp(const float (*src)[NW], int p)
 {
@@ -360,9 +427,13 @@ __device__ __forceinline__ int owner_reg(int row, int col)
 }
 
 template <bool FP8, bool TA, bool TB, bool ABFT>
-__device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
+__device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> &sm)
 {
     using E = Elem<FP8>;
+    constexpr bool kMma = !FP8;  // BF16: encoded checksums on the matrix cores
+    // the checksum products of step s run during step s + 1, from a third stage
+    constexpr bool kLag = kMma && ABFT;
+    constexpr int NS = kLag ? 3 : 2;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w & 1, wn = w >> 1;
     const int q = lane >> 4, c16 = lane & 15;
@@ -400,6 +471,19 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
     int kind = 0, first_nr = 0, first_nc = 0, first_i = -1, first_j = -1;
     double rec_before = 0, rec_after = 0;
 
+    // Checksum products of a staged step (BF16): the x-part rows times this
+    // wave's B block 16 (2 wn + wm) .., this wave's A block 16 (4 wm + wn) ..
+    // times the y-part rows.
+    auto check_products = [&](const Stage &st, int kk, f4 &acc_r, f4 &acc_c) {
+        const int rb = 16 * (4 * wm + wn) + c16, cb = 16 * (2 * wn + wm) + c16;
+        const bf8v fxa = *(const bf8v *)&st.A[TM + c16][16 * swz(TM + c16, 4 * kk + q)];
+        const bf8v fyb = *(const bf8v *)&st.B[TN + c16][16 * swz(TN + c16, 4 * kk + q)];
+        const bf8v fra = *(const bf8v *)&st.A[rb][16 * swz(rb, 4 * kk + q)];
+        const bf8v fcb = *(const bf8v *)&st.B[cb][16 * swz(cb, 4 * kk + q)];
+        acc_r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxa, fcb, acc_r, 0, 0, 0);
+        acc_c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fra, fyb, acc_c, 0, 0, 0);
+    };
+
     f4 acc[4][2];
 #pragma unroll 1
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -413,11 +497,25 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
         float enc_b[LB::kOuter] = {}, nrm_b[LB::kOuter] = {};
         float vx = 0.0f, vy = 0.0f, amx_a = 0.0f, amx_b = 0.0f;
         float yv[LA::kNP], xv[LB::kNP];  // y at the A loader's p, x at the B loader's
+        f4 acc_r = (f4){0.0f, 0.0f, 0.0f, 0.0f};  // x-part rows times this wave's B block
+        f4 acc_c = (f4){0.0f, 0.0f, 0.0f, 0.0f};  // this wave's A block times the y parts
+
+        if (ABFT && kMma) {
+            // clear the extra rows of both stages (the epilogue reuses the
+            // memory); done before step 0's barrier
+            constexpr int kChunks = NS * 2 * XR * (SROW / 16);
+            for (int c = t; c < kChunks; c += NT) {
+                const int st = c / (2 * XR * (SROW / 16)), rem = c % (2 * XR * (SROW / 16));
+                const int op = rem / (XR * (SROW / 16)), rr = rem % (XR * (SROW / 16));
+                unsigned char(*dst)[SROW] = op ? sm.u.st[st].B : sm.u.st[st].A;
+                *(i4v *)&dst[TM + rr / (SROW / 16)][16 * (rr % (SROW / 16))] = (i4v){0, 0, 0, 0};
+            }
+        }
 
         load(0);
         if (ABFT) {
-            la.sum_to(sm.xs[0]);
-            lb.sum_to(sm.ys[0]);
+            la.template sum_to<kMma>(sm.xs[0], nrm_a);
+            lb.template sum_to<kMma>(sm.ys[0], nrm_b);
         }
         int s = 0;
 #pragma unroll 1
@@ -430,11 +528,25 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 }
 #pragma unroll 1
             for (; s <= stop; ++s) {
-                const int buf = s & 1;
-                la.store(sm.u.st[buf].A);
-                lb.store(sm.u.st[buf].B);
+                const int buf = s & 1;                          // checksum buffers
+                const int stg = kLag ? s % 3 : buf;             // staged step s
+                const int pst = kLag ? (s + 2) % 3 : buf;       // staged step s - 1
+                la.store(sm.u.st[stg].A);
+                lb.store(sm.u.st[stg].B);
                 __syncthreads();
-                if (ABFT) {
+                if (ABFT && kMma) {
+                    // x_p, y_p of step s are complete: their parts go to the
+                    // extra rows, for the checksum products of step s (run
+                    // during step s + 1, after its barrier)
+                    if (t < E::BK) {
+                        const float xp = gather_lp<LA::kParts>(sm.xs[buf], t);
+                        const float yp = gather_lp<LB::kParts>(sm.ys[buf], t);
+                        vx = fmaf(xp, xp, vx);
+                        vy = fmaf(yp, yp, vy);
+                        put_parts(sm.u.st[stg].A, TM, t, xp);
+                        put_parts(sm.u.st[stg].B, TN, t, yp);
+                    }
+                } else if (ABFT) {
                     // x_p, y_p of step s are complete: the encoded checksums
                     // and norms of step s, before the registers take step s + 1
 #pragma unroll
@@ -457,11 +569,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                         bf8v fa[4], fb[2];
 #pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
-                            fa[mi] = *(const bf8v *)&sm.u.st[buf].A[wm * 64 + 16 * mi + c16]
+                            fa[mi] = *(const bf8v *)&sm.u.st[stg].A[wm * 64 + 16 * mi + c16]
                                                                     [16 * swz(wm * 64 + 16 * mi + c16, 4 * kk + q)];
 #pragma unroll
                         for (int ni = 0; ni < 2; ++ni)
-                            fb[ni] = *(const bf8v *)&sm.u.st[buf].B[wn * 32 + 16 * ni + c16]
+                            fb[ni] = *(const bf8v *)&sm.u.st[stg].B[wn * 32 + 16 * ni + c16]
                                                                     [16 * swz(wn * 32 + 16 * ni + c16, 4 * kk + q)];
 #pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
@@ -469,22 +581,23 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                             for (int ni = 0; ni < 2; ++ni)
                                 acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                                     fa[mi], fb[ni], acc[mi][ni], 0, 0, 0);
+                        if (kLag && s > 0) check_products(sm.u.st[pst], kk, acc_r, acc_c);
                     } else {
                         i8v fa[4], fb[2];
 #pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
                         {
                             const int r = wm * 64 + 16 * mi + c16;
-                            const i4v lo = *(const i4v *)&sm.u.st[buf].A[r][16 * swz(r, 2 * q)];
-                            const i4v hi = *(const i4v *)&sm.u.st[buf].A[r][16 * swz(r, 2 * q + 1)];
+                            const i4v lo = *(const i4v *)&sm.u.st[stg].A[r][16 * swz(r, 2 * q)];
+                            const i4v hi = *(const i4v *)&sm.u.st[stg].A[r][16 * swz(r, 2 * q + 1)];
                             fa[mi] = (i8v){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
                         }
 #pragma unroll
                         for (int ni = 0; ni < 2; ++ni)
                         {
                             const int r = wn * 32 + 16 * ni + c16;
-                            const i4v lo = *(const i4v *)&sm.u.st[buf].B[r][16 * swz(r, 2 * q)];
-                            const i4v hi = *(const i4v *)&sm.u.st[buf].B[r][16 * swz(r, 2 * q + 1)];
+                            const i4v lo = *(const i4v *)&sm.u.st[stg].B[r][16 * swz(r, 2 * q)];
+                            const i4v hi = *(const i4v *)&sm.u.st[stg].B[r][16 * swz(r, 2 * q + 1)];
                             fb[ni] = (i8v){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
                         }
 #pragma unroll
@@ -497,8 +610,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 }
                 if (ABFT && s + 1 < nsteps) {
                     // operand checksums of step s + 1, published before its barrier
-                    la.sum_to(sm.xs[buf ^ 1]);
-                    lb.sum_to(sm.ys[buf ^ 1]);
+                    la.template sum_to<kMma>(sm.xs[buf ^ 1], nrm_a);
+                    lb.template sum_to<kMma>(sm.ys[buf ^ 1], nrm_b);
                 }
             }
             if (ABFT && faults_on) {
@@ -531,6 +644,14 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             }
         }
         __syncthreads();
+        if (kLag) {
+            // the last step's checksum products (its parts are now visible);
+            // the epilogue then reuses the stages' memory
+#pragma unroll
+            for (int kk = 0; kk < E::NKK; ++kk)
+                check_products(sm.u.st[(nsteps - 1) % 3], kk, acc_r, acc_c);
+            __syncthreads();
+        }
         // From here on the lane-derived indices are formed again instead of
         // being carried across the main loop.
         const int t = fresh_tid(), lane = t & 63, w = t >> 6;
@@ -556,14 +677,28 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
             return;
         }
 
-        la.partials_to(enc_a, sm.u.epi.enc_row);
+        if (kMma) {
+            // encoded checksums from the matrix cores: row parts (lanes with
+            // column 0..2 of the A . y block), column sums of the x-part rows
+            if (c16 < 3)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sm.u.epi.enc_row[c16][16 * (4 * wm + wn) + 4 * q + r] = (double)acc_c[r];
+            if (q == 0)
+                sm.u.epi.enc_col[0][16 * (2 * wn + wm) + c16] =
+                    ((double)acc_r[0] + (double)acc_r[1]) + (double)acc_r[2];
+        } else {
+            la.partials_to(enc_a, sm.u.epi.enc_row);
+            lb.partials_to(enc_b, sm.u.epi.enc_col);
+        }
         la.partials_to(nrm_a, sm.u.epi.nrm_row);
-        lb.partials_to(enc_b, sm.u.epi.enc_col);
         lb.partials_to(nrm_b, sm.u.epi.nrm_col);
         // |x|^2 (B loader) and |y|^2 (A loader): one thread per group of p
         {
-            const double sx = sum64(lb.first_of_p() ? (double)vx : 0.0);
-            const double sy = sum64(la.first_of_p() ? (double)vy : 0.0);
+            const bool hx = kMma ? t < E::BK : lb.first_of_p();
+            const bool hy = kMma ? t < E::BK : la.first_of_p();
+            const double sx = sum64(hx ? (double)vx : 0.0);
+            const double sy = sum64(hy ? (double)vy : 0.0);
             const double ma = FP8 ? max64((double)amx_a) : 0.0;
             const double mb = FP8 ? max64((double)amx_b) : 0.0;
             if (lane == 0) {
@@ -620,13 +755,25 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
         if (is_row) {
             double e = 0, nr = 0;
 #pragma unroll
-            for (int v = 0; v < LA::kOuterParts; ++v) { e += sm.u.epi.enc_row[v][x]; nr += sm.u.epi.nrm_row[v][x]; }
+            for (int v = 0; v < LA::kOuterParts; ++v) nr += sm.u.epi.nrm_row[v][x];
+            if (kMma) {
+                e = (sm.u.epi.enc_row[0][x] + sm.u.epi.enc_row[1][x]) + sm.u.epi.enc_row[2][x];
+            } else {
+#pragma unroll
+                for (int v = 0; v < LA::kOuterParts; ++v) e += sm.u.epi.enc_row[v][x];
+            }
             nrm2 = nr;
             sm.u.epi.fin_row[x] = e;
         } else if (is_col) {
             double e = 0, nr = 0;
 #pragma unroll
-            for (int v = 0; v < LB::kOuterParts; ++v) { e += sm.u.epi.enc_col[v][x]; nr += sm.u.epi.nrm_col[v][x]; }
+            for (int v = 0; v < LB::kOuterParts; ++v) nr += sm.u.epi.nrm_col[v][x];
+            if (kMma) {
+                e = sm.u.epi.enc_col[0][x];
+            } else {
+#pragma unroll
+                for (int v = 0; v < LB::kOuterParts; ++v) e += sm.u.epi.enc_col[v][x];
+            }
             nrm2 = nr;
             sm.u.epi.fin_col[x] = e;
         }
@@ -848,7 +995,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
 template <bool FP8, bool TA, bool TB, bool ABFT>
 __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
 {
-    __shared__ Smem sm;
+    __shared__ Smem<FP8, ABFT> sm;
     int tm_, tn_;
     map_tile(blockIdx.x, g.tiles_m, g.tiles_n, tm_, tn_);
     tile<FP8, TA, TB, ABFT>(g, tm_, tn_, sm);
@@ -861,7 +1008,7 @@ __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
 template <bool FP8, bool TA, bool TB, bool ABFT>
 __global__ __launch_bounds__(NT, 2) void batched_kernel(BatchArgs b)
 {
-    __shared__ Smem sm;
+    __shared__ Smem<FP8, ABFT> sm;
     __shared__ int next;
     const int first = (int)(blockIdx.x % (unsigned)b.nqueues);
     for (int qi = 0; qi < b.nqueues; ++qi) {
