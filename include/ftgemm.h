@@ -26,8 +26,8 @@
  *   - A, B and C are device pointers owned by the caller; C is read (unless
  *     beta == 0) and written.  Nothing is retained after the call returns.
  *   - Calls are asynchronous on `stream` (a hipStream_t; NULL is the
- *     default stream).  A report, when requested, is complete once the
- *     stream has been synchronised.
+ *     default stream), except that a call asked for a report waits for the
+ *     stream before it returns, the report then being complete.
  *   - Arguments are checked on the host before any HIP call.  An invalid
  *     one returns FTGEMM_ERR_INVALID_ARG and ftgemm_last_invalid_arg()
  *     gives its 1-based BLAS position (1 transA, 2 transB, 3 m, 4 n, 5 k,
@@ -172,9 +172,18 @@ ftgemm_status ftgemm_gemm_ex(const ftgemm_gemm_desc *desc, ftgemm_report *report
 
 /* `count` independent GEMMs (Section 2.3's independent parts, taken to
  * whole problems), each with its own checksums, in one persistent launch
- * replayed from a captured HIP graph.  problems: host array of `count`
- * descriptors (device data pointers); all must share dtype and abft.
- * reports: NULL or a host array of `count` reports, one per problem. */
+ * replayed from a captured HIP graph.
+ *   problems: host array of `count` descriptors (device data pointers); all
+ *     must share dtype, abft and the two transposes (otherwise
+ *     FTGEMM_ERR_UNSUPPORTED).  An invalid descriptor returns
+ *     FTGEMM_ERR_INVALID_ARG with the position of its bad field.
+ *   reports: NULL or a host array of `count` reports, one per problem; the
+ *     fault plan's `problem` field is the index in `problems`.
+ * The work order is tuned on the first call with a batch of a given shape
+ * when every beta is 0 (C is then write-only, so the trial runs are
+ * harmless); later calls with that shape reuse it.  The device arrays of
+ * per-problem arguments and the captured graph belong to the library and
+ * are reused while the batch's size and the plan stay the same. */
 ftgemm_status ftgemm_gemm_batched(int32_t count, const ftgemm_gemm_desc *problems,
                                   ftgemm_report *reports, void *stream);
 
@@ -188,8 +197,12 @@ ftgemm_status ftgemm_gemm_batched_loop(int32_t count, const ftgemm_gemm_desc *pr
 ftgemm_status ftgemm_set_fault_plan(const ftgemm_injection *plan, int32_t n);
 
 /* Verification tile (tm x tn), inner step bk and split of the inner
- * dimension chosen for a problem.  split_k > 1 means the inner dimension is
- * cut into split_k slices, each verified as its own tile. */
+ * dimension chosen for a problem.  split_k > 1 (FP64 only) means the inner
+ * dimension is cut into split_k slices run in one launch: each slice
+ * verifies and corrects its partial product as its own tile (its faults are
+ * those whose k_index falls in it; records carry the tile, once per slice
+ * that found something), and a verified reduction then forms C.  The
+ * report's tiles_verified counts split_k + 1 verifications per tile. */
 ftgemm_status ftgemm_query_tiling(ftgemm_dtype dtype, int64_t m, int64_t n, int64_t k,
                                   int32_t *tm, int32_t *tn, int32_t *bk,
                                   int32_t *split_k);

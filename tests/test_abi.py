@@ -77,6 +77,27 @@ def test_query_tiling():
     tm, tn, bk, sk = F.query_tiling(F.F64, 256, 256, 256)
     assert (tm, tn, sk) == (128, 128, 1) and bk in (16, 32)
     assert F.lib().ftgemm_query_tiling(9, 1, 1, 1, None, None, None, None) == F.ERR_INVALID_ARG
+    # low precision: 128 bytes of the inner dimension per row per step, no split
+    assert F.query_tiling(F.BF16, 8192, 8192, 8192) == (128, 128, 64, 1)
+    assert F.query_tiling(F.FP8_E4M3, 8192, 8192, 8192) == (128, 128, 128, 1)
+    assert F.query_tiling(F.BF16, 1024, 1024, 32768)[3] == 1
+
+
+def test_split_choice():
+    """FP64 splits the inner dimension only when the output has fewer tiles
+    than compute units and the inner dimension is long: slices of at least
+    8 steps, at most 16, aimed at 512 workgroups."""
+    bk = F.query_tiling(F.F64, 64, 64, 64)[2]
+    cases = {(8192, 8192, 8192): 1,           # 4096 tiles
+             (16384, 16384, 256): 1,          # 16384 tiles
+             (1024, 1024, 32768): 8,          # 64 tiles -> 512 workgroups
+             (16384, 64, 16384): 4,           # 128 tiles
+             (256, 256, 256): 1,              # inner dimension too short
+             (128, 128, 32 * bk): 4,          # 1 tile, 32 steps -> 4 slices of 8
+             (128, 128, 1 << 20): 16}         # 1 tile, capped at 16 slices
+    for (m, n, k), want in cases.items():
+        assert F.query_tiling(F.F64, m, n, k)[3] == want, (m, n, k)
+
 
 
 def test_status_strings():
