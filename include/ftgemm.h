@@ -197,7 +197,11 @@ ftgemm_status ftgemm_gemm_batched_loop(int32_t count, const ftgemm_gemm_desc *pr
 ftgemm_status ftgemm_set_fault_plan(const ftgemm_injection *plan, int32_t n);
 
 /* Verification tile (tm x tn), inner step bk and split of the inner
- * dimension chosen for a problem.  split_k > 1 (FP64 only) means the inner
+ * dimension chosen for a fault-tolerant call on a problem: FP64 128 x 128;
+ * BF16 256 x 128 once the output holds at least 256 such tiles, else
+ * 128 x 128; FP8 128 x 128 (a call without fault tolerance may use 256-row
+ * tiles there too; nothing is verified then).  Batches use 128 x 128 for
+ * every low-precision problem.  split_k > 1 (FP64 only) means the inner
  * dimension is cut into split_k slices run in one launch: each slice
  * verifies and corrects its partial product as its own tile (its faults are
  * those whose k_index falls in it; records carry the tile, once per slice

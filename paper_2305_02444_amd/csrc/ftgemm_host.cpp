@@ -320,7 +320,7 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
     if (d.dtype == FTGEMM_F64)
         ftg::tiling_f64(&tm, &tn, &bk);
     else
-        ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, &tm, &tn, &bk);
+        ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft != 0, d.m, d.n, false, &tm, &tn, &bk);
     GemmArgs g = base_args(d, tm, tn);
     int64_t slice_k = d.k;
     const int nslices =
@@ -370,7 +370,7 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
             HIP_TRY(ftg::launch_splitk_reduce(r, d.abft != 0, stream));
         }
     } else
-        HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft != 0, stream));
+        HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft != 0, tm, stream));
     if (rep && d.abft) {
         HIP_TRY(hipMemcpyAsync(ws->h_counters, ws->counters, sizeof(DevCounters),
                                hipMemcpyDeviceToHost, stream));
@@ -567,7 +567,7 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
     if (d0.dtype == FTGEMM_F64)
         ftg::tiling_f64(&tm, &tn, &bk);
     else
-        ftg::tiling_lp(d0.dtype == FTGEMM_FP8_E4M3, &tm, &tn, &bk);
+        ftg::tiling_lp(d0.dtype == FTGEMM_FP8_E4M3, d0.abft != 0, 0, 0, true, &tm, &tn, &bk);
     std::vector<ftg::GemmArgs> probs(count);
     std::vector<int> live;
     uint64_t sig = 0xcbf29ce484222325ull;
@@ -775,7 +775,7 @@ ftgemm_status ftgemm_query_tiling(ftgemm_dtype dtype, int64_t m, int64_t n, int6
         ftg::tiling_f64(&a, &b, &c);
         s = choose_split(m, n, k, a, b, c, &slice_k);
     } else {
-        ftg::tiling_lp(dtype == FTGEMM_FP8_E4M3, &a, &b, &c);
+        ftg::tiling_lp(dtype == FTGEMM_FP8_E4M3, true, m, n, false, &a, &b, &c);
     }
     *tm = a;
     *tn = b;

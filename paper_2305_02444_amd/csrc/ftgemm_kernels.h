@@ -11,11 +11,15 @@ namespace ftg {
 hipError_t launch_f64(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream);
 void tiling_f64(int *tm, int *tn, int *bk);
 
-// BF16 / FP8 E4M3 tile kernel (FP32 accumulation and output, one 128 x 128
-// output tile per workgroup).
-hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, bool abft,
+// BF16 / FP8 E4M3 tile kernel (FP32 accumulation and output, one tm x 128
+// output tile per workgroup, tm = 128 or 256 as tiling_lp chose).
+hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, bool abft, int tm,
                      hipStream_t stream);
-void tiling_lp(bool fp8, int *tm, int *tn, int *bk);
+// Tile of an m x n low-precision output, with or without fault tolerance
+// (batched: the batched kernel's tile).
+constexpr int64_t kLargeTileMin = 256;  // 256-row tiles from this many tiles on
+void tiling_lp(bool fp8, bool abft, int64_t m, int64_t n, bool batched, int *tm, int *tn,
+               int *bk);
 
 // Verified reduction of a split inner dimension (FP64): C = alpha * sum_s
 // W_s + beta * C, checked against the slices' encoded checksums.

@@ -2,8 +2,9 @@
 // for gfx950: matrix-core products accumulated in FP32, FP32 checksums,
 // verification, location and correction in FP64, FP32 output.
 //
-// One workgroup (8 waves, 2 x 4) owns a 128 x 128 output tile and walks the
-// inner dimension in steps of 128 bytes per row (64 BF16 or 128 FP8 values).
+// One workgroup of 8 waves owns a BM x 128 output tile (BM = 128: waves 2 x 4
+// of 64 x 32; BM = 256: waves 4 x 2 of 64 x 64) and walks the inner dimension
+// in steps of 128 bytes per row (64 BF16 or 128 FP8 values).
 // Both operand tiles live in LDS with the inner index contiguous, the layout
 // the MFMA operands want: v_mfma_f32_16x16x32_bf16 and
 // v_mfma_f32_16x16x128_f8f6f4 (E4M3, unit block scales) read 8 / 32
@@ -24,9 +25,23 @@
 namespace ftg {
 namespace lp {
 
-constexpr int TM = 128, TN = 128, BKB = 128;  // tile, inner step in bytes per row
-constexpr int WM = 2, WN = 4, NW = WM * WN, NT = 64 * NW;
-constexpr int SROW = BKB + 16;                // LDS row stride in bytes
+constexpr int TN = 128, BKB = 128;  // tile columns, inner step in bytes per row
+constexpr int NW = 8, NT = 64 * NW;
+constexpr int SROW = BKB + 16;      // LDS row stride in bytes
+
+// Wave grid of a BM x TN tile: wave w = wm + WM wn holds rows 64 wm .. +63
+// and columns WC wn .. +WC-1.
+template <int BM>
+struct Geo {
+    static constexpr int WM = BM / 64;          // waves along the rows
+    static constexpr int WN = NW / WM;          // waves along the columns
+    static constexpr int WC = TN / WN;          // columns per wave
+    static constexpr int NI = WC / 16;          // 16-column blocks per wave
+    static constexpr int NA = BM / (16 * NW);   // 16-row A blocks per wave in A . y
+    static constexpr int NREG = 16 * NI;        // accumulator values per lane
+    static constexpr int kRW = BM / 64;         // waves that verify rows
+    static constexpr int kVW = kRW + TN / 64;   // ... and columns after them
+};
 constexpr double U = 5.9604644775390625e-08;  // 2^-24, unit roundoff of FP32
 // The FP8 matrix instructions do not add their products exactly: products
 // are summed in groups of 8 consecutive inner indices, each cut (toward
@@ -43,9 +58,8 @@ typedef int i8v __attribute__((ext_vector_type(8)));
 typedef int i4v __attribute__((ext_vector_type(4)));
 
 // Result layout of both MFMAs (measured on gfx950): lane l = 16 q + c,
-// register r holds D[4 q + r][c].  Wave w = wm + 2 wn holds rows
-// 64 wm .. +63 and columns 32 wn .. +31 as acc[mi][ni][r] =
-// C(64 wm + 16 mi + 4 q + r, 32 wn + 16 ni + c).
+// register r holds D[4 q + r][c].  Wave (wm, wn) holds its block as
+// acc[mi][ni][r] = C(64 wm + 16 mi + 4 q + r, WC wn + 16 ni + c).
 
 template <bool FP8>
 struct Elem {
@@ -69,43 +83,46 @@ __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >>
 // FP32 like the product).
 constexpr int XR = 16;  // extra rows (3 parts, the rest zero)
 
+template <int BM>
 struct Stage {
-    unsigned char A[TM + XR][SROW];  // A tile, [i][inner bytes]; rows TM.. x parts
+    unsigned char A[BM + XR][SROW];  // A tile, [i][inner bytes]; rows BM.. x parts
     unsigned char B[TN + XR][SROW];  // B tile, [j][inner bytes]; rows TN.. y parts
 };
 
+template <int BM>
 struct Epi {
-    double ref_row[WN][TM], ref_col[WM][TN];
-    double cin_row[WN][TM], cin_col[WM][TN];
-    double cin2_row[WN][TM], cin2_col[WM][TN];
-    double enc_row[NW][TM], enc_col[NW][TN];
-    double nrm_row[NW][TM], nrm_col[NW][TN];
-    double fin_row[TM], fin_col[TN];
-    double tau_row[TM], tau_col[TN];
-    double d_row[TM], d_col[TN];
+    using G = Geo<BM>;
+    double ref_row[G::WN][BM], ref_col[G::WM][TN];
+    double cin_row[G::WN][BM], cin_col[G::WM][TN];
+    double cin2_row[G::WN][BM], cin2_col[G::WM][TN];
+    double enc_row[NW][BM], enc_col[NW][TN];
+    double nrm_row[NW][BM], nrm_col[NW][TN];
+    double fin_row[BM], fin_col[TN];
+    double tau_row[BM], tau_col[TN];
+    double d_row[BM], d_col[TN];
 };
 
-// NS staged steps: 2, or 3 when the checksum products trail the main
-// product by one step (BF16 with fault tolerance), so the stage a trailing
-// product reads is not the one being refilled.
-template <int NS>
-struct SmemT {
+// Two staged steps.  (The BF16 checksum products trail the main product by
+// one step; the fragments of the main rows they need are kept in registers
+// from the step itself, and their extra rows are only rewritten after the
+// next barrier, so a third stage is not needed.)
+template <int BM>
+struct Smem {
     union {
-        Stage st[NS];
-        Epi epi;
+        Stage<BM> st[2];
+        Epi<BM> epi;
     } u;
     float xs[2][128][NW];  // [buffer][p][partial]: column sums of the A tile
     float ys[2][128][NW];  // [buffer][p][partial]: row sums of the B tile
+    float xc[128], yc[128];  // FP8: the step's x_p, y_p, combined once
     double red[NW][2];
     double wsum[NW][5];    // per wave: |x|^2, |y|^2, row / column norms^2, max|A|, max|B|
     double scal[6];
     TileFault faults[kMaxTileFaults];
     int nfaults;
-    double wratio[4];      // largest |d| / tau of the waves that verify
+    double wratio[NW];     // largest |d| / tau of the waves that verify
     int nbad_r, nbad_c, ibad, jbad;
 };
-template <bool FP8, bool ABFT>
-using Smem = SmemT<(!FP8 && ABFT) ? 3 : 2>;
 
 // E4M3 byte b (a constant after unrolling) of a dword, exactly widened
 __device__ __forceinline__ float fp8_byte(int d, int b)
@@ -133,27 +150,31 @@ __device__ __forceinline__ float elem(const i4v &w, int e)
     return FP8 ? elem_dw<true>(w[e >> 2], e & 3) : elem_dw<false>(w[e >> 1], e & 1);
 }
 
-// Staging of one operand for one step; every thread handles 32 bytes.
+// Staging of one operand (OUTER = 128 or 256 outer indices) for one step;
+// every thread handles OUTER / 4 bytes.
 //   kInner (the inner index runs along the stored rows: A transposed, B not
 //   transposed): thread t fetches 16 bytes (KV consecutive inner values) at
-//   outer indices o = t / 8 + 64 r (r = 0, 1), inner chunk t % 8, and
+//   outer indices o = t / 8 + 64 r (r < OUTER / 64), inner chunk t % 8, and
 //   stores them unchanged.
 //   otherwise (the outer index runs along the stored rows): thread t fetches
-//   the 8 outer indices 8 (t % 16) .. +7 at the PG (2 for BF16, 4 for FP8)
-//   consecutive inner indices PG (t / 16) .. +PG-1 and regroups them into one
-//   dword per outer index (its inner pair or quad), the LDS layout.
-template <bool FP8, bool kInner>
+//   the outer indices 8 (t % 16) + 128 g .. +7 (g < OUTER / 128) at the PG
+//   (2 for BF16, 4 for FP8) consecutive inner indices PG (t / 16) .. +PG-1
+//   and regroups them into one dword per outer index (its inner pair or
+//   quad), the LDS layout.
+template <bool FP8, bool kInner, int OUTER>
 struct LpLoader {
     using E = Elem<FP8>;
     static constexpr int PG = 4 / E::EB;               // inner values per dword
     static constexpr int kNP = kInner ? E::KV : PG;    // inner values per thread
     static constexpr int kParts = kInner ? NW : 1;     // partials of an operand checksum
-    static constexpr int kOuter = kInner ? 2 : 8;      // outer indices per thread
+    static constexpr int kGroups = OUTER / 128;        // otherwise: groups of 8 outer
+    static constexpr int kOuter = kInner ? OUTER / 64 : 8 * kGroups;  // outer indices per thread
     static constexpr int kOuterParts = kInner ? 1 : NW;  // partials of a per-outer sum
     const char *X;
     int64_t ld, R, total_bytes;  // stored rows R, leading dimension ld (elements)
     int t;
-    i4v w[2];  // kInner: two raw 16-byte chunks; otherwise: 8 regrouped dwords
+    // kInner: raw 16-byte chunks; otherwise: regrouped dwords, outer e in w[e / 4][e % 4]
+    i4v w[kInner ? kOuter : kOuter / 4];
 
     __device__ __forceinline__ void init(const void *x, int64_t ld_, int64_t rows, int64_t cols,
                                          int t_)
@@ -174,7 +195,7 @@ struct LpLoader {
     }
     __device__ __forceinline__ int outer(int r) const
     {
-        return kInner ? (t >> 3) + 64 * r : 8 * (t & 15) + r;
+        return kInner ? (t >> 3) + 64 * r : 8 * (t & 15) + (r & 7) + 128 * (r >> 3);
     }
     __device__ __forceinline__ int p0() const { return kInner ? E::KV * (t & 7) : PG * (t >> 4); }
 
@@ -191,7 +212,7 @@ struct LpLoader {
             const __amdgpu_buffer_rsrc_t rs = rsrc(k0, o0);
             const int valid = (int)((k - k0) < E::BK ? (k - k0) : E::BK) - p0();
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
+            for (int r = 0; r < kOuter; ++r) {
                 const uint32_t off =
                     valid > 0 ? (uint32_t)((p0() + (int64_t)outer(r) * ld) * E::EB) : kOob;
                 w[r] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
@@ -200,7 +221,7 @@ struct LpLoader {
                 // a chunk that crosses the end of the inner dimension: element
                 // by element, so nothing past the matrix is read into it
 #pragma unroll
-                for (int r = 0; r < 2; ++r) {
+                for (int r = 0; r < kOuter; ++r) {
                     const uint32_t base = (uint32_t)((p0() + (int64_t)outer(r) * ld) * E::EB);
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
@@ -217,60 +238,63 @@ struct LpLoader {
             }
         } else {
             const __amdgpu_buffer_rsrc_t rs = rsrc(o0, k0);
-            const uint32_t base = (uint32_t)((outer(0) + (int64_t)p0() * ld) * E::EB);
             const uint32_t col = (uint32_t)(ld * E::EB);
-            // raw columns: PG columns of 8 outer indices (16 or 8 bytes each)
-            int c[4][4];
-            if (!FP8) {
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const i4v v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(base + b * col), 0, 0);
+            for (int g = 0; g < kGroups; ++g) {
+                const uint32_t base = (uint32_t)((outer(8 * g) + (int64_t)p0() * ld) * E::EB);
+                // raw columns: PG columns of 8 outer indices (16 or 8 bytes each)
+                int c[4][4];
+                if (!FP8) {
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) c[b][d] = v[d];
-                }
-            } else {
+                    for (int b = 0; b < 2; ++b) {
+                        const i4v v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(base + b * col), 0, 0);
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(base + b * col), 0, 0);
-                    c[b][0] = (int)v[0];
-                    c[b][1] = (int)v[1];
-                }
-            }
-            const int live = (int)(nouter - o0) - outer(0);  // outer indices inside
-            if (live < 8) {
-                // the tile's last rows: element by element (a chunk that
-                // crosses the end of the matrix), zero past it
-#pragma unroll
-                for (int b = 0; b < PG; ++b)
-#pragma unroll
-                    for (int d = 0; d < 8 / PG; ++d) {
-                        unsigned v = 0;
-#pragma unroll
-                        for (int e = 0; e < PG; ++e) {
-                            const int idx = d * PG + e;
-                            if (idx < live)
-                                v |= load_elem(rs, base + b * col + idx * E::EB) << (8 * E::EB * e);
-                        }
-                        c[b][d] = (int)v;
+                        for (int d = 0; d < 4; ++d) c[b][d] = v[d];
                     }
-            }
-            if (!FP8) {
+                } else {
 #pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    // dword d of a column holds outer 2d (low half), 2d + 1 (high)
-                    w[d >> 1][(2 * d) & 3] =
-                        (int)__builtin_amdgcn_perm((unsigned)c[1][d], (unsigned)c[0][d], 0x05040100u);
-                    w[d >> 1][(2 * d + 1) & 3] =
-                        (int)__builtin_amdgcn_perm((unsigned)c[1][d], (unsigned)c[0][d], 0x07060302u);
+                    for (int b = 0; b < 4; ++b) {
+                        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(base + b * col), 0, 0);
+                        c[b][0] = (int)v[0];
+                        c[b][1] = (int)v[1];
+                    }
                 }
-            } else {
+                const int live = (int)(nouter - o0) - outer(8 * g);  // outer indices inside
+                if (live < 8) {
+                    // the tile's last rows: element by element (a chunk that
+                    // crosses the end of the matrix), zero past it
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int h = e >> 2, sb = e & 3;  // dword and byte of outer e in a column
-                    const unsigned sel = (unsigned)(sb | ((sb + 4) << 8)) | 0x0c0c0000u;
-                    const unsigned p01 = __builtin_amdgcn_perm((unsigned)c[1][h], (unsigned)c[0][h], sel);
-                    const unsigned p23 = __builtin_amdgcn_perm((unsigned)c[3][h], (unsigned)c[2][h], sel);
-                    w[e >> 2][e & 3] = (int)__builtin_amdgcn_perm(p23, p01, 0x05040100u);
+                    for (int b = 0; b < PG; ++b)
+#pragma unroll
+                        for (int d = 0; d < 8 / PG; ++d) {
+                            unsigned v = 0;
+#pragma unroll
+                            for (int e = 0; e < PG; ++e) {
+                                const int idx = d * PG + e;
+                                if (idx < live)
+                                    v |= load_elem(rs, base + b * col + idx * E::EB) << (8 * E::EB * e);
+                            }
+                            c[b][d] = (int)v;
+                        }
+                }
+                if (!FP8) {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        // dword d of a column holds outer 2d (low half), 2d + 1 (high)
+                        w[2 * g + (d >> 1)][(2 * d) & 3] =
+                            (int)__builtin_amdgcn_perm((unsigned)c[1][d], (unsigned)c[0][d], 0x05040100u);
+                        w[2 * g + (d >> 1)][(2 * d + 1) & 3] =
+                            (int)__builtin_amdgcn_perm((unsigned)c[1][d], (unsigned)c[0][d], 0x07060302u);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int h = e >> 2, sb = e & 3;  // dword and byte of outer e in a column
+                        const unsigned sel = (unsigned)(sb | ((sb + 4) << 8)) | 0x0c0c0000u;
+                        const unsigned p01 = __builtin_amdgcn_perm((unsigned)c[1][h], (unsigned)c[0][h], sel);
+                        const unsigned p23 = __builtin_amdgcn_perm((unsigned)c[3][h], (unsigned)c[2][h], sel);
+                        w[2 * g + (e >> 2)][e & 3] = (int)__builtin_amdgcn_perm(p23, p01, 0x05040100u);
+                    }
                 }
             }
         }
@@ -279,11 +303,11 @@ struct LpLoader {
     {
         if (kInner) {
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
+            for (int r = 0; r < kOuter; ++r)
                 *(i4v *)&dst[outer(r)][16 * swz(outer(r), t & 7)] = w[r];
         } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
+            for (int e = 0; e < kOuter; ++e)
                 *(int *)&dst[outer(e)][16 * swz(outer(e), t >> 6) + 4 * ((t >> 4) & 3)] =
                     w[e >> 2][e & 3];
         }
@@ -371,7 +395,7 @@ struct LpLoader {
     }
     // Per-outer sums completed over the threads holding the same outer
     // index, into dst[part][outer].
-    __device__ __forceinline__ void partials_to(const float (&a_in)[kOuter], double (*dst)[128]) const
+    __device__ __forceinline__ void partials_to(const float (&a_in)[kOuter], double (*dst)[OUTER]) const
     {
 #pragma unroll
         for (int r = 0; r < kOuter; ++r) {
@@ -388,8 +412,6 @@ struct LpLoader {
             }
         }
     }
-    // one thread per group of inner indices accounts for their checksum
-    __device__ __forceinline__ bool first_of_p() const { return kInner ? t < 8 : (t & 15) == 0; }
 };
 
 // v as hi + mid + lo, three BF16 values (exact: each part takes the next
@@ -416,38 +438,46 @@ __device__ __forceinline__ float gather_lp(const float (*src)[NW], int p)
            ((src[p][4] + src[p][5]) + (src[p][6] + src[p][7]));
 }
 
-__device__ __forceinline__ int owner_wave(int row, int col) { return (row >> 6) + 2 * (col >> 5); }
+// wave, lane and accumulator slot (acc[e / (4 NI)][(e / 4) % NI][e % 4])
+// holding element (row, col) of a BM x TN tile
+template <int BM>
+__device__ __forceinline__ int owner_wave(int row, int col)
+{
+    return (row >> 6) + Geo<BM>::WM * (col / Geo<BM>::WC);
+}
 __device__ __forceinline__ int owner_lane(int row, int col)
 {
     return 16 * ((row & 15) >> 2) + (col & 15);
 }
+template <int BM>
 __device__ __forceinline__ int owner_reg(int row, int col)
 {
-    return ((row & 63) >> 4) * 8 + ((col & 31) >> 4) * 4 + (row & 3);
+    return ((row & 63) >> 4) * (4 * Geo<BM>::NI) + ((col % Geo<BM>::WC) >> 4) * 4 + (row & 3);
 }
 
-template <bool FP8, bool TA, bool TB, bool ABFT>
-__device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> &sm)
+template <bool FP8, bool TA, bool TB, bool ABFT, int BM>
+__device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
 {
     using E = Elem<FP8>;
+    using G = Geo<BM>;
+    constexpr int NI = G::NI, NA = G::NA;
     constexpr bool kMma = !FP8;  // BF16: encoded checksums on the matrix cores
-    // the checksum products of step s run during step s + 1, from a third stage
+    // the checksum products of step s run during step s + 1
     constexpr bool kLag = kMma && ABFT;
-    constexpr int NS = kLag ? 3 : 2;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wm = w & 1, wn = w >> 1;
+    const int wm = w % G::WM, wn = w / G::WM;
     const int q = lane >> 4, c16 = lane & 15;
-    const int64_t i0 = (int64_t)tile_m * TM, j0 = (int64_t)tile_n * TN;
+    const int64_t i0 = (int64_t)tile_m * BM, j0 = (int64_t)tile_n * TN;
     float *__restrict__ C = (float *)g.C;
     const int64_t m = g.m, n = g.n, k = g.k, ldc = g.ldc;
     const int nsteps = (int)((k + E::BK - 1) / E::BK);
-    const int hrows = (int)(m - i0 < TM ? m - i0 : TM);
+    const int hrows = (int)(m - i0 < BM ? m - i0 : BM);
     const int wcols = (int)(n - j0 < TN ? n - j0 : TN);
     const bool use_c = g.beta != 0.0;
 
     // inner index along the stored rows: A transposed, B not transposed
-    using LA = LpLoader<FP8, TA>;
-    using LB = LpLoader<FP8, !TB>;
+    using LA = LpLoader<FP8, TA, BM>;
+    using LB = LpLoader<FP8, !TB, TN>;
     LA la;
     LB lb;
     la.init(g.A, g.lda, TA ? k : m, TA ? m : k, t);
@@ -461,7 +491,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
     int nf = 0;
     if (ABFT) {
         if (w == 0) {
-            const int cnt = gather_tile_faults(g, i0, j0, TM, TN, E::BK, g.k_base, sm.faults);
+            const int cnt = gather_tile_faults(g, i0, j0, BM, TN, E::BK, g.k_base, sm.faults);
             if (lane == 0) sm.nfaults = cnt;
         }
         __syncthreads();
@@ -472,43 +502,51 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
     double rec_before = 0, rec_after = 0;
 
     // Checksum products of a staged step (BF16): the x-part rows times this
-    // wave's B block 16 (2 wn + wm) .., this wave's A block 16 (4 wm + wn) ..
-    // times the y-part rows.
-    auto check_products = [&](const Stage &st, int kk, f4 &acc_r, f4 &acc_c) {
-        const int rb = 16 * (4 * wm + wn) + c16, cb = 16 * (2 * wn + wm) + c16;
-        const bf8v fxa = *(const bf8v *)&st.A[TM + c16][16 * swz(TM + c16, 4 * kk + q)];
+    // wave's B block (columns WC wn + 16 wm ..), this wave's NA A blocks
+    // (rows 64 wm + 16 (NA wn + h) ..) times the y-part rows.  The parts come
+    // from the extra rows of the step's stage, the blocks from registers
+    // (hb, ha) read while the step was the current one.
+    auto check_products = [&](const Stage<BM> &st, int kk, const bf8v &hb, const bf8v (&ha)[NA],
+                              f4 &acc_r, f4 (&acc_c)[NA]) {
+        const bf8v fxa = *(const bf8v *)&st.A[BM + c16][16 * swz(BM + c16, 4 * kk + q)];
         const bf8v fyb = *(const bf8v *)&st.B[TN + c16][16 * swz(TN + c16, 4 * kk + q)];
-        const bf8v fra = *(const bf8v *)&st.A[rb][16 * swz(rb, 4 * kk + q)];
-        const bf8v fcb = *(const bf8v *)&st.B[cb][16 * swz(cb, 4 * kk + q)];
-        acc_r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxa, fcb, acc_r, 0, 0, 0);
-        acc_c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fra, fyb, acc_c, 0, 0, 0);
+        acc_r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxa, hb, acc_r, 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < NA; ++h)
+            acc_c[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[h], fyb, acc_c[h], 0, 0, 0);
     };
+    constexpr int kHold = kLag ? E::NKK : 1;
+    bf8v hold_b[kHold], hold_a[kHold][NA];  // this wave's check blocks of the last step
 
-    f4 acc[4][2];
+    f4 acc[4][NI];
 #pragma unroll 1
     for (int attempt = 0; attempt < 2; ++attempt) {
         const bool faults_on = ABFT && attempt == 0 && nf > 0;
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni)
+            for (int ni = 0; ni < NI; ++ni)
                 acc[mi][ni] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
         float enc_a[LA::kOuter] = {}, nrm_a[LA::kOuter] = {};
         float enc_b[LB::kOuter] = {}, nrm_b[LB::kOuter] = {};
         float vx = 0.0f, vy = 0.0f, amx_a = 0.0f, amx_b = 0.0f;
         float yv[LA::kNP], xv[LB::kNP];  // y at the A loader's p, x at the B loader's
         f4 acc_r = (f4){0.0f, 0.0f, 0.0f, 0.0f};  // x-part rows times this wave's B block
-        f4 acc_c = (f4){0.0f, 0.0f, 0.0f, 0.0f};  // this wave's A block times the y parts
+        f4 acc_c[NA];                             // this wave's A blocks times the y parts
+#pragma unroll
+        for (int h = 0; h < NA; ++h) acc_c[h] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
 
         if (ABFT && kMma) {
             // clear the extra rows of both stages (the epilogue reuses the
             // memory); done before step 0's barrier
-            constexpr int kChunks = NS * 2 * XR * (SROW / 16);
+            constexpr int kRowChunks = XR * (SROW / 16);
+            constexpr int kChunks = 2 * 2 * kRowChunks;
             for (int c = t; c < kChunks; c += NT) {
-                const int st = c / (2 * XR * (SROW / 16)), rem = c % (2 * XR * (SROW / 16));
-                const int op = rem / (XR * (SROW / 16)), rr = rem % (XR * (SROW / 16));
+                const int st = c / (2 * kRowChunks), rem = c % (2 * kRowChunks);
+                const int op = rem / kRowChunks, rr = rem % kRowChunks;
                 unsigned char(*dst)[SROW] = op ? sm.u.st[st].B : sm.u.st[st].A;
-                *(i4v *)&dst[TM + rr / (SROW / 16)][16 * (rr % (SROW / 16))] = (i4v){0, 0, 0, 0};
+                *(i4v *)&dst[(op ? TN : BM) + rr / (SROW / 16)][16 * (rr % (SROW / 16))] =
+                    (i4v){0, 0, 0, 0};
             }
         }
 
@@ -528,9 +566,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
                 }
 #pragma unroll 1
             for (; s <= stop; ++s) {
-                const int buf = s & 1;                          // checksum buffers
-                const int stg = kLag ? s % 3 : buf;             // staged step s
-                const int pst = kLag ? (s + 2) % 3 : buf;       // staged step s - 1
+                const int stg = s & 1;  // stage and checksum buffers of step s
                 la.store(sm.u.st[stg].A);
                 lb.store(sm.u.st[stg].B);
                 __syncthreads();
@@ -539,51 +575,69 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
                     // extra rows, for the checksum products of step s (run
                     // during step s + 1, after its barrier)
                     if (t < E::BK) {
-                        const float xp = gather_lp<LA::kParts>(sm.xs[buf], t);
-                        const float yp = gather_lp<LB::kParts>(sm.ys[buf], t);
+                        const float xp = gather_lp<LA::kParts>(sm.xs[stg], t);
+                        const float yp = gather_lp<LB::kParts>(sm.ys[stg], t);
                         vx = fmaf(xp, xp, vx);
                         vy = fmaf(yp, yp, vy);
-                        put_parts(sm.u.st[stg].A, TM, t, xp);
+                        put_parts(sm.u.st[stg].A, BM, t, xp);
                         put_parts(sm.u.st[stg].B, TN, t, yp);
                     }
                 } else if (ABFT) {
-                    // x_p, y_p of step s are complete: the encoded checksums
-                    // and norms of step s, before the registers take step s + 1
+                    // x_p, y_p of step s are complete: combined once (one
+                    // thread per p), then the encoded checksums and norms of
+                    // step s, before the registers take step s + 1
+                    if (t < E::BK) {
+                        const float xp = gather_lp<LA::kParts>(sm.xs[stg], t);
+                        const float yp = gather_lp<LB::kParts>(sm.ys[stg], t);
+                        vx = fmaf(xp, xp, vx);
+                        vy = fmaf(yp, yp, vy);
+                        sm.xc[t] = xp;
+                        sm.yc[t] = yp;
+                    }
+                    __syncthreads();
 #pragma unroll
-                    for (int e = 0; e < LA::kNP; ++e) yv[e] = gather_lp<LB::kParts>(sm.ys[buf], la.p0() + e);
+                    for (int e = 0; e < LA::kNP; ++e) yv[e] = sm.yc[la.p0() + e];
 #pragma unroll
-                    for (int e = 0; e < LB::kNP; ++e) xv[e] = gather_lp<LA::kParts>(sm.xs[buf], lb.p0() + e);
+                    for (int e = 0; e < LB::kNP; ++e) xv[e] = sm.xc[lb.p0() + e];
                     la.encode(yv, enc_a, nrm_a, amx_a);
                     lb.encode(xv, enc_b, nrm_b, amx_b);
-                    if (la.first_of_p())
-#pragma unroll
-                        for (int e = 0; e < LA::kNP; ++e) vy = fmaf(yv[e], yv[e], vy);
-                    if (lb.first_of_p())
-#pragma unroll
-                        for (int e = 0; e < LB::kNP; ++e) vx = fmaf(xv[e], xv[e], vx);
                 }
                 if (s + 1 < nsteps) load(s + 1);
 #pragma unroll
                 for (int kk = 0; kk < E::NKK; ++kk) {
                     if (!FP8) {
-                        bf8v fa[4], fb[2];
+                        bf8v fa[4], fb[NI];
+#pragma unroll
+                        for (int mi = 0; mi < 4; ++mi) {
+                            const int r = wm * 64 + 16 * mi + c16;
+                            fa[mi] = *(const bf8v *)&sm.u.st[stg].A[r][16 * swz(r, 4 * kk + q)];
+                        }
+#pragma unroll
+                        for (int ni = 0; ni < NI; ++ni) {
+                            const int r = wn * G::WC + 16 * ni + c16;
+                            fb[ni] = *(const bf8v *)&sm.u.st[stg].B[r][16 * swz(r, 4 * kk + q)];
+                        }
 #pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
-                            fa[mi] = *(const bf8v *)&sm.u.st[stg].A[wm * 64 + 16 * mi + c16]
-                                                                    [16 * swz(wm * 64 + 16 * mi + c16, 4 * kk + q)];
 #pragma unroll
-                        for (int ni = 0; ni < 2; ++ni)
-                            fb[ni] = *(const bf8v *)&sm.u.st[stg].B[wn * 32 + 16 * ni + c16]
-                                                                    [16 * swz(wn * 32 + 16 * ni + c16, 4 * kk + q)];
-#pragma unroll
-                        for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-                            for (int ni = 0; ni < 2; ++ni)
+                            for (int ni = 0; ni < NI; ++ni)
                                 acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                                     fa[mi], fb[ni], acc[mi][ni], 0, 0, 0);
-                        if (kLag && s > 0) check_products(sm.u.st[pst], kk, acc_r, acc_c);
+                        if (kLag) {
+                            if (s > 0)
+                                check_products(sm.u.st[stg ^ 1], kk, hold_b[kk], hold_a[kk], acc_r,
+                                               acc_c);
+                            const int rb = wn * G::WC + 16 * wm + c16;
+                            hold_b[kk] = *(const bf8v *)&sm.u.st[stg].B[rb][16 * swz(rb, 4 * kk + q)];
+#pragma unroll
+                            for (int h = 0; h < NA; ++h) {
+                                const int ra = 64 * wm + 16 * (NA * wn + h) + c16;
+                                hold_a[kk][h] =
+                                    *(const bf8v *)&sm.u.st[stg].A[ra][16 * swz(ra, 4 * kk + q)];
+                            }
+                        }
                     } else {
-                        i8v fa[4], fb[2];
+                        i8v fa[4], fb[NI];
 #pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
                         {
@@ -593,9 +647,9 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
                             fa[mi] = (i8v){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
                         }
 #pragma unroll
-                        for (int ni = 0; ni < 2; ++ni)
+                        for (int ni = 0; ni < NI; ++ni)
                         {
-                            const int r = wn * 32 + 16 * ni + c16;
+                            const int r = wn * G::WC + 16 * ni + c16;
                             const i4v lo = *(const i4v *)&sm.u.st[stg].B[r][16 * swz(r, 2 * q)];
                             const i4v hi = *(const i4v *)&sm.u.st[stg].B[r][16 * swz(r, 2 * q + 1)];
                             fb[ni] = (i8v){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
@@ -603,32 +657,32 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
 #pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-                            for (int ni = 0; ni < 2; ++ni)
+                            for (int ni = 0; ni < NI; ++ni)
                                 acc[mi][ni] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
                                     fa[mi], fb[ni], acc[mi][ni], 0, 0, 0, 127, 0, 127);
                     }
                 }
                 if (ABFT && s + 1 < nsteps) {
                     // operand checksums of step s + 1, published before its barrier
-                    la.template sum_to<kMma>(sm.xs[buf ^ 1], nrm_a);
-                    lb.template sum_to<kMma>(sm.ys[buf ^ 1], nrm_b);
+                    la.template sum_to<kMma>(sm.xs[stg ^ 1], nrm_a);
+                    lb.template sum_to<kMma>(sm.ys[stg ^ 1], nrm_b);
                 }
             }
             if (ABFT && faults_on) {
                 for (int f = 0; f < nf; ++f) {
                     const TileFault tf = sm.faults[f];
                     if (tf.target != FTGEMM_TGT_ACC || tf.kstep != stop) continue;
-                    if (w != owner_wave(tf.row, tf.col)) continue;
-                    const int ol = owner_lane(tf.row, tf.col), sel = owner_reg(tf.row, tf.col);
+                    if (w != owner_wave<BM>(tf.row, tf.col)) continue;
+                    const int ol = owner_lane(tf.row, tf.col), sel = owner_reg<BM>(tf.row, tf.col);
                     float before = 0.0f;
 #pragma unroll
-                    for (int e = 0; e < 32; ++e)
-                        if (sel == e) before = acc[e >> 3][(e >> 2) & 1][e & 3];
+                    for (int e = 0; e < G::NREG; ++e)
+                        if (sel == e) before = acc[e / (4 * NI)][(e >> 2) % NI][e & 3];
                     const float after = tf.mode == FTGEMM_INJ_ADD ? (float)((double)before + tf.delta)
                                                                   : flip_bit_f32(before, tf.bit & 31);
 #pragma unroll
-                    for (int e = 0; e < 32; ++e)
-                        if (sel == e && lane == ol) acc[e >> 3][(e >> 2) & 1][e & 3] = after;
+                    for (int e = 0; e < G::NREG; ++e)
+                        if (sel == e && lane == ol) acc[e / (4 * NI)][(e >> 2) % NI][e & 3] = after;
                     if (lane == ol) {
                         ftgemm_injection_echo ech;
                         ech.problem = g.problem;
@@ -649,13 +703,13 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
             // the epilogue then reuses the stages' memory
 #pragma unroll
             for (int kk = 0; kk < E::NKK; ++kk)
-                check_products(sm.u.st[(nsteps - 1) % 3], kk, acc_r, acc_c);
+                check_products(sm.u.st[(nsteps - 1) & 1], kk, hold_b[kk], hold_a[kk], acc_r, acc_c);
             __syncthreads();
         }
         // From here on the lane-derived indices are formed again instead of
         // being carried across the main loop.
         const int t = fresh_tid(), lane = t & 63, w = t >> 6;
-        const int wm = w & 1, wn = w >> 1, q = lane >> 4, c16 = lane & 15;
+        const int wm = w % G::WM, wn = w / G::WM, q = lane >> 4, c16 = lane & 15;
         la.t = t;
         lb.t = t;
 
@@ -663,11 +717,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < 2; ++ni)
+                for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = wm * 64 + 16 * mi + 4 * q + r;
-                        const int col = wn * 32 + 16 * ni + c16;
+                        const int col = wn * G::WC + 16 * ni + c16;
                         if (row < hrows && col < wcols) {
                             float *pc = C + (i0 + row) + (j0 + col) * ldc;
                             const double o = g.alpha * (double)acc[mi][ni][r];
@@ -682,10 +736,13 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
             // column 0..2 of the A . y block), column sums of the x-part rows
             if (c16 < 3)
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    sm.u.epi.enc_row[c16][16 * (4 * wm + wn) + 4 * q + r] = (double)acc_c[r];
+                for (int h = 0; h < NA; ++h)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        sm.u.epi.enc_row[c16][64 * wm + 16 * (NA * wn + h) + 4 * q + r] =
+                            (double)acc_c[h][r];
             if (q == 0)
-                sm.u.epi.enc_col[0][16 * (2 * wn + wm) + c16] =
+                sm.u.epi.enc_col[0][wn * G::WC + 16 * wm + c16] =
                     ((double)acc_r[0] + (double)acc_r[1]) + (double)acc_r[2];
         } else {
             la.partials_to(enc_a, sm.u.epi.enc_row);
@@ -693,12 +750,10 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
         }
         la.partials_to(nrm_a, sm.u.epi.nrm_row);
         lb.partials_to(nrm_b, sm.u.epi.nrm_col);
-        // |x|^2 (B loader) and |y|^2 (A loader): one thread per group of p
+        // |x|^2 and |y|^2: threads t < BK took one p each
         {
-            const bool hx = kMma ? t < E::BK : lb.first_of_p();
-            const bool hy = kMma ? t < E::BK : la.first_of_p();
-            const double sx = sum64(hx ? (double)vx : 0.0);
-            const double sy = sum64(hy ? (double)vy : 0.0);
+            const double sx = sum64(t < E::BK ? (double)vx : 0.0);
+            const double sy = sum64(t < E::BK ? (double)vy : 0.0);
             const double ma = FP8 ? max64((double)amx_a) : 0.0;
             const double mb = FP8 ? max64((double)amx_b) : 0.0;
             if (lane == 0) {
@@ -708,7 +763,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
 
         // Beta pass fused with the C_in part of the encoding; the output is
         // rounded to FP32 and the reference sums are taken of what is stored.
-        double col_o[2] = {0, 0}, col_c[2] = {0, 0}, col_c2[2] = {0, 0};
+        double col_o[NI] = {}, col_c[NI] = {}, col_c2[NI] = {};
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -716,8 +771,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
                 double row_o = 0, row_c = 0, row_c2 = 0;
                 const int row = wm * 64 + 16 * mi + 4 * q + r;
 #pragma unroll
-                for (int ni = 0; ni < 2; ++ni) {
-                    const int col = wn * 32 + 16 * ni + c16;
+                for (int ni = 0; ni < NI; ++ni) {
+                    const int col = wn * G::WC + 16 * ni + c16;
                     const bool ok = row < hrows && col < wcols;
                     const double cin = (use_c && ok) ? (double)C[(i0 + row) + (j0 + col) * ldc] : 0.0;
                     double o = g.alpha * (double)acc[mi][ni][r];
@@ -736,21 +791,21 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
                 }
             }
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni) {
+        for (int ni = 0; ni < NI; ++ni) {
             col_o[ni] = sum_rows(col_o[ni]);
             if (use_c) { col_c[ni] = sum_rows(col_c[ni]); col_c2[ni] = sum_rows(col_c2[ni]); }
             if (q == 0) {
-                const int col = wn * 32 + 16 * ni + c16;
+                const int col = wn * G::WC + 16 * ni + c16;
                 sm.u.epi.ref_col[wm][col] = col_o[ni];
                 sm.u.epi.cin_col[wm][col] = col_c[ni];
                 sm.u.epi.cin2_col[wm][col] = col_c2[ni];
             }
         }
-        if (t == 0) { sm.nbad_r = 0; sm.nbad_c = 0; sm.ibad = TM; sm.jbad = TN; }
+        if (t == 0) { sm.nbad_r = 0; sm.nbad_c = 0; sm.ibad = BM; sm.jbad = TN; }
         __syncthreads();
 
-        const bool is_row = t < TM, is_col = t >= TM && t < TM + TN;
-        const int x = is_row ? t : t - TM;
+        const bool is_row = t < BM, is_col = t >= BM && t < BM + TN;
+        const int x = is_row ? t : t - BM;
         double nrm2 = 0.0;
         if (is_row) {
             double e = 0, nr = 0;
@@ -777,8 +832,9 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
             nrm2 = nr;
             sm.u.epi.fin_col[x] = e;
         }
-        // Frobenius norms of the A and B tiles (waves 0-1 and 2-3), |x|, |y|
-        if (w < 4) {
+        // Frobenius norms of the A and B tiles (the waves verifying rows,
+        // then those verifying columns), |x|, |y|
+        if (w < G::kVW) {
             const double f = sum64(nrm2);
             if (lane == 0) sm.wsum[w][2] = f;
         }
@@ -794,8 +850,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
             sm.scal[1] = sy;                                // |y|^2
             sm.scal[4] = ma;                                // max|A_I|
             sm.scal[5] = mb;                                // max|B_J|
-            sm.scal[2] = sm.wsum[0][2] + sm.wsum[1][2];     // |A_I|_F^2
-            sm.scal[3] = sm.wsum[2][2] + sm.wsum[3][2];     // |B_J|_F^2
+            double fa = 0, fb = 0;
+#pragma unroll
+            for (int v = 0; v < G::kVW; ++v) (v < G::kRW ? fa : fb) += sm.wsum[v][2];
+            sm.scal[2] = fa;                                // |A_I|_F^2
+            sm.scal[3] = fb;                                // |B_J|_F^2
         }
         __syncthreads();
 
@@ -807,15 +866,18 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
                 double R = 0.0, cs = 0.0, c2 = 0.0;
                 if (is_row) {
 #pragma unroll
-                    for (int v = 0; v < WN; ++v) {
+                    for (int v = 0; v < G::WN; ++v) {
                         R += sm.u.epi.ref_row[v][x];
                         cs += sm.u.epi.cin_row[v][x];
                         c2 += sm.u.epi.cin2_row[v][x];
                     }
                 } else {
-                    R = sm.u.epi.ref_col[0][x] + sm.u.epi.ref_col[1][x];
-                    cs = sm.u.epi.cin_col[0][x] + sm.u.epi.cin_col[1][x];
-                    c2 = sm.u.epi.cin2_col[0][x] + sm.u.epi.cin2_col[1][x];
+#pragma unroll
+                    for (int v = 0; v < G::WM; ++v) {
+                        R += sm.u.epi.ref_col[v][x];
+                        cs += sm.u.epi.cin_col[v][x];
+                        c2 += sm.u.epi.cin2_col[v][x];
+                    }
                 }
                 if (use_c) P += g.beta * cs;
                 if (faults_on)
@@ -856,16 +918,18 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
                     }
                 }
             }
-            if (w < 4) {
+            if (w < G::kVW) {
                 ratio = max64(ratio);
                 if (lane == 0) sm.wratio[w] = ratio;
             }
         }
         __syncthreads();
-        if (t == 0)
-            atomic_max_nonneg(&g.counters->max_ratio_bits,
-                              fmax(fmax(sm.wratio[0], sm.wratio[1]),
-                                   fmax(sm.wratio[2], sm.wratio[3])));
+        if (t == 0) {
+            double r = 0.0;
+#pragma unroll
+            for (int v = 0; v < G::kVW; ++v) r = fmax(r, sm.wratio[v]);
+            atomic_max_nonneg(&g.counters->max_ratio_bits, r);
+        }
 
         const int nr = sm.nbad_r, nc = sm.nbad_c;
         if (nr == 0 && nc == 0) {
@@ -886,11 +950,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < 2; ++ni)
+                for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = wm * 64 + 16 * mi + 4 * q + r;
-                        const int col = wn * 32 + 16 * ni + c16;
+                        const int col = wn * G::WC + 16 * ni + c16;
                         const double o = (double)acc[mi][ni][r];
                         if (col == js && row != is) s_col += o;
                         if (row == is && col != js) s_row += o;
@@ -906,13 +970,13 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
             const double fixed = sm.u.epi.fin_col[js] - sc;
             const float fixed_f = (float)fixed;
             if (fabs(sr + (double)fixed_f - sm.u.epi.fin_row[is]) <= sm.u.epi.tau_row[is]) {
-                if (w == owner_wave(is, js)) {
-                    const int ol = owner_lane(is, js), sel = owner_reg(is, js);
+                if (w == owner_wave<BM>(is, js)) {
+                    const int ol = owner_lane(is, js), sel = owner_reg<BM>(is, js);
 #pragma unroll
-                    for (int e = 0; e < 32; ++e)
+                    for (int e = 0; e < G::NREG; ++e)
                         if (sel == e && lane == ol) {
-                            rec_before = (double)acc[e >> 3][(e >> 2) & 1][e & 3];
-                            acc[e >> 3][(e >> 2) & 1][e & 3] = fixed_f;
+                            rec_before = (double)acc[e / (4 * NI)][(e >> 2) % NI][e & 3];
+                            acc[e / (4 * NI)][(e >> 2) % NI][e & 3] = fixed_f;
                         }
                 }
                 rec_after = (double)fixed_f;
@@ -935,10 +999,10 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
 
     if (ABFT) {
         const int t = fresh_tid(), lane = t & 63, w = t >> 6;
-        const int wm = w & 1, wn = w >> 1, q = lane >> 4, c16 = lane & 15;
+        const int wm = w % G::WM, wn = w / G::WM, q = lane >> 4, c16 = lane & 15;
         if (kind == FTGEMM_KIND_CORRECTED) {
             __syncthreads();
-            if (w == owner_wave(first_i, first_j) && lane == owner_lane(first_i, first_j))
+            if (w == owner_wave<BM>(first_i, first_j) && lane == owner_lane(first_i, first_j))
                 sm.red[2][0] = rec_before;
             __syncthreads();
             rec_before = sm.red[2][0];
@@ -981,26 +1045,28 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<FP8, ABFT> 
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni)
+            for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = wm * 64 + 16 * mi + 4 * q + r;
-                    const int col = wn * 32 + 16 * ni + c16;
+                    const int col = wn * G::WC + 16 * ni + c16;
                     if (row < hrows && col < wcols)
                         C[(i0 + row) + (j0 + col) * ldc] = acc[mi][ni][r];
                 }
     }
 }
 
-template <bool FP8, bool TA, bool TB, bool ABFT>
+template <bool FP8, bool TA, bool TB, bool ABFT, int BM>
 __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
 {
-    __shared__ Smem<FP8, ABFT> sm;
+    __shared__ Smem<BM> sm;
     int tm_, tn_;
     map_tile(blockIdx.x, g.tiles_m, g.tiles_n, tm_, tn_);
-    tile<FP8, TA, TB, ABFT>(g, tm_, tn_, sm);
+    tile<FP8, TA, TB, ABFT, BM>(g, tm_, tn_, sm);
 }
 
+// Tile rows of the batched kernel (problems of mixed, often small, shapes).
+constexpr int kBatchBM = 128;
 
 // Persistent batched kernel: workgroup w starts on queue w mod nqueues (with
 // one queue per XCD, the XCD it runs on) and moves on to the others when it
@@ -1008,7 +1074,7 @@ __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
 template <bool FP8, bool TA, bool TB, bool ABFT>
 __global__ __launch_bounds__(NT, 2) void batched_kernel(BatchArgs b)
 {
-    __shared__ Smem<FP8, ABFT> sm;
+    __shared__ Smem<kBatchBM> sm;
     __shared__ int next;
     const int first = (int)(blockIdx.x % (unsigned)b.nqueues);
     for (int qi = 0; qi < b.nqueues; ++qi) {
@@ -1022,7 +1088,7 @@ __global__ __launch_bounds__(NT, 2) void batched_kernel(BatchArgs b)
             if (it >= end) break;
             const WorkItem w = b.items[it];
             const GemmArgs g = b.probs[w.problem];
-            tile<FP8, TA, TB, ABFT>(g, w.tile_m, w.tile_n, sm);
+            tile<FP8, TA, TB, ABFT, kBatchBM>(g, w.tile_m, w.tile_n, sm);
             __syncthreads();
         }
     }
@@ -1049,13 +1115,13 @@ hipError_t launch_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int g
     return hipGetLastError();
 }
 
-template <bool FP8>
+template <bool FP8, int BM>
 hipError_t launch(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream)
 {
     const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n;
     if (grid == 0) return hipSuccess;
 #define FTG_LP_CASE(a, b, c) \
-    hipLaunchKernelGGL((kernel<FP8, a, b, c>), dim3(grid), dim3(NT), 0, stream, g)
+    hipLaunchKernelGGL((kernel<FP8, a, b, c, BM>), dim3(grid), dim3(NT), 0, stream, g)
     if (abft) {
         if (!ta && !tb) FTG_LP_CASE(false, false, true);
         else if (!ta && tb) FTG_LP_CASE(false, true, true);
@@ -1073,11 +1139,15 @@ hipError_t launch(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t st
 
 }  // namespace lp
 
-hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, bool abft,
+hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, bool abft, int tm,
                      hipStream_t stream)
 {
-    return fp8 ? lp::launch<true>(g, ta, tb, abft, stream)
-               : lp::launch<false>(g, ta, tb, abft, stream);
+    if (tm == 256)
+        return fp8 ? lp::launch<true, 256>(g, ta, tb, abft, stream)
+                   : lp::launch<false, 256>(g, ta, tb, abft, stream);
+    if (tm != 128) return hipErrorInvalidValue;
+    return fp8 ? lp::launch<true, 128>(g, ta, tb, abft, stream)
+               : lp::launch<false, 128>(g, ta, tb, abft, stream);
 }
 
 hipError_t launch_lp_batched(const BatchArgs &b, bool fp8, bool ta, bool tb, bool abft, int grid,
@@ -1087,9 +1157,17 @@ hipError_t launch_lp_batched(const BatchArgs &b, bool fp8, bool ta, bool tb, boo
                : lp::launch_batched<false>(b, ta, tb, abft, grid, stream);
 }
 
-void tiling_lp(bool fp8, int *tm, int *tn, int *bk)
+// 256-row tiles once they still give every compute unit a tile (they do
+// twice the matrix work per staged byte of the 128-row tiles), 128 rows
+// otherwise and in batches.  The fault-tolerant FP8 kernel keeps 128-row
+// tiles: at 256 rows its per-row checksum and norm registers no longer fit
+// beside the accumulators and it spills inside the main loop.
+void tiling_lp(bool fp8, bool abft, int64_t m, int64_t n, bool batched, int *tm, int *tn,
+               int *bk)
 {
-    *tm = lp::TM;
+    const int64_t tiles256 = ((m + 255) / 256) * ((n + lp::TN - 1) / lp::TN);
+    const bool large = !batched && !(fp8 && abft) && tiles256 >= kLargeTileMin;
+    *tm = large ? 256 : lp::kBatchBM;
     *tn = lp::TN;
     *bk = fp8 ? lp::Elem<true>::BK : lp::Elem<false>::BK;
 }

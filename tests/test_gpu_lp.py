@@ -132,9 +132,12 @@ def test_lp_small_and_edge_shapes(dtype, m, n, k):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_lp_plain_kernel_bitwise_equals_ft(dtype):
-    """With no faults the checksum-free kernel writes the same bits."""
-    A, B, Cin = synth.operands(32, 0, 333, 222, 111, "normal")
+@pytest.mark.parametrize("m,n,k", [(333, 222, 111), (3999, 2001, 301)])
+def test_lp_plain_kernel_bitwise_equals_ft(dtype, m, n, k):
+    """With no faults the checksum-free kernel writes the same bits (also
+    where the two use different tiles: at 3999 x 2001 the FP8 kernel
+    without checksums takes 256-row tiles, the fault-tolerant one 128)."""
+    A, B, Cin = synth.operands(32, 0, m, n, k, "normal")
     ca, cb, sa, sb, dA, dB = lp_inputs(A, B, dtype)
     C32 = _c32(Cin)
     ft, rep = gpu_lp(ca, cb, C32, 1.5, -0.5, dtype, scale_a=sa, scale_b=sb)
@@ -200,26 +203,53 @@ def test_lp_bitflips_and_fault_classes(dtype):
                                                             F.KIND_CHECKSUM_ONLY])
 
 
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+def test_lp_256_row_tiles(ta, tb):
+    """The 256 x 128 BF16 tile (chosen from 256 tiles on): ragged in every
+    dimension, beta != 0, additive faults on accumulators in the last row
+    and column tiles and the interior, checked against the oracle on the
+    whole output."""
+    dtype = F.BF16
+    m, n, k = 3999, 2001, 301
+    tm, tn, bk = lp_tiling(dtype, m, n, k)
+    assert (tm, tn) == (256, 128)
+    A, B, Cin = synth.operands(31, 1, m, n, k, "normal", ta, tb)
+    q = lp_inputs(A, B, dtype)
+    unit = 1.0 / (q[2] * q[3])  # accumulator units per output unit
+    Fa = synth.Fault
+    plan = [Fa(m - 1, n - 1, k - 1, synth.ADD, 2e3 * unit),      # corner tile, last step
+            Fa(3840 + 100, 70, 64, synth.ADD, -5e3 * unit),      # last row tile
+            Fa(255, 1920 + 7, 0, synth.ADD, 1e4 * unit),         # last column tile, first step
+            Fa(1000, 1000, 150, synth.ADD, 3e3 * unit)]          # interior
+    got, rep, ref = _compare(A, B, Cin, 0.9, -1.1, dtype, ta, tb, plan, q=q)
+    assert rep.corrected == 4 == rep.detected
+    assert rep.tiles_verified == 16 * 16
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_lp_8192_sampled_tiles(dtype):
-    """m = n = k = 8192, normal inputs, as timed by the benchmark.  Error-free:
-    no tile flagged (false-positive rate 0 of 4096).  With one guarded FP32
+    """m = n = k = 8192, normal inputs, as timed by the benchmark (BF16:
+    256 x 128 tiles; FP8: 128 x 128).  Error-free: no tile flagged.  With
+    one guarded FP32
     bit flip per 64 tiles: every one located and rebuilt; the oracle checks
     the tiles holding a fault plus sampled clean and corner tiles."""
     size = 8192
     A, B, Cin = synth.operands(40, size, size, size, size, "normal")
     q = lp_inputs(A, B, dtype)
     ca, cb, sa, sb, dA, dB = q
-    tiles_m = size // 128
-    extra = [0, tiles_m * tiles_m - 1, tiles_m - 1] + [int(t) for t in synth.rng(40, 1, 9).choice(
-        tiles_m * tiles_m, 5, replace=False)]
+    tm, tn, bk = lp_tiling(dtype, size, size, size)
+    assert (tm, tn) == ((256, 128) if dtype == F.BF16 else (128, 128))
+    tiles_m, tiles_n = size // tm, size // tn
+    ntiles = tiles_m * tiles_n
+    extra = [0, ntiles - 1, tiles_m - 1, ntiles - tiles_m] + [
+        int(t) for t in synth.rng(40, 1, 9).choice(ntiles, 5, replace=False)]
     got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, dtype, tiles=sorted(set(extra)), q=q)
-    assert rep.detected == 0 and rep.tiles_verified == tiles_m * tiles_m
+    assert rep.detected == 0 and rep.tiles_verified == ntiles
     assert 0 < rep.max_ratio < 1
     g = synth.rng(40, size, synth.STREAM_PLAN)
-    flips = _guarded_flips(A, B, dA, dB, sa, sb, 1.0, 1.0, Cin, dtype, tiles_m * tiles_m // 64, g)
-    assert len(flips) == tiles_m * tiles_m // 64
-    faulty = sorted({(f.row // 128) + (f.col // 128) * tiles_m for f in flips})
+    flips = _guarded_flips(A, B, dA, dB, sa, sb, 1.0, 1.0, Cin, dtype, ntiles // 64, g)
+    assert len(flips) == ntiles // 64
+    faulty = sorted({(f.row // tm) + (f.col // tn) * tiles_m for f in flips})
     tiles = sorted(set(faulty[:12]) | set(extra))
     got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, dtype, plan=flips, tiles=tiles, q=q)
     assert rep.corrected == len(flips) == rep.detected
