@@ -159,8 +159,10 @@ __device__ __forceinline__ float elem(const i4v &w, int e)
 //   otherwise (the outer index runs along the stored rows): thread t fetches
 //   the outer indices 8 (t % 16) + 128 g .. +7 (g < OUTER / 128) at the PG
 //   (2 for BF16, 4 for FP8) consecutive inner indices PG (t / 16) .. +PG-1
-//   and regroups them into one dword per outer index (its inner pair or
-//   quad), the LDS layout.
+//   as PG raw columns, and regroups them into one dword per outer index (its
+//   inner pair or quad, the LDS layout) only when storing: nothing reads the
+//   loaded registers before the next step's store, so the loads stay in
+//   flight across the step's matrix products.
 template <bool FP8, bool kInner, int OUTER>
 struct LpLoader {
     using E = Elem<FP8>;
@@ -173,8 +175,21 @@ struct LpLoader {
     const char *X;
     int64_t ld, R, total_bytes;  // stored rows R, leading dimension ld (elements)
     int t;
-    // kInner: raw 16-byte chunks; otherwise: regrouped dwords, outer e in w[e / 4][e % 4]
+    // kInner: raw 16-byte chunks; otherwise: raw columns, see col_dw
     i4v w[kInner ? kOuter : kOuter / 4];
+    // otherwise: dword d of raw column b (inner p0 + b) of group g, holding
+    // outer 8 g + d PG / 2 .. (BF16: 2 per dword, FP8: 4)
+    __device__ __forceinline__ int col_dw(int g, int b, int d) const
+    {
+        return FP8 ? w[2 * g + (b >> 1)][2 * (b & 1) + d] : w[2 * g + b][d];
+    }
+    __device__ __forceinline__ void set_col_dw(int g, int b, int d, int v)
+    {
+        if (FP8)
+            w[2 * g + (b >> 1)][2 * (b & 1) + d] = v;
+        else
+            w[2 * g + b][d] = v;
+    }
 
     __device__ __forceinline__ void init(const void *x, int64_t ld_, int64_t rows, int64_t cols,
                                          int t_)
@@ -243,20 +258,14 @@ struct LpLoader {
             for (int g = 0; g < kGroups; ++g) {
                 const uint32_t base = (uint32_t)((outer(8 * g) + (int64_t)p0() * ld) * E::EB);
                 // raw columns: PG columns of 8 outer indices (16 or 8 bytes each)
-                int c[4][4];
-                if (!FP8) {
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const i4v v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(base + b * col), 0, 0);
-#pragma unroll
-                        for (int d = 0; d < 4; ++d) c[b][d] = v[d];
-                    }
-                } else {
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
+                for (int b = 0; b < PG; ++b) {
+                    if (!FP8) {
+                        w[2 * g + b] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(base + b * col), 0, 0);
+                    } else {
                         const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(base + b * col), 0, 0);
-                        c[b][0] = (int)v[0];
-                        c[b][1] = (int)v[1];
+                        set_col_dw(g, b, 0, (int)v[0]);
+                        set_col_dw(g, b, 1, (int)v[1]);
                     }
                 }
                 const int live = (int)(nouter - o0) - outer(8 * g);  // outer indices inside
@@ -274,27 +283,8 @@ struct LpLoader {
                                 if (idx < live)
                                     v |= load_elem(rs, base + b * col + idx * E::EB) << (8 * E::EB * e);
                             }
-                            c[b][d] = (int)v;
+                            set_col_dw(g, b, d, (int)v);
                         }
-                }
-                if (!FP8) {
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        // dword d of a column holds outer 2d (low half), 2d + 1 (high)
-                        w[2 * g + (d >> 1)][(2 * d) & 3] =
-                            (int)__builtin_amdgcn_perm((unsigned)c[1][d], (unsigned)c[0][d], 0x05040100u);
-                        w[2 * g + (d >> 1)][(2 * d + 1) & 3] =
-                            (int)__builtin_amdgcn_perm((unsigned)c[1][d], (unsigned)c[0][d], 0x07060302u);
-                    }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int h = e >> 2, sb = e & 3;  // dword and byte of outer e in a column
-                        const unsigned sel = (unsigned)(sb | ((sb + 4) << 8)) | 0x0c0c0000u;
-                        const unsigned p01 = __builtin_amdgcn_perm((unsigned)c[1][h], (unsigned)c[0][h], sel);
-                        const unsigned p23 = __builtin_amdgcn_perm((unsigned)c[3][h], (unsigned)c[2][h], sel);
-                        w[2 * g + (e >> 2)][e & 3] = (int)__builtin_amdgcn_perm(p23, p01, 0x05040100u);
-                    }
                 }
             }
         }
@@ -306,17 +296,38 @@ struct LpLoader {
             for (int r = 0; r < kOuter; ++r)
                 *(i4v *)&dst[outer(r)][16 * swz(outer(r), t & 7)] = w[r];
         } else {
+            // regroup: one dword per outer index holding its PG inner values
 #pragma unroll
-            for (int e = 0; e < kOuter; ++e)
-                *(int *)&dst[outer(e)][16 * swz(outer(e), t >> 6) + 4 * ((t >> 4) & 3)] =
-                    w[e >> 2][e & 3];
+            for (int g = 0; g < kGroups; ++g)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    unsigned v;
+                    if (!FP8) {
+                        // dword e / 2 of a column holds outer e (low half if e is even)
+                        v = __builtin_amdgcn_perm((unsigned)col_dw(g, 1, e >> 1),
+                                                  (unsigned)col_dw(g, 0, e >> 1),
+                                                  (e & 1) ? 0x07060302u : 0x05040100u);
+                    } else {
+                        const int h = e >> 2, sb = e & 3;  // dword and byte of outer e in a column
+                        const unsigned sel = (unsigned)(sb | ((sb + 4) << 8)) | 0x0c0c0000u;
+                        const unsigned p01 = __builtin_amdgcn_perm((unsigned)col_dw(g, 1, h),
+                                                                   (unsigned)col_dw(g, 0, h), sel);
+                        const unsigned p23 = __builtin_amdgcn_perm((unsigned)col_dw(g, 3, h),
+                                                                   (unsigned)col_dw(g, 2, h), sel);
+                        v = __builtin_amdgcn_perm(p23, p01, 0x05040100u);
+                    }
+                    const int o = outer(8 * g + e);
+                    *(int *)&dst[o][16 * swz(o, t >> 6) + 4 * ((t >> 4) & 3)] = (int)v;
+                }
         }
     }
     // value of inner e (0 .. kNP-1) at outer slot r (0 .. kOuter-1)
     __device__ __forceinline__ float val(int r, int e) const
     {
         if (kInner) return elem<FP8>(w[r], e);
-        return elem_dw<FP8>(w[r >> 2][r & 3], e);
+        const int g = r >> 3, o = r & 7;  // raw column e holds outer o of group g
+        return FP8 ? elem_dw<true>(col_dw(g, e, o >> 2), o & 3)
+                   : elem_dw<false>(col_dw(g, e, o >> 1), o & 1);
     }
     // This step's operand checksum over the tile's outer indices, into
     // dst[p][slot]: complete (otherwise, slot 0, the 16 lanes of a row share
