@@ -298,24 +298,35 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 const int buf = s & 1;
                 store(buf);
                 __syncthreads();
+                // x_p, y_p of step s are complete; their gather is issued
+                // here and used after the step's first products
+                double yv = 0.0, xv = 0.0;
                 if (ABFT) {
-                    // x_p, y_p of step s are complete: the encoded checksums
-                    // and norms of step s, before ra/rb take step s + 1
-                    const double yv = gather<OpLoader<TB>::kParts>(sm.ys[buf], la.p());
-                    const double xv = gather<OpLoader<!TA>::kParts>(sm.xs[buf], lb.p());
-#pragma unroll
-                    for (int r = 0; r < EPT; ++r) {
-                        enc_a[r] += ra[r] * yv;
-                        enc_b[r] += xv * rb[r];
-                        nrm_a[r] += (float)(ra[r] * ra[r]);
-                        nrm_b[r] += (float)(rb[r] * rb[r]);
-                    }
-                    vy += (float)(yv * yv);
-                    vx += (float)(xv * xv);
+                    yv = gather<OpLoader<TB>::kParts>(sm.ys[buf], la.p());
+                    xv = gather<OpLoader<!TA>::kParts>(sm.xs[buf], lb.p());
                 }
-                if (s + 1 < nsteps) load(s + 1);
 #pragma unroll
                 for (int kk = 0; kk < BK / 4; ++kk) {
+                    if (kk == (ABFT ? 1 : 0)) {
+                        if (ABFT) {
+                            // the encoded checksums and norms of step s,
+                            // before ra/rb take step s + 1
+#pragma unroll
+                            for (int r = 0; r < EPT; ++r) {
+                                enc_a[r] += ra[r] * yv;
+                                enc_b[r] += xv * rb[r];
+                                // squares of the FP32-rounded values: two
+                                // instructions (convert, FP32 fma)
+                                const float fa = (float)ra[r], fb = (float)rb[r];
+                                nrm_a[r] = fmaf(fa, fa, nrm_a[r]);
+                                nrm_b[r] = fmaf(fb, fb, nrm_b[r]);
+                            }
+                            const float fy = (float)yv, fx = (float)xv;
+                            vy = fmaf(fy, fy, vy);
+                            vx = fmaf(fx, fx, vx);
+                        }
+                        if (s + 1 < nsteps) load(s + 1);
+                    }
                     double fa[4], fb[2];
 #pragma unroll
                     for (int mi = 0; mi < 4; ++mi)
