@@ -161,13 +161,21 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
     inj = rb.view()
     F.clear_fault_plan()
     name = "bf16" if dtype == F.BF16 else "fp8"
-    # flips the verification did not see: the change they made to the
-    # output against the thresholds of the flagged tiles
-    hit = {(r["row"], r["col"]) for r in inj.records}
+    # flips the verification did not see, and flips seen on one side only
+    # (a change between the row and the column threshold: classified as a
+    # checksum fault): the change they made to the output, against the
+    # thresholds of the flagged tiles
+    kinds = {(r["tile_m"], r["tile_n"]): r["kind"] for r in inj.records}
     taus = sorted(max(r["tau_row"], r["tau_col"]) for r in inj.records)
     alpha_p = sa * sb
-    missed = [abs(alpha_p * (e["after"] - e["before"])) for e in inj.echoes
-              if (e["row"], e["col"]) not in hit]
+    missed, one_side = [], []
+    for e in inj.echoes:
+        kind = kinds.get((e["row"] // tm, e["col"] // tn))
+        change = abs(alpha_p * (e["after"] - e["before"]))
+        if kind is None:
+            missed.append(change)
+        elif kind == F.KIND_CHECKSUM_ONLY:
+            one_side.append(change)
     achieved = flops / (t_ft_ev * 1e-3) / 1e12
     return {
         "tflops": round(flops / (t_ft * 1e-3) / 1e12, 3),
@@ -183,7 +191,9 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
                      "tflops": round(flops / (t_inj * 1e-3) / 1e12, 3),
                      "overhead_pct": round(100.0 * (t_inj / t_plain - 1.0), 2),
                      "corrected": int(inj.corrected), "detected": int(inj.detected),
+                     "checksum_only": int(inj.checksum_only),
                      "undetected_output_change": [float("%.4g" % d) for d in missed],
+                     "one_side_output_change": [float("%.4g" % d) for d in one_side],
                      "median_threshold": float("%.4g" % taus[len(taus) // 2]) if taus else None},
         "error_free_check": {"detected": int(clean.detected), "max_ratio": clean.max_ratio,
                              "tiles_verified": int(clean.tiles_verified)},
