@@ -27,6 +27,13 @@
  * X^r = e^T X (one entry per column).  Everything here is FP64 and
  * column-major, in the BLAS convention: op(A) is m x k, op(B) is k x n.
  *
+ * One-sided mode (one_sided = 1; the ranked extension "one-sided checksum plus
+ * recompute on detection" for the low-precision formats): only the column
+ * checksum C^c = C e of each tile is encoded and compared, one entry per row;
+ * any disagreeing row has the tile computed again, since one side can
+ * neither place the faulty column nor tell a data fault from a checksum
+ * fault.  Faults aimed at the row checksum have no entry to land on.
+ *
  * Pins (tests/test_oracle_*.py): the checksum identities e^T(AB) = (e^T A)B
  * and (AB)e = A(Be) bit-exactly on small-integer data; brute-force location
  * of single injected errors; bit-exact recovery of integer data; GEMM against
@@ -193,7 +200,8 @@ typedef struct {
     double lambda;             /* threshold multiplier                      */
     double mma_grid;           /* 0, or the truncation grid of a matrix     */
     int32_t mma_group;         /* instruction's group sums (see threshold)  */
-    int32_t pad;
+    int32_t one_sided;         /* 1: only the column checksum (one entry    */
+                               /* per row), recompute on any disagreement   */
 } oracle_params;
 
 /* Flip one bit of an accumulator held at the given precision. */
@@ -442,8 +450,8 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
         /* Faults aimed at the encoded checksums. */
         for (int64_t q = 0; attempt_faults && inj && q < ninj; ++q) {
             const oracle_injection *f = &inj[q];
-            if (f->target == TGT_ROW_CHECKSUM && f->col >= j0 && f->col < j0 + w &&
-                f->row >= i0 && f->row < i0 + h) {
+            if (f->target == TGT_ROW_CHECKSUM && !P->one_sided && f->col >= j0 &&
+                f->col < j0 + w && f->row >= i0 && f->row < i0 + h) {
                 double before = Pr[f->col - j0];
                 Pr[f->col - j0] = (f->mode == INJ_ADD) ? before + f->delta
                                                        : flip_bit(before, f->bit, 64);
@@ -488,7 +496,7 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
 
         /* Verify.  The comparison is written so that NaN residuals flag. */
         int64_t nbad_c = 0, nbad_r = 0, jbad = -1, ibad = -1;
-        for (int64_t jj = 0; jj < w; ++jj) {
+        for (int64_t jj = 0; !P->one_sided && jj < w; ++jj) {
             double d = Rr[jj] - Pr[jj];
             if (!(fabs(d) <= tr[jj])) {
                 if (nbad_c++ == 0) jbad = jj;
@@ -530,12 +538,16 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
             rec->after = rec->before;
         }
         if (!P->correct) {
-            if (rec) rec->kind = (nbad_r == 1 && nbad_c == 1) ? KIND_CORRECTED
+            if (rec) rec->kind = P->one_sided ? KIND_RECOMPUTED
+                               : (nbad_r == 1 && nbad_c == 1) ? KIND_CORRECTED
                                : (nbad_r + nbad_c == 1) ? KIND_CHECKSUM_ONLY
                                                         : KIND_RECOMPUTED;
             break;
         }
-        if (nbad_r == 1 && nbad_c == 1) {
+        if (P->one_sided) {
+            /* With one side the faulty column is unknown, and a checksum
+             * fault looks like a data fault: the tile is computed again. */
+        } else if (nbad_r == 1 && nbad_c == 1) {
             /* Locate at the crossing of the flagged row and column; rebuild
              * the element from the encoded row checksum and the rest of its
              * column (this also repairs NaN / Inf values), then confirm it

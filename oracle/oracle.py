@@ -70,7 +70,7 @@ class _Params(C.Structure):
                 ("alpha", C.c_double), ("beta", C.c_double), ("tm", C.c_int64),
                 ("tn", C.c_int64), ("bk", C.c_int64), ("acc_bits", C.c_int32),
                 ("correct", C.c_int32), ("lam", C.c_double), ("mma_grid", C.c_double),
-                ("mma_group", C.c_int32), ("pad", C.c_int32)]
+                ("mma_group", C.c_int32), ("one_sided", C.c_int32)]
 
 
 @dataclass
@@ -188,23 +188,25 @@ class Oracle:
 
     # -- fault-tolerant GEMM ----------------------------------------------
     def _params(self, A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, correct, lam,
-                mma=(0.0, 1)):
+                mma=(0.0, 1), one_sided=False):
         m, n, k = _dims(A, B, ta, tb)
         return _Params(int(ta), int(tb), m, n, k, max(1, A.shape[0]), max(1, B.shape[0]),
                        max(1, Cin.shape[0]), alpha, beta, tm, tn, bk, acc_bits,
-                       int(correct), lam, float(mma[0]), int(mma[1]), 0)
+                       int(correct), lam, float(mma[0]), int(mma[1]), int(bool(one_sided)))
 
     def ftgemm(self, A, B, Cin=None, alpha=1.0, beta=0.0, ta=False, tb=False, tm=128,
                tn=128, bk=16, acc_bits=64, injections=(), tiles=None, correct=True,
-               lam=DEFAULT_LAMBDA, mma=(0.0, 1)):
+               lam=DEFAULT_LAMBDA, mma=(0.0, 1), one_sided=False):
         """Fault-tolerant GEMM, tile by tile (Sections 2.2 and 2.3).  mma:
         (grid, group) of a multiplier that truncates its in-instruction
-        sums, which widens the thresholds; (0, 1) for exact sums."""
+        sums, which widens the thresholds; (0, 1) for exact sums.
+        one_sided: only the column checksum (one entry per row) is kept, and
+        a tile with any disagreeing row is computed again."""
         A, B = _f64(A), _f64(B)
         m, n, k = _dims(A, B, ta, tb)
         Cin = np.zeros((max(m, 1), max(n, 1)), order="F") if Cin is None else _f64(Cin)
         P = self._params(A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, correct, lam,
-                         mma)
+                         mma, one_sided)
         out = np.full((m, n), np.nan, order="F")
         raw = np.full((m, n), np.nan, order="F")
         inj = list(injections)

@@ -210,6 +210,53 @@ def pin_classification(orc):
     assert not r.records
 
 
+def pin_one_sided(orc):
+    """One-sided mode (only the column checksum, one entry per row;
+    recompute on any disagreement).  On integer data: each accumulator fault
+    flags exactly the row where the faulty output differs from the
+    fault-free product (brute force), with residual alpha * delta; the tile
+    is computed again and the output equals the fault-free product bit for
+    bit.  A fault on the column checksum of a row flags that row; one on
+    the row checksum has no entry to land on.  Fault-free: nothing flagged."""
+    g = synth.rng(92, 0, 0)
+    m, n, k = 37, 34, 40
+    A = np.asfortranarray(g.integers(-8, 9, (m, k)).astype(float))
+    B = np.asfortranarray(g.integers(-8, 9, (k, n)).astype(float))
+    Cin = np.asfortranarray(g.integers(-8, 9, (m, n)).astype(float))
+    Cff = 3.0 * (A @ B) + 2.0 * Cin
+    r = orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=8, one_sided=True)
+    assert np.array_equal(r.C, Cff) and not r.records
+    plan = [O.Injection(3, 4, 5, O.ADD, 1000.0),      # tile (0, 0)
+            O.Injection(20, 17, 39, O.ADD, -77.0),    # tile (1, 1), last step
+            O.Injection(36, 33, 0, O.ADD, 5.0)]       # corner tile (2, 2)
+    r = orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=8, injections=plan, one_sided=True)
+    assert np.array_equal(r.C, Cff)
+    rows = np.unique(np.argwhere(r.raw != Cff)[:, 0]).tolist()
+    assert rows == [3, 20, 36]
+    assert sorted(d["row"] for d in r.records) == rows
+    for d in r.records:
+        assert d["kind"] == O.RECOMPUTED and d["col"] == -1
+        assert d["nbad_rows"] == 1 and d["nbad_cols"] == 0
+        assert d["d_row"] == 0.0 and d["tau_row"] == 0.0
+        assert d["d_col"] == 3.0 * {3: 1000.0, 20: -77.0, 36: 5.0}[d["row"]]
+    # two faults in different rows of one tile: both rows flagged, one record
+    r = orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=8, one_sided=True, injections=[
+        O.Injection(17, 1, 3, O.ADD, 9.0), O.Injection(30, 12, 30, O.ADD, 4.0)])
+    assert [(d["kind"], d["row"], d["nbad_rows"]) for d in r.records] == [(O.RECOMPUTED, 17, 2)]
+    assert np.array_equal(r.C, Cff)
+    # checksum targets: the column checksum of row 20 is an entry, the row
+    # checksum of column 21 is not
+    r = orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=8, one_sided=True, injections=[
+        O.Injection(20, 21, 10, O.ADD, 50.0, target=O.TGT_COL_CHECKSUM),
+        O.Injection(5, 6, 10, O.ADD, 50.0, target=O.TGT_ROW_CHECKSUM)])
+    assert [(d["kind"], d["row"], d["d_col"]) for d in r.records] == [(O.RECOMPUTED, 20, -50.0)]
+    assert r.echo[0]["applied"] and not r.echo[1]["applied"]
+    assert np.array_equal(r.C, Cff)
+    # the two-sided mode on the same faults corrects instead
+    r = orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=8, injections=plan)
+    assert all(d["kind"] == O.CORRECTED for d in r.records) and np.array_equal(r.C, Cff)
+
+
 def pin_no_false_positives(orc):
     """Fault-free runs flag nothing, for both accumulator precisions, and the
     largest residual stays well inside its threshold."""
@@ -239,5 +286,5 @@ def pin_ragged_and_subset(orc):
 
 ALL_PINS = [pin_gemm_vs_numpy, pin_gemm_integer_exact, pin_blas_special_cases,
             pin_checksum_identities, pin_brute_force_location, pin_exact_recovery,
-            pin_nonfinite_recovery, pin_classification, pin_no_false_positives,
-            pin_ragged_and_subset]
+            pin_nonfinite_recovery, pin_classification, pin_one_sided,
+            pin_no_false_positives, pin_ragged_and_subset]
