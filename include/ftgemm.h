@@ -144,8 +144,20 @@ typedef struct {
 } ftgemm_injection;
 
 /* A GEMM described in full, for ftgemm_gemm_ex and ftgemm_gemm_batched.
- * abft = 0 runs the same kernel with every checksum operation compiled out
- * (the plain-GEMM baseline). */
+ * abft selects the fault tolerance:
+ *   0  the same kernel with every checksum operation compiled out (the
+ *      plain-GEMM baseline);
+ *   1  row and column checksums of every tile (Section 2.2): a single
+ *      error per tile is located and rebuilt;
+ *   2  one-sided (BF16 / FP8 single calls only; FTGEMM_ERR_UNSUPPORTED for
+ *      F64 and in batches): only the column checksum C e of each tile is
+ *      kept, one entry per row, and a tile with any disagreeing row is
+ *      computed again (records: kind RECOMPUTED, col -1).  The threshold
+ *      norms of the rows of op(A) and columns of op(B) are taken in one
+ *      pass over A and B before the product, using the library's
+ *      workspace.  Faults planned on the row checksum have no entry to land
+ *      on and are not applied.
+ * Other values are rejected (argument position 14). */
 typedef struct {
     ftgemm_dtype dtype;
     ftgemm_op transA, transB;
@@ -210,6 +222,14 @@ ftgemm_status ftgemm_set_fault_plan(const ftgemm_injection *plan, int32_t n);
 ftgemm_status ftgemm_query_tiling(ftgemm_dtype dtype, int64_t m, int64_t n, int64_t k,
                                   int32_t *tm, int32_t *tn, int32_t *bk,
                                   int32_t *split_k);
+
+/* The same for the call a descriptor describes (its dtype, abft, m, n, k;
+ * the other fields are not read): in the one-sided mode FP8 also takes
+ * 256 x 128 tiles from 256 tiles on.  Errors: desc NULL or its fields out of
+ * range (position 1), an output pointer NULL (position 2); one-sided F64
+ * returns FTGEMM_ERR_UNSUPPORTED. */
+ftgemm_status ftgemm_query_tiling_ex(const ftgemm_gemm_desc *desc, int32_t *tm, int32_t *tn,
+                                     int32_t *bk, int32_t *split_k);
 
 /* 1-based position of the argument rejected by the last call on this
  * thread that returned FTGEMM_ERR_INVALID_ARG (0 if none). */

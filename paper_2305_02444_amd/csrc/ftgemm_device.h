@@ -54,6 +54,10 @@ struct GemmArgs {
     int64_t slice_k;
     double *wsp;
     double *chk;
+    // one-sided low-precision mode: squared norms and largest magnitudes of
+    // the rows of op(A) (m each) and the columns of op(B) (n each), over
+    // the whole inner dimension, computed before the product
+    const double *row_nrm2, *row_max, *col_nrm2, *col_max;
 };
 
 // Slice checksum workspace: for slice s and tile t (tile_m + tile_n *

@@ -42,7 +42,8 @@ struct DeviceWs {
     ftgemm_fault_record *h_records = nullptr;
     ftgemm_injection_echo *h_echo = nullptr;
     int h_echo_cap = 0;
-    // split inner dimension: partial products, slice checksums
+    // split inner dimension (FP64): partial products, slice checksums; or
+    // the line norms of the one-sided low-precision mode
     double *split = nullptr;
     size_t split_bytes = 0;
     // auxiliary counters: [0] record slots, [1 ..] batched work queues
@@ -267,6 +268,7 @@ int check_args(const ftgemm_gemm_desc &d)
     if (d.dtype == FTGEMM_FP8_E4M3 &&
         !(std::isfinite(d.scaleA) && std::isfinite(d.scaleB) && d.scaleA > 0 && d.scaleB > 0))
         return 14;
+    if (d.abft < 0 || d.abft > 2) return 14;
     if (d.m > INT32_MAX / 2 || d.n > INT32_MAX / 2) return d.m > INT32_MAX / 2 ? 3 : 4;
     return 0;
 }
@@ -309,6 +311,7 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
         HIP_TRY(ftg::launch_scale(d.C, c_is_f64, d.m, d.n, d.ldc, d.beta, stream));
         return FTGEMM_OK;
     }
+    if (d.abft == 2 && d.dtype == FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
     if (d.dtype != FTGEMM_F64 && d.abft)
         for (const ftgemm_injection &f : g_plan)  // FP32 accumulators have 32 bits
@@ -320,8 +323,28 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
     if (d.dtype == FTGEMM_F64)
         ftg::tiling_f64(&tm, &tn, &bk);
     else
-        ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft != 0, d.m, d.n, false, &tm, &tn, &bk);
+        ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, &tm, &tn, &bk);
     GemmArgs g = base_args(d, tm, tn);
+    const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
+    if (d.abft == 2) {
+        // line norms of op(A) (rows) and op(B) (columns) for the thresholds
+        const bool fp8 = d.dtype == FTGEMM_FP8_E4M3;
+        const int64_t part = std::max<int64_t>(int64_t(1) << 22, 2 * std::max(d.m, d.n));
+        if (ftgemm_status st = split_space(*ws, sizeof(double) * (2 * (d.m + d.n) + part)))
+            return st;
+        double *nb = ws->split;
+        g.row_nrm2 = nb;
+        g.row_max = nb + d.m;
+        g.col_nrm2 = nb + 2 * d.m;
+        g.col_max = nb + 2 * d.m + d.n;
+        double *pw = nb + 2 * (d.m + d.n);
+        // op(A) row i is stored row i (N) or stored column i (T); op(B)
+        // column j is stored column j (N) or stored row j (T)
+        HIP_TRY(ftg::launch_line_norms(d.A, d.lda, ta ? d.k : d.m, ta ? d.m : d.k, fp8, !ta,
+                                       nb, nb + d.m, pw, part, stream));
+        HIP_TRY(ftg::launch_line_norms(d.B, d.ldb, tb ? d.n : d.k, tb ? d.k : d.n, fp8, tb,
+                                       nb + 2 * d.m, nb + 2 * d.m + d.n, pw, part, stream));
+    }
     int64_t slice_k = d.k;
     const int nslices =
         d.dtype == FTGEMM_F64 ? choose_split(d.m, d.n, d.k, tm, tn, bk, &slice_k) : 1;
@@ -346,7 +369,6 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
     if (rep && d.abft)
         HIP_TRY(ftg::launch_clear_report(ws->counters, 1, ws->echo, ws->nplan, ws->aux, 1,
                                          stream));
-    const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
     if (d.dtype == FTGEMM_F64) {
         HIP_TRY(ftg::launch_f64(g, ta, tb, d.abft != 0, stream));
         if (nslices > 1) {
@@ -370,7 +392,7 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
             HIP_TRY(ftg::launch_splitk_reduce(r, d.abft != 0, stream));
         }
     } else
-        HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft != 0, tm, stream));
+        HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft, tm, stream));
     if (rep && d.abft) {
         HIP_TRY(hipMemcpyAsync(ws->h_counters, ws->counters, sizeof(DevCounters),
                                hipMemcpyDeviceToHost, stream));
@@ -545,7 +567,7 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
         if (int pos = check_args(descs[p])) return invalid(pos);
         const ftgemm_gemm_desc &d = descs[p];
         if (d.dtype != descs[0].dtype || (d.abft != 0) != (descs[0].abft != 0) ||
-            d.transA != descs[0].transA || d.transB != descs[0].transB)
+            d.transA != descs[0].transA || d.transB != descs[0].transB || d.abft == 2)
             return FTGEMM_ERR_UNSUPPORTED;
         if (reps && ((reps[p].record_capacity && !reps[p].records) ||
                      (reps[p].echo_capacity && !reps[p].echoes)))
@@ -567,7 +589,7 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
     if (d0.dtype == FTGEMM_F64)
         ftg::tiling_f64(&tm, &tn, &bk);
     else
-        ftg::tiling_lp(d0.dtype == FTGEMM_FP8_E4M3, d0.abft != 0, 0, 0, true, &tm, &tn, &bk);
+        ftg::tiling_lp(d0.dtype == FTGEMM_FP8_E4M3, d0.abft, 0, 0, true, &tm, &tn, &bk);
     std::vector<ftg::GemmArgs> probs(count);
     std::vector<int> live;
     uint64_t sig = 0xcbf29ce484222325ull;
@@ -775,7 +797,35 @@ ftgemm_status ftgemm_query_tiling(ftgemm_dtype dtype, int64_t m, int64_t n, int6
         ftg::tiling_f64(&a, &b, &c);
         s = choose_split(m, n, k, a, b, c, &slice_k);
     } else {
-        ftg::tiling_lp(dtype == FTGEMM_FP8_E4M3, true, m, n, false, &a, &b, &c);
+        ftg::tiling_lp(dtype == FTGEMM_FP8_E4M3, 1, m, n, false, &a, &b, &c);
+    }
+    *tm = a;
+    *tn = b;
+    *bk = c;
+    *split_k = s;
+    return FTGEMM_OK;
+}
+
+ftgemm_status ftgemm_query_tiling_ex(const ftgemm_gemm_desc *desc, int32_t *tm, int32_t *tn,
+                                     int32_t *bk, int32_t *split_k)
+{
+    t_last_invalid = 0;
+    if (!desc) return invalid(1);
+    const ftgemm_gemm_desc &d = *desc;
+    if (d.dtype != FTGEMM_F64 && d.dtype != FTGEMM_BF16 && d.dtype != FTGEMM_FP8_E4M3)
+        return invalid(1);
+    if (d.abft < 0 || d.abft > 2) return invalid(1);
+    if (d.m < 0 || d.n < 0 || d.k < 0) return invalid(1);
+    if (!tm || !tn || !bk || !split_k) return invalid(2);
+    if (d.abft == 2 && d.dtype == FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
+    int a = 0, b = 0, c = 0;
+    int64_t slice_k = d.k;
+    int s = 1;
+    if (d.dtype == FTGEMM_F64) {
+        ftg::tiling_f64(&a, &b, &c);
+        s = choose_split(d.m, d.n, d.k, a, b, c, &slice_k);
+    } else {
+        ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, &a, &b, &c);
     }
     *tm = a;
     *tn = b;

@@ -12,14 +12,23 @@ hipError_t launch_f64(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_
 void tiling_f64(int *tm, int *tn, int *bk);
 
 // BF16 / FP8 E4M3 tile kernel (FP32 accumulation and output, one tm x 128
-// output tile per workgroup, tm = 128 or 256 as tiling_lp chose).
-hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, bool abft, int tm,
+// output tile per workgroup, tm = 128 or 256 as tiling_lp chose).  mode: 0
+// without checksums, 1 fault-tolerant, 2 one-sided (g's line norms set).
+hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode, int tm,
                      hipStream_t stream);
-// Tile of an m x n low-precision output, with or without fault tolerance
-// (batched: the batched kernel's tile).
+// Tile of an m x n low-precision output in a mode (batched: the batched
+// kernel's tile).
 constexpr int64_t kLargeTileMin = 256;  // 256-row tiles from this many tiles on
-void tiling_lp(bool fp8, bool abft, int64_t m, int64_t n, bool batched, int *tm, int *tn,
+void tiling_lp(bool fp8, int mode, int64_t m, int64_t n, bool batched, int *tm, int *tn,
                int *bk);
+
+// Squared norms and largest magnitudes of the lines of a column-major R x Cn
+// matrix of BF16 / E4M3 codes: of each row (along_rows; R results) or of
+// each column (Cn results).  Row sums use part (at least 2 R doubles; more
+// lets the columns be split into more chunks).
+hipError_t launch_line_norms(const void *X, int64_t ld, int64_t R, int64_t Cn, bool fp8,
+                             bool along_rows, double *nrm2, double *amax, double *part,
+                             int64_t part_cap, hipStream_t stream);
 
 // Verified reduction of a split inner dimension (FP64): C = alpha * sum_s
 // W_s + beta * C, checked against the slices' encoded checksums.

@@ -391,6 +391,8 @@ struct LpLoader {
     // Encoded checksum (with the other operand's checksum v, indexed like
     // this thread's inner values) and squared norms over this step.
     // (FP8: amx tracks the largest magnitude for the truncation term.)
+    // (kNrm false: the encoded checksum only.)
+    template <bool kNrm = true>
     __device__ __forceinline__ void encode(const float (&v)[kNP], float (&enc)[kOuter],
                                            float (&nrm)[kOuter], float &amx) const
     {
@@ -400,8 +402,8 @@ struct LpLoader {
             for (int e = 0; e < kNP; ++e) {
                 const float a = val(r, e);
                 enc[r] = fmaf(a, v[e], enc[r]);
-                nrm[r] = fmaf(a, a, nrm[r]);
-                if (FP8) amx = fmaxf(amx, fabsf(a));
+                if (kNrm) nrm[r] = fmaf(a, a, nrm[r]);
+                if (FP8 && kNrm) amx = fmaxf(amx, fabsf(a));
             }
     }
     // Per-outer sums completed over the threads holding the same outer
@@ -466,13 +468,18 @@ __device__ __forceinline__ int owner_reg(int row, int col)
     return ((row & 63) >> 4) * (4 * Geo<BM>::NI) + ((col % Geo<BM>::WC) >> 4) * 4 + (row & 3);
 }
 
-template <bool FP8, bool TA, bool TB, bool ABFT, int BM>
+// ONE: the one-sided mode -- only the column checksum of the tile (one
+// entry per row, C^c = C e) is encoded and verified, any disagreement has the
+// tile computed again, and the threshold norms come from g.row_nrm2 /
+// g.col_nrm2 / g.row_max / g.col_max instead of the staged operands.
+template <bool FP8, bool TA, bool TB, bool ABFT, int BM, bool ONE = false>
 __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
 {
     using E = Elem<FP8>;
     using G = Geo<BM>;
     constexpr int NI = G::NI, NA = G::NA;
     constexpr bool kMma = !FP8;  // BF16: encoded checksums on the matrix cores
+    constexpr bool kOne = ABFT && ONE;
     // the checksum products of step s run during step s + 1
     constexpr bool kLag = kMma && ABFT;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -519,9 +526,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
     // (hb, ha) read while the step was the current one.
     auto check_products = [&](const Stage<BM> &st, int kk, const bf8v &hb, const bf8v (&ha)[NA],
                               f4 &acc_r, f4 (&acc_c)[NA]) {
-        const bf8v fxa = *(const bf8v *)&st.A[BM + c16][16 * swz(BM + c16, 4 * kk + q)];
         const bf8v fyb = *(const bf8v *)&st.B[TN + c16][16 * swz(TN + c16, 4 * kk + q)];
-        acc_r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxa, hb, acc_r, 0, 0, 0);
+        if (!kOne) {
+            const bf8v fxa = *(const bf8v *)&st.A[BM + c16][16 * swz(BM + c16, 4 * kk + q)];
+            acc_r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxa, hb, acc_r, 0, 0, 0);
+        }
 #pragma unroll
         for (int h = 0; h < NA; ++h)
             acc_c[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[h], fyb, acc_c[h], 0, 0, 0);
@@ -563,8 +572,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
 
         load(0);
         if (ABFT) {
-            la.template sum_to<kMma>(sm.xs[0], nrm_a);
-            lb.template sum_to<kMma>(sm.ys[0], nrm_b);
+            if (!kOne) la.template sum_to<kMma>(sm.xs[0], nrm_a);
+            lb.template sum_to<kMma && !kOne>(sm.ys[0], nrm_b);
         }
         int s = 0;
 #pragma unroll 1
@@ -586,32 +595,38 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                     // extra rows, for the checksum products of step s (run
                     // during step s + 1, after its barrier)
                     if (t < E::BK) {
-                        const float xp = gather_lp<LA::kParts>(sm.xs[stg], t);
                         const float yp = gather_lp<LB::kParts>(sm.ys[stg], t);
-                        vx = fmaf(xp, xp, vx);
                         vy = fmaf(yp, yp, vy);
-                        put_parts(sm.u.st[stg].A, BM, t, xp);
                         put_parts(sm.u.st[stg].B, TN, t, yp);
+                        if (!kOne) {
+                            const float xp = gather_lp<LA::kParts>(sm.xs[stg], t);
+                            vx = fmaf(xp, xp, vx);
+                            put_parts(sm.u.st[stg].A, BM, t, xp);
+                        }
                     }
                 } else if (ABFT) {
                     // x_p, y_p of step s are complete: combined once (one
                     // thread per p), then the encoded checksums and norms of
                     // step s, before the registers take step s + 1
                     if (t < E::BK) {
-                        const float xp = gather_lp<LA::kParts>(sm.xs[stg], t);
                         const float yp = gather_lp<LB::kParts>(sm.ys[stg], t);
-                        vx = fmaf(xp, xp, vx);
                         vy = fmaf(yp, yp, vy);
-                        sm.xc[t] = xp;
                         sm.yc[t] = yp;
+                        if (!kOne) {
+                            const float xp = gather_lp<LA::kParts>(sm.xs[stg], t);
+                            vx = fmaf(xp, xp, vx);
+                            sm.xc[t] = xp;
+                        }
                     }
                     __syncthreads();
 #pragma unroll
                     for (int e = 0; e < LA::kNP; ++e) yv[e] = sm.yc[la.p0() + e];
+                    la.template encode<!kOne>(yv, enc_a, nrm_a, amx_a);
+                    if (!kOne) {
 #pragma unroll
-                    for (int e = 0; e < LB::kNP; ++e) xv[e] = sm.xc[lb.p0() + e];
-                    la.encode(yv, enc_a, nrm_a, amx_a);
-                    lb.encode(xv, enc_b, nrm_b, amx_b);
+                        for (int e = 0; e < LB::kNP; ++e) xv[e] = sm.xc[lb.p0() + e];
+                        lb.encode(xv, enc_b, nrm_b, amx_b);
+                    }
                 }
                 if (s + 1 < nsteps) load(s + 1);
 #pragma unroll
@@ -639,7 +654,9 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                                 check_products(sm.u.st[stg ^ 1], kk, hold_b[kk], hold_a[kk], acc_r,
                                                acc_c);
                             const int rb = wn * G::WC + 16 * wm + c16;
-                            hold_b[kk] = *(const bf8v *)&sm.u.st[stg].B[rb][16 * swz(rb, 4 * kk + q)];
+                            if (!kOne)
+                                hold_b[kk] =
+                                    *(const bf8v *)&sm.u.st[stg].B[rb][16 * swz(rb, 4 * kk + q)];
 #pragma unroll
                             for (int h = 0; h < NA; ++h) {
                                 const int ra = 64 * wm + 16 * (NA * wn + h) + c16;
@@ -675,8 +692,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                 }
                 if (ABFT && s + 1 < nsteps) {
                     // operand checksums of step s + 1, published before its barrier
-                    la.template sum_to<kMma>(sm.xs[stg ^ 1], nrm_a);
-                    lb.template sum_to<kMma>(sm.ys[stg ^ 1], nrm_b);
+                    if (!kOne) la.template sum_to<kMma>(sm.xs[stg ^ 1], nrm_a);
+                    lb.template sum_to<kMma && !kOne>(sm.ys[stg ^ 1], nrm_b);
                 }
             }
             if (ABFT && faults_on) {
@@ -752,21 +769,23 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                     for (int r = 0; r < 4; ++r)
                         sm.u.epi.enc_row[c16][64 * wm + 16 * (NA * wn + h) + 4 * q + r] =
                             (double)acc_c[h][r];
-            if (q == 0)
+            if (!kOne && q == 0)
                 sm.u.epi.enc_col[0][wn * G::WC + 16 * wm + c16] =
                     ((double)acc_r[0] + (double)acc_r[1]) + (double)acc_r[2];
         } else {
             la.partials_to(enc_a, sm.u.epi.enc_row);
-            lb.partials_to(enc_b, sm.u.epi.enc_col);
+            if (!kOne) lb.partials_to(enc_b, sm.u.epi.enc_col);
         }
-        la.partials_to(nrm_a, sm.u.epi.nrm_row);
-        lb.partials_to(nrm_b, sm.u.epi.nrm_col);
+        if (!kOne) {
+            la.partials_to(nrm_a, sm.u.epi.nrm_row);
+            lb.partials_to(nrm_b, sm.u.epi.nrm_col);
+        }
         // |x|^2 and |y|^2: threads t < BK took one p each
         {
-            const double sx = sum64(t < E::BK ? (double)vx : 0.0);
+            const double sx = kOne ? 0.0 : sum64(t < E::BK ? (double)vx : 0.0);
             const double sy = sum64(t < E::BK ? (double)vy : 0.0);
-            const double ma = FP8 ? max64((double)amx_a) : 0.0;
-            const double mb = FP8 ? max64((double)amx_b) : 0.0;
+            const double ma = FP8 && !kOne ? max64((double)amx_a) : 0.0;
+            const double mb = FP8 && !kOne ? max64((double)amx_b) : 0.0;
             if (lane == 0) {
                 sm.wsum[w][0] = sx; sm.wsum[w][1] = sy; sm.wsum[w][3] = ma; sm.wsum[w][4] = mb;
             }
@@ -820,8 +839,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         double nrm2 = 0.0;
         if (is_row) {
             double e = 0, nr = 0;
+            if (kOne)
+                nr = x < hrows ? g.row_nrm2[i0 + x] : 0.0;
+            else
 #pragma unroll
-            for (int v = 0; v < LA::kOuterParts; ++v) nr += sm.u.epi.nrm_row[v][x];
+                for (int v = 0; v < LA::kOuterParts; ++v) nr += sm.u.epi.nrm_row[v][x];
             if (kMma) {
                 e = (sm.u.epi.enc_row[0][x] + sm.u.epi.enc_row[1][x]) + sm.u.epi.enc_row[2][x];
             } else {
@@ -830,6 +852,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
             }
             nrm2 = nr;
             sm.u.epi.fin_row[x] = e;
+        } else if (is_col && kOne) {
+            nrm2 = x < wcols ? g.col_nrm2[j0 + x] : 0.0;
         } else if (is_col) {
             double e = 0, nr = 0;
 #pragma unroll
@@ -848,6 +872,13 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         if (w < G::kVW) {
             const double f = sum64(nrm2);
             if (lane == 0) sm.wsum[w][2] = f;
+            if (kOne && FP8) {
+                // the tile's largest magnitudes, from the per-line maxima
+                const double ra = is_row && x < hrows ? g.row_max[i0 + x] : 0.0;
+                const double cb = is_col && x < wcols ? g.col_max[j0 + x] : 0.0;
+                const double a = max64(ra), b = max64(cb);
+                if (lane == 0) { sm.wsum[w][3] = a; sm.wsum[w][4] = b; }
+            }
         }
         __syncthreads();
         if (t == 0) {
@@ -872,7 +903,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         {
             const double sqk = sqrt((double)k);
             double ratio = 0.0;
-            if (is_row || is_col) {
+            if (is_row || (is_col && !kOne)) {
                 double P = g.alpha * (is_row ? sm.u.epi.fin_row[x] : sm.u.epi.fin_col[x]);
                 double R = 0.0, cs = 0.0, c2 = 0.0;
                 if (is_row) {
@@ -955,7 +986,10 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         first_i = nr ? sm.ibad : -1;
         first_j = nc ? sm.jbad : -1;
 
-        if (nr == 1 && nc == 1) {
+        if (kOne) {
+            // one side: neither the column of a data fault nor a checksum
+            // fault can be told apart -- the tile is computed again
+        } else if (nr == 1 && nc == 1) {
             const int is = first_i, js = first_j;
             double s_col = 0.0, s_row = 0.0;
 #pragma unroll
@@ -1067,13 +1101,13 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
     }
 }
 
-template <bool FP8, bool TA, bool TB, bool ABFT, int BM>
+template <bool FP8, bool TA, bool TB, bool ABFT, int BM, bool ONE>
 __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
 {
     __shared__ Smem<BM> sm;
     int tm_, tn_;
     map_tile(blockIdx.x, g.tiles_m, g.tiles_n, tm_, tn_);
-    tile<FP8, TA, TB, ABFT, BM>(g, tm_, tn_, sm);
+    tile<FP8, TA, TB, ABFT, BM, ONE>(g, tm_, tn_, sm);
 }
 
 // Tile rows of the batched kernel (problems of mixed, often small, shapes).
@@ -1127,38 +1161,39 @@ hipError_t launch_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int g
 }
 
 template <bool FP8, int BM>
-hipError_t launch(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream)
+hipError_t launch(const GemmArgs &g, bool ta, bool tb, int mode, hipStream_t stream)
 {
     const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n;
     if (grid == 0) return hipSuccess;
-#define FTG_LP_CASE(a, b, c) \
-    hipLaunchKernelGGL((kernel<FP8, a, b, c, BM>), dim3(grid), dim3(NT), 0, stream, g)
-    if (abft) {
-        if (!ta && !tb) FTG_LP_CASE(false, false, true);
-        else if (!ta && tb) FTG_LP_CASE(false, true, true);
-        else if (ta && !tb) FTG_LP_CASE(true, false, true);
-        else FTG_LP_CASE(true, true, true);
-    } else {
-        if (!ta && !tb) FTG_LP_CASE(false, false, false);
-        else if (!ta && tb) FTG_LP_CASE(false, true, false);
-        else if (ta && !tb) FTG_LP_CASE(true, false, false);
-        else FTG_LP_CASE(true, true, false);
-    }
+#define FTG_LP_CASE(a, b, c, d) \
+    hipLaunchKernelGGL((kernel<FP8, a, b, c, BM, d>), dim3(grid), dim3(NT), 0, stream, g)
+#define FTG_LP_MODE(c, d)                                   \
+    do {                                                    \
+        if (!ta && !tb) FTG_LP_CASE(false, false, c, d);    \
+        else if (!ta && tb) FTG_LP_CASE(false, true, c, d); \
+        else if (ta && !tb) FTG_LP_CASE(true, false, c, d); \
+        else FTG_LP_CASE(true, true, c, d);                 \
+    } while (0)
+    if (mode == 2) FTG_LP_MODE(true, true);
+    else if (mode == 1) FTG_LP_MODE(true, false);
+    else FTG_LP_MODE(false, false);
+#undef FTG_LP_MODE
 #undef FTG_LP_CASE
     return hipGetLastError();
 }
 
 }  // namespace lp
 
-hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, bool abft, int tm,
+hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode, int tm,
                      hipStream_t stream)
 {
+    if (mode < 0 || mode > 2) return hipErrorInvalidValue;
     if (tm == 256)
-        return fp8 ? lp::launch<true, 256>(g, ta, tb, abft, stream)
-                   : lp::launch<false, 256>(g, ta, tb, abft, stream);
+        return fp8 ? lp::launch<true, 256>(g, ta, tb, mode, stream)
+                   : lp::launch<false, 256>(g, ta, tb, mode, stream);
     if (tm != 128) return hipErrorInvalidValue;
-    return fp8 ? lp::launch<true, 128>(g, ta, tb, abft, stream)
-               : lp::launch<false, 128>(g, ta, tb, abft, stream);
+    return fp8 ? lp::launch<true, 128>(g, ta, tb, mode, stream)
+               : lp::launch<false, 128>(g, ta, tb, mode, stream);
 }
 
 hipError_t launch_lp_batched(const BatchArgs &b, bool fp8, bool ta, bool tb, bool abft, int grid,
@@ -1170,14 +1205,14 @@ hipError_t launch_lp_batched(const BatchArgs &b, bool fp8, bool ta, bool tb, boo
 
 // 256-row tiles once they still give every compute unit a tile (they do
 // twice the matrix work per staged byte of the 128-row tiles), 128 rows
-// otherwise and in batches.  The fault-tolerant FP8 kernel keeps 128-row
-// tiles: at 256 rows its per-row checksum and norm registers no longer fit
-// beside the accumulators and it spills inside the main loop.
-void tiling_lp(bool fp8, bool abft, int64_t m, int64_t n, bool batched, int *tm, int *tn,
+// otherwise and in batches.  The two-sided fault-tolerant FP8 kernel keeps
+// 128-row tiles: at 256 rows its per-row checksum and norm registers no
+// longer fit beside the accumulators and it spills inside the main loop.
+void tiling_lp(bool fp8, int mode, int64_t m, int64_t n, bool batched, int *tm, int *tn,
                int *bk)
 {
     const int64_t tiles256 = ((m + 255) / 256) * ((n + lp::TN - 1) / lp::TN);
-    const bool large = !batched && !(fp8 && abft) && tiles256 >= kLargeTileMin;
+    const bool large = !batched && !(fp8 && mode == 1) && tiles256 >= kLargeTileMin;
     *tm = large ? 256 : lp::kBatchBM;
     *tn = lp::TN;
     *bk = fp8 ? lp::Elem<true>::BK : lp::Elem<false>::BK;

@@ -98,6 +98,8 @@ def lib():
         L.ftgemm_set_fault_plan.argtypes = [C.POINTER(Injection), C.c_int32]
         L.ftgemm_query_tiling.restype = C.c_int
         L.ftgemm_query_tiling.argtypes = [C.c_int, i64, i64, i64] + [C.POINTER(C.c_int32)] * 4
+        L.ftgemm_query_tiling_ex.restype = C.c_int
+        L.ftgemm_query_tiling_ex.argtypes = [C.POINTER(GemmDesc)] + [C.POINTER(C.c_int32)] * 4
         L.ftgemm_last_invalid_arg.restype = C.c_int32
         L.ftgemm_last_invalid_arg.argtypes = []
         L.ftgemm_status_string.restype = C.c_char_p
@@ -229,7 +231,8 @@ def make_desc(A, B, Cm, alpha=1.0, beta=0.0, transA=False, transB=False, abft=Tr
     d.dtype = _dtype_code(A) if dtype is None else dtype
     d.transA = OP_T if transA else OP_N
     d.transB = OP_T if transB else OP_N
-    d.abft = 1 if abft else 0
+    # abft: False / True, or the mode number (0, 1, 2 = one-sided)
+    d.abft = int(abft) if not isinstance(abft, bool) else (1 if abft else 0)
     d.m, d.n, d.k = m, n, k
     d.lda, d.ldb, d.ldc = _ld(A), _ld(B), _ld(Cm)
     d.alpha, d.beta = float(alpha), float(beta)
@@ -288,4 +291,14 @@ def query_tiling(dtype, m, n, k):
     v = [C.c_int32() for _ in range(4)]
     _check(lib().ftgemm_query_tiling(dtype, m, n, k, *[C.byref(x) for x in v]),
            "ftgemm_query_tiling")
+    return tuple(x.value for x in v)
+
+
+def query_tiling_ex(dtype, m, n, k, abft=1):
+    """Tiling of the call with this dtype, shape and abft mode."""
+    d = GemmDesc()
+    d.dtype, d.abft, d.m, d.n, d.k = dtype, int(abft), m, n, k
+    v = [C.c_int32() for _ in range(4)]
+    _check(lib().ftgemm_query_tiling_ex(C.byref(d), *[C.byref(x) for x in v]),
+           "ftgemm_query_tiling_ex")
     return tuple(x.value for x in v)

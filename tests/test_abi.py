@@ -59,6 +59,47 @@ def test_gemm_ex_descriptor_checks():
     assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
 
 
+def test_abft_modes_checked_on_the_host():
+    """abft outside 0..2 is an argument error; the one-sided mode (2) is
+    refused for FP64 and in batches before anything runs."""
+    L = F.lib()
+    d = F.GemmDesc()
+    d.dtype, d.m, d.n, d.k, d.lda, d.ldb, d.ldc = F.BF16, 4, 4, 4, 4, 4, 4
+    d.alpha, d.scaleA, d.scaleB, d.A, d.B, d.C = 1.0, 1.0, 1.0, 1, 1, 1
+    for bad in (-1, 3, 7):
+        d.abft = bad
+        assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+        assert L.ftgemm_last_invalid_arg() == 14
+    d.dtype, d.abft = F.F64, 2
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_UNSUPPORTED
+    d.dtype = F.BF16
+    assert L.ftgemm_gemm_batched(1, C.byref(d), None, None) == F.ERR_UNSUPPORTED
+
+
+def test_query_tiling_ex():
+    """The tiling of the call a descriptor describes: the one-sided mode
+    also gives FP8 256-row tiles; modes 0 and 1 agree with
+    ftgemm_query_tiling where it speaks for them."""
+    for dt in (F.F64, F.BF16, F.FP8_E4M3):
+        for shape in ((8192, 8192, 8192), (1000, 1000, 300), (1024, 1024, 32768)):
+            assert F.query_tiling_ex(dt, *shape, abft=1) == F.query_tiling(dt, *shape)
+    assert F.query_tiling_ex(F.FP8_E4M3, 8192, 8192, 8192, abft=2) == (256, 128, 128, 1)
+    assert F.query_tiling_ex(F.FP8_E4M3, 8192, 8192, 8192, abft=0) == (256, 128, 128, 1)
+    assert F.query_tiling_ex(F.BF16, 8192, 8192, 8192, abft=2) == (256, 128, 64, 1)
+    assert F.query_tiling_ex(F.FP8_E4M3, 1000, 1000, 300, abft=2) == (128, 128, 128, 1)
+    L = F.lib()
+    v = [C.c_int32() for _ in range(4)]
+    assert L.ftgemm_query_tiling_ex(None, *[C.byref(x) for x in v]) == F.ERR_INVALID_ARG
+    d = F.GemmDesc()
+    d.dtype, d.abft, d.m, d.n, d.k = F.F64, 2, 64, 64, 64
+    assert L.ftgemm_query_tiling_ex(C.byref(d), *[C.byref(x) for x in v]) == F.ERR_UNSUPPORTED
+    d.abft = 5
+    assert L.ftgemm_query_tiling_ex(C.byref(d), *[C.byref(x) for x in v]) == F.ERR_INVALID_ARG
+    d.abft = 1
+    assert L.ftgemm_query_tiling_ex(C.byref(d), None, None, None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 2
+
+
 def test_fault_plan_validation():
     L = F.lib()
     bad = F.Injection(0, 5, 0, 0, 1, 1, 1, 1.0)  # unknown mode
