@@ -162,6 +162,8 @@ enum { INJ_ADD = 0, INJ_BITFLIP = 1 };
 enum { TGT_ACC = 0, TGT_ROW_CHECKSUM = 1, TGT_COL_CHECKSUM = 2 };
 enum { KIND_CORRECTED = 1, KIND_CHECKSUM_ONLY = 2, KIND_RECOMPUTED = 3,
        KIND_UNCORRECTABLE = 4 };
+/* Largest number of elements rebuilt along one line of a tile. */
+#define MAX_LINE_FIXES 4
 
 /* One planned soft error.  It lands after the inner-dimension step (of
  * length bk) that contains k_index has been accumulated.  TGT_ACC hits the
@@ -547,20 +549,53 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
         if (P->one_sided) {
             /* With one side the faulty column is unknown, and a checksum
              * fault looks like a data fault: the tile is computed again. */
-        } else if (nbad_r == 1 && nbad_c == 1) {
-            /* Locate at the crossing of the flagged row and column; rebuild
-             * the element from the encoded row checksum and the rest of its
-             * column (this also repairs NaN / Inf values), then confirm it
-             * against the encoded column checksum of its row. */
-            double sr = 0.0, sc = 0.0;
-            for (int64_t ii = 0; ii < h; ++ii)
-                if (ii != ibad) sr += out[ii + jbad * h];
-            for (int64_t jj = 0; jj < w; ++jj)
-                if (jj != jbad) sc += out[ibad + jj * h];
-            double fixed = Pr[jbad] - sr;
-            if (fabs(sc + fixed - Pc[ibad]) <= tc[ibad]) {
-                out[ibad + jbad * h] = fixed;
-                if (rec) { rec->kind = KIND_CORRECTED; rec->after = fixed; }
+        } else if ((nbad_r == 1 && nbad_c >= 1 && nbad_c <= MAX_LINE_FIXES) ||
+                   (nbad_c == 1 && nbad_r >= 2 && nbad_r <= MAX_LINE_FIXES)) {
+            /* The errors lie on one line: the flagged row (one flagged row,
+             * up to MAX_LINE_FIXES flagged columns) or the flagged column.
+             * Each element where the line crosses a flagged entry of the
+             * other side is rebuilt from that entry's encoded checksum and
+             * the rest of its column (row) -- NaN / Inf values included --
+             * and the line is then confirmed against its own encoded
+             * checksum.  One row and one column is the single-error case. */
+            const int by_row = (nbad_r == 1);
+            const int64_t line = by_row ? ibad : jbad;
+            const int64_t len = by_row ? w : h;       /* elements on the line */
+            const int64_t across = by_row ? h : w;    /* elements across it  */
+            double fixed[MAX_LINE_FIXES];
+            int64_t at[MAX_LINE_FIXES];
+            int nfix = 0;
+            double rest = 0.0;   /* the line's elements that are kept */
+            for (int64_t x = 0; x < len; ++x) {
+                const int64_t ii = by_row ? line : x, jj = by_row ? x : line;
+                const double d = by_row ? Rr[x] - Pr[x] : Rc[x] - Pc[x];
+                const double tau = by_row ? tr[x] : tc[x];
+                if (!(fabs(d) <= tau)) {
+                    double s = 0.0;   /* the rest of the crossing column (row) */
+                    for (int64_t y = 0; y < across; ++y) {
+                        if (y == line) continue;
+                        s += by_row ? out[y + x * h] : out[x + y * h];
+                    }
+                    at[nfix] = x;
+                    fixed[nfix++] = (by_row ? Pr[x] : Pc[x]) - s;
+                } else {
+                    rest += out[ii + jj * h];
+                }
+            }
+            double total = rest;
+            for (int f = 0; f < nfix; ++f) total += fixed[f];
+            const double target = by_row ? Pc[line] : Pr[line];
+            const double tau = by_row ? tc[line] : tr[line];
+            if (fabs(total - target) <= tau) {
+                for (int f = 0; f < nfix; ++f) {
+                    const int64_t ii = by_row ? line : at[f], jj = by_row ? at[f] : line;
+                    out[ii + jj * h] = fixed[f];
+                }
+                if (rec) {
+                    /* the record names the first rebuilt element */
+                    rec->kind = KIND_CORRECTED;
+                    rec->after = fixed[0];
+                }
                 break;
             }
         } else if (nbad_r + nbad_c == 1) {

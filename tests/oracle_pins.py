@@ -184,10 +184,11 @@ def pin_classification(orc):
     r = orc.ftgemm(A, B, tm=16, tn=16, bk=16, injections=ck)
     assert [d["kind"] for d in r.records] == [O.CHECKSUM_ONLY]
     assert r.records[0]["row"] == 20 and r.records[0]["col"] == -1
-    # two errors in one row: one row and two columns disagree -> recomputed
+    # two errors in one row: one row and two columns disagree -> both
+    # rebuilt from their columns and confirmed by the row
     r = orc.ftgemm(A, B, tm=16, tn=16, bk=16, injections=[
         O.Injection(3, 1, 3, O.ADD, 5.0), O.Injection(3, 7, 30, O.ADD, 8.0)])
-    assert [d["kind"] for d in r.records] == [O.RECOMPUTED]
+    assert [(d["kind"], d["row"], d["col"]) for d in r.records] == [(O.CORRECTED, 3, 1)]
     assert np.max(np.abs(r.C - Cff)) < 1e-13
     # two errors cancelling in their column: two rows and no column disagree;
     # that is not a single checksum fault -> recomputed, not left alone
@@ -208,6 +209,53 @@ def pin_classification(orc):
     r = orc.ftgemm(A, B, tm=16, tn=16, bk=16,
                    injections=[O.Injection(20, 21, 10, O.ADD, tiny)])
     assert not r.records
+
+
+def pin_line_correction(orc):
+    """Errors confined to one row (or one column) of a tile, on integer
+    data: each element on the flagged line is rebuilt from the checksum of
+    its column (row) and the line is confirmed by its own checksum; the
+    output equals the fault-free product bit for bit.  More than four
+    elements on the line, or a checksum fault that joins the line, leaves
+    a rebuild that does not confirm (or none) -> recomputed."""
+    g = synth.rng(93, 0, 0)
+    m, n, k = 32, 32, 24
+    A = np.asfortranarray(g.integers(-8, 9, (m, k)).astype(float))
+    B = np.asfortranarray(g.integers(-8, 9, (k, n)).astype(float))
+    Cin = np.asfortranarray(g.integers(-8, 9, (m, n)).astype(float))
+    Cff = 3.0 * (A @ B) + 2.0 * Cin
+    run = lambda plan: orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=8, injections=plan)
+    Inj = O.Injection
+    # two in row 20 (tile (1, 0)), four in row 5 (tile (0, 1)), three in
+    # column 9 (tile (1, 0) is taken: column 9 of tile (0, 0))
+    plan = [Inj(20, 2, 3, O.ADD, 100.0), Inj(20, 11, 17, O.ADD, -40.0),
+            Inj(5, 16, 0, O.ADD, 7.0), Inj(5, 18, 8, O.ADD, 9.0), Inj(5, 25, 8, O.ADD, -3.0),
+            Inj(5, 31, 23, O.ADD, 1.0e6),
+            Inj(1, 9, 5, O.ADD, 50.0), Inj(7, 9, 9, O.ADD, 60.0), Inj(14, 9, 20, O.ADD, -70.0)]
+    r = run(plan)
+    assert np.array_equal(r.C, Cff)
+    got = sorted((d["kind"], d["row"], d["col"], d["nbad_rows"], d["nbad_cols"])
+                 for d in r.records)
+    assert got == [(O.CORRECTED, 1, 9, 3, 1), (O.CORRECTED, 5, 16, 1, 4),
+                   (O.CORRECTED, 20, 2, 1, 2)]
+    # the record's before / after are those of the first rebuilt element
+    d = [d for d in r.records if d["row"] == 20][0]
+    assert d["before"] == Cff[20, 2] + 300.0 and d["after"] == Cff[20, 2]
+    # a non-finite value on the line is rebuilt too
+    r = orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=8, injections=[
+        Inj(3, 4, 7, O.ADD, np.inf), Inj(3, 12, 7, O.ADD, 5.0)])
+    assert np.array_equal(r.C, Cff) and [d["kind"] for d in r.records] == [O.CORRECTED]
+    # five on one line: more than a line rebuild takes
+    five = [Inj(6, j, 2, O.ADD, 10.0 + j) for j in (0, 3, 6, 9, 12)]
+    r = run(five)
+    assert [(d["kind"], d["nbad_cols"]) for d in r.records] == [(O.RECOMPUTED, 5)]
+    assert np.array_equal(r.C, Cff)
+    # a data error and a checksum fault on another column of its row: the
+    # rebuilt checksum column does not confirm against the row
+    r = run([Inj(6, 3, 2, O.ADD, 10.0), Inj(0, 12, 2, O.ADD, 30.0, target=O.TGT_ROW_CHECKSUM)])
+    assert [(d["kind"], d["nbad_rows"], d["nbad_cols"]) for d in r.records] == \
+        [(O.RECOMPUTED, 1, 2)]
+    assert np.array_equal(r.C, Cff)
 
 
 def pin_one_sided(orc):
@@ -286,5 +334,5 @@ def pin_ragged_and_subset(orc):
 
 ALL_PINS = [pin_gemm_vs_numpy, pin_gemm_integer_exact, pin_blas_special_cases,
             pin_checksum_identities, pin_brute_force_location, pin_exact_recovery,
-            pin_nonfinite_recovery, pin_classification, pin_one_sided,
+            pin_nonfinite_recovery, pin_classification, pin_line_correction, pin_one_sided,
             pin_no_false_positives, pin_ragged_and_subset]

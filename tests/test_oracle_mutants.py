@@ -14,7 +14,9 @@ MUTANTS = {
         "s += x[p] * opB(B, P->ldb, P->tb, p, j0 + jj);",
         "s += y[p] * opB(B, P->ldb, P->tb, p, j0 + jj);"),
     "wrong_sign_in_correction": (
-        "double fixed = Pr[jbad] - sr;", "double fixed = sr - Pr[jbad];"),
+        "fixed[nfix++] = (by_row ? Pr[x] : Pc[x]) - s;", "fixed[nfix++] = s - (by_row ? Pr[x] : Pc[x]);"),
+    "column_line_rebuilt_from_row_checksums": (
+        "fixed[nfix++] = (by_row ? Pr[x] : Pc[x]) - s;", "fixed[nfix++] = Pr[x] - s;"),
     "transposed_operand_A": (
         "return ta ? A[p + i * lda] : A[i + p * lda];",
         "return ta ? A[i + p * lda] : A[p + i * lda];"),
@@ -30,7 +32,7 @@ MUTANTS = {
         "const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 : P->tm;\n    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;\n    const double alpha",
         "const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 - 1 : P->tm;\n    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;\n    const double alpha"),
     "correction_not_confirmed": (
-        "if (fabs(sc + fixed - Pc[ibad]) <= tc[ibad]) {", "if (1) {"),
+        "if (fabs(total - target) <= tau) {", "if (1) {"),
     "bf16_exponent_bias_off_by_one": (
         "v = ldexp((double)(128 + f), e - 127 - 7);", "v = ldexp((double)(128 + f), e - 126 - 7);"),
     "e4m3_nan_code_wrong": (
