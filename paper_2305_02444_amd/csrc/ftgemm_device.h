@@ -238,6 +238,11 @@ __device__ __forceinline__ double ft_threshold(double lambda, double u, double s
 
 constexpr double kLambda = 8.0;
 
+// Errors confined to one row (column) of a tile are rebuilt from the other
+// side's checksums when the other side flags at most this many entries;
+// the line's own checksum confirms them.
+constexpr int kMaxLineFixes = 4;
+
 // threadIdx.x as a value the compiler cannot tie to earlier reads: indices
 // derived from it after a long loop are formed again from this rather than
 // kept alive (and spilled to scratch) across the loop.

@@ -80,6 +80,7 @@ struct Smem {
     int nfaults;
     double wratio[4];      // largest |d| / tau of the waves that verify
     int nbad_r, nbad_c, ibad, jbad;
+    int bad_r[kMaxLineFixes], bad_c[kMaxLineFixes];  // the first flagged entries, any order
 };
 
 // Fetches one step's part of a stored (column-major) operand: 8 elements per
@@ -550,7 +551,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 }
                 if (x < (is_row ? hrows : wcols)) {
                     if (!(fabs(d) <= tau)) {
-                        atomicAdd(is_row ? &sm.nbad_r : &sm.nbad_c, 1);
+                        const int slot = atomicAdd(is_row ? &sm.nbad_r : &sm.nbad_c, 1);
+                        if (slot < kMaxLineFixes) (is_row ? sm.bad_r : sm.bad_c)[slot] = x;
                         atomicMin(is_row ? &sm.ibad : &sm.jbad, x);
                     } else if (tau > 0.0) {
                         ratio = fabs(d) / tau;
@@ -624,6 +626,55 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 kind = FTGEMM_KIND_CORRECTED;
                 break;
             }
+        } else if ((nr == 1 && nc >= 2 && nc <= kMaxLineFixes) ||
+                   (nc == 1 && nr >= 2 && nr <= kMaxLineFixes)) {
+            // Several errors on one line: the flagged row (or column).  Each
+            // element where it crosses a flagged entry of the other side
+            // loses that entry's residual (the classical ABFT correction),
+            // and the line is confirmed by its own residual, which after the
+            // corrections is d_line - sum of the crossing residuals.  A
+            // residual that is not finite cannot be subtracted: the line
+            // fails to confirm and the tile is computed again.
+            const bool by_row = nr == 1;
+            const int line = by_row ? first_i : first_j;
+            const int nfix = by_row ? nc : nr;
+            double sumd = 0.0;
+#pragma unroll
+            for (int f = 0; f < kMaxLineFixes; ++f)
+                if (f < nfix)
+                    sumd += by_row ? sm.u.epi.d_col[sm.bad_c[f]] : sm.u.epi.d_row[sm.bad_r[f]];
+            const double dl = by_row ? sm.u.epi.d_row[line] : sm.u.epi.d_col[line];
+            if (fabs(dl - sumd) <= (by_row ? sm.u.epi.tau_row[line] : sm.u.epi.tau_col[line])) {
+                // each crossing's residual at its position along the line
+                // (the encoded-sum partials are no longer needed)
+                double *lfix = sm.u.epi.enc_row[0];
+                for (int x = t; x < (by_row ? TN : TM); x += NT) lfix[x] = 0.0;
+                __syncthreads();
+                if (t < nfix) {
+                    const int cf = by_row ? sm.bad_c[t] : sm.bad_r[t];
+                    lfix[cf] = by_row ? sm.u.epi.d_col[cf] : sm.u.epi.d_row[cf];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = wm * 64 + 16 * mi + 4 * r + q;
+                            const int col = wn * 32 + 16 * ni + c16;
+                            if ((by_row ? row : col) != line) continue;
+                            const int at = by_row ? col : row;
+                            const double d = lfix[at];
+                            if (d == 0.0) continue;
+                            const bool named = at == (by_row ? first_j : first_i);
+                            if (named) rec_before = acc[mi][ni][r];
+                            acc[mi][ni][r] -= d;
+                            if (named) rec_after = acc[mi][ni][r];
+                        }
+                kind = FTGEMM_KIND_CORRECTED;
+                break;
+            }
         } else if (nr + nc == 1) {
             kind = FTGEMM_KIND_CHECKSUM_ONLY;
             break;
@@ -646,10 +697,13 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
         if (kind == FTGEMM_KIND_CORRECTED) {
             // the owner lane of a corrected element knows its old value
             __syncthreads();
-            if (w == owner_wave(first_i, first_j) && lane == owner_lane(first_i, first_j))
+            if (w == owner_wave(first_i, first_j) && lane == owner_lane(first_i, first_j)) {
                 sm.red[2][0] = rec_before;
+                sm.red[2][1] = rec_after;
+            }
             __syncthreads();
             rec_before = sm.red[2][0];
+            rec_after = sm.red[2][1];
         }
         if (t == 0) {
             DevCounters *ct = g.counters;

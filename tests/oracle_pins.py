@@ -213,11 +213,11 @@ def pin_classification(orc):
 
 def pin_line_correction(orc):
     """Errors confined to one row (or one column) of a tile, on integer
-    data: each element on the flagged line is rebuilt from the checksum of
-    its column (row) and the line is confirmed by its own checksum; the
-    output equals the fault-free product bit for bit.  More than four
-    elements on the line, or a checksum fault that joins the line, leaves
-    a rebuild that does not confirm (or none) -> recomputed."""
+    data: each element where the flagged line crosses a flagged entry loses
+    that entry's residual, the line is confirmed by its own residual, and
+    the output equals the fault-free product bit for bit.  More than four
+    elements on the line, a checksum fault that joins the line, or a value
+    that is not finite (its residual cannot be subtracted) -> recomputed."""
     g = synth.rng(93, 0, 0)
     m, n, k = 32, 32, 24
     A = np.asfortranarray(g.integers(-8, 9, (m, k)).astype(float))
@@ -241,10 +241,11 @@ def pin_line_correction(orc):
     # the record's before / after are those of the first rebuilt element
     d = [d for d in r.records if d["row"] == 20][0]
     assert d["before"] == Cff[20, 2] + 300.0 and d["after"] == Cff[20, 2]
-    # a non-finite value on the line is rebuilt too
+    # a non-finite value among several on a line: computed again (alone on
+    # its row and column it is rebuilt, see pin_nonfinite_recovery)
     r = orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=8, injections=[
         Inj(3, 4, 7, O.ADD, np.inf), Inj(3, 12, 7, O.ADD, 5.0)])
-    assert np.array_equal(r.C, Cff) and [d["kind"] for d in r.records] == [O.CORRECTED]
+    assert np.array_equal(r.C, Cff) and [d["kind"] for d in r.records] == [O.RECOMPUTED]
     # five on one line: more than a line rebuild takes
     five = [Inj(6, j, 2, O.ADD, 10.0 + j) for j in (0, 3, 6, 9, 12)]
     r = run(five)

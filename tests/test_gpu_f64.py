@@ -103,6 +103,34 @@ def test_padded_leading_dimension_of_c():
     assert normwise(got, ref) <= TOL
 
 
+def test_line_corrections():
+    """Errors confined to one row or one column of a tile: two and four in
+    a row, three in a column -- each loses its crossing entry's residual
+    and the line is confirmed by its own; C within 1e-12 of the oracle's.
+    A line holding a non-finite value (an FP64 exponent flip) cannot be
+    corrected by residuals: that tile is computed again."""
+    m, n, k = 384, 300, 200
+    A, B, Cin = synth.operands(7, 0, m, n, k, "uniform")
+    bk = f64_tiling(m, n, k)[2]
+    F_ = synth.Fault
+    part = A[:, :bk] @ B[:bk, :]
+    cand = [(int(i), int(j)) for i, j in np.argwhere((np.abs(part) >= 1) & (np.abs(part) < 2))
+            if 256 <= i < 384 and j == 40 and i != 300]
+    assert cand
+    plan = [F_(17, 3, 10, synth.ADD, 30.0), F_(17, 90, 150, synth.ADD, -40.0),      # (0, 0)
+            F_(140, 130, 5, synth.ADD, 2.0), F_(140, 150, 60, synth.ADD, 5.0),      # (1, 1)
+            F_(140, 200, 199, synth.ADD, -3.0), F_(140, 255, 99, synth.ADD, 6.0),
+            F_(260, 280, 0, synth.ADD, 20.0), F_(300, 280, 70, synth.ADD, 8.0),     # (2, 2)
+            F_(383, 280, 199, synth.ADD, -5.0),
+            F_(300, 40, 70, synth.ADD, 8.0),                                        # (2, 0)
+            F_(cand[0][0], 40, 3, synth.BITFLIP, 0.0, 62)]
+    got, rep, ref = _compare(A, B, Cin, 1.0, 0.5, False, False, plan)
+    kinds = {(r["tile_m"], r["tile_n"]): r["kind"] for r in rep.records}
+    assert kinds == {(0, 0): F.KIND_CORRECTED, (1, 1): F.KIND_CORRECTED,
+                     (2, 2): F.KIND_CORRECTED, (2, 0): F.KIND_RECOMPUTED}
+    assert np.all(np.isfinite(got))
+
+
 def test_fault_classes():
     """Two faults in one tile -> recomputed; a fault on an encoded checksum
     only -> checksum-only, data untouched; a data fault plus a fault on its

@@ -14,9 +14,12 @@ MUTANTS = {
         "s += x[p] * opB(B, P->ldb, P->tb, p, j0 + jj);",
         "s += y[p] * opB(B, P->ldb, P->tb, p, j0 + jj);"),
     "wrong_sign_in_correction": (
-        "fixed[nfix++] = (by_row ? Pr[x] : Pc[x]) - s;", "fixed[nfix++] = s - (by_row ? Pr[x] : Pc[x]);"),
-    "column_line_rebuilt_from_row_checksums": (
-        "fixed[nfix++] = (by_row ? Pr[x] : Pc[x]) - s;", "fixed[nfix++] = Pr[x] - s;"),
+        "double fixed = Pr[jbad] - sr;", "double fixed = sr - Pr[jbad];"),
+    "line_residual_added_not_subtracted": (
+        "out[ii + jj * h] -= d;", "out[ii + jj * h] += d;"),
+    "line_confirmed_without_its_own_residual": (
+        "if (fabs(dl - sumd) <= (by_row ? tc[line] : tr[line])) {",
+        "if (fabs(sumd) <= (by_row ? tc[line] : tr[line]) || 1) {"),
     "transposed_operand_A": (
         "return ta ? A[p + i * lda] : A[i + p * lda];",
         "return ta ? A[i + p * lda] : A[p + i * lda];"),
@@ -32,7 +35,7 @@ MUTANTS = {
         "const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 : P->tm;\n    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;\n    const double alpha",
         "const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 - 1 : P->tm;\n    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;\n    const double alpha"),
     "correction_not_confirmed": (
-        "if (fabs(total - target) <= tau) {", "if (1) {"),
+        "if (fabs(sc + fixed - Pc[ibad]) <= tc[ibad]) {", "if (1) {"),
     "bf16_exponent_bias_off_by_one": (
         "v = ldexp((double)(128 + f), e - 127 - 7);", "v = ldexp((double)(128 + f), e - 126 - 7);"),
     "e4m3_nan_code_wrong": (
