@@ -549,52 +549,52 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
         if (P->one_sided) {
             /* With one side the faulty column is unknown, and a checksum
              * fault looks like a data fault: the tile is computed again. */
-        } else if ((nbad_r == 1 && nbad_c >= 1 && nbad_c <= MAX_LINE_FIXES) ||
+        } else if (nbad_r == 1 && nbad_c == 1) {
+            /* Locate at the crossing of the flagged row and column; rebuild
+             * the element from the encoded row checksum and the rest of its
+             * column (this also repairs NaN / Inf values), then confirm it
+             * against the encoded column checksum of its row. */
+            double sr = 0.0, sc = 0.0;
+            for (int64_t ii = 0; ii < h; ++ii)
+                if (ii != ibad) sr += out[ii + jbad * h];
+            for (int64_t jj = 0; jj < w; ++jj)
+                if (jj != jbad) sc += out[ibad + jj * h];
+            double fixed = Pr[jbad] - sr;
+            if (fabs(sc + fixed - Pc[ibad]) <= tc[ibad]) {
+                out[ibad + jbad * h] = fixed;
+                if (rec) { rec->kind = KIND_CORRECTED; rec->after = fixed; }
+                break;
+            }
+        } else if ((nbad_r == 1 && nbad_c >= 2 && nbad_c <= MAX_LINE_FIXES) ||
                    (nbad_c == 1 && nbad_r >= 2 && nbad_r <= MAX_LINE_FIXES)) {
-            /* The errors lie on one line: the flagged row (one flagged row,
+            /* Several errors on one line: the flagged row (one flagged row,
              * up to MAX_LINE_FIXES flagged columns) or the flagged column.
-             * Each element where the line crosses a flagged entry of the
-             * other side is rebuilt from that entry's encoded checksum and
-             * the rest of its column (row) -- NaN / Inf values included --
-             * and the line is then confirmed against its own encoded
-             * checksum.  One row and one column is the single-error case. */
+             * Each element where the line crosses a flagged entry x of the
+             * other side loses that entry's residual, out - (R_x - P_x) (the
+             * classical ABFT correction), and the line is confirmed by its
+             * own residual: after the corrections it is d_line - sum_x d_x.
+             * A residual that is not finite cannot be subtracted: such a
+             * line fails to confirm and the tile is computed again. */
             const int by_row = (nbad_r == 1);
             const int64_t line = by_row ? ibad : jbad;
-            const int64_t len = by_row ? w : h;       /* elements on the line */
-            const int64_t across = by_row ? h : w;    /* elements across it  */
-            double fixed[MAX_LINE_FIXES];
-            int64_t at[MAX_LINE_FIXES];
-            int nfix = 0;
-            double rest = 0.0;   /* the line's elements that are kept */
+            const int64_t len = by_row ? w : h;
+            double sumd = 0.0;
             for (int64_t x = 0; x < len; ++x) {
-                const int64_t ii = by_row ? line : x, jj = by_row ? x : line;
                 const double d = by_row ? Rr[x] - Pr[x] : Rc[x] - Pc[x];
-                const double tau = by_row ? tr[x] : tc[x];
-                if (!(fabs(d) <= tau)) {
-                    double s = 0.0;   /* the rest of the crossing column (row) */
-                    for (int64_t y = 0; y < across; ++y) {
-                        if (y == line) continue;
-                        s += by_row ? out[y + x * h] : out[x + y * h];
-                    }
-                    at[nfix] = x;
-                    fixed[nfix++] = (by_row ? Pr[x] : Pc[x]) - s;
-                } else {
-                    rest += out[ii + jj * h];
-                }
+                if (!(fabs(d) <= (by_row ? tr[x] : tc[x]))) sumd += d;
             }
-            double total = rest;
-            for (int f = 0; f < nfix; ++f) total += fixed[f];
-            const double target = by_row ? Pc[line] : Pr[line];
-            const double tau = by_row ? tc[line] : tr[line];
-            if (fabs(total - target) <= tau) {
-                for (int f = 0; f < nfix; ++f) {
-                    const int64_t ii = by_row ? line : at[f], jj = by_row ? at[f] : line;
-                    out[ii + jj * h] = fixed[f];
+            const double dl = by_row ? Rc[line] - Pc[line] : Rr[line] - Pr[line];
+            if (fabs(dl - sumd) <= (by_row ? tc[line] : tr[line])) {
+                for (int64_t x = 0; x < len; ++x) {
+                    const double d = by_row ? Rr[x] - Pr[x] : Rc[x] - Pc[x];
+                    if (fabs(d) <= (by_row ? tr[x] : tc[x])) continue;
+                    const int64_t ii = by_row ? line : x, jj = by_row ? x : line;
+                    out[ii + jj * h] -= d;
                 }
                 if (rec) {
                     /* the record names the first rebuilt element */
                     rec->kind = KIND_CORRECTED;
-                    rec->after = fixed[0];
+                    rec->after = out[ibad + jbad * h];
                 }
                 break;
             }
