@@ -326,7 +326,7 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
         ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, &tm, &tn, &bk);
     GemmArgs g = base_args(d, tm, tn);
     const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
-    if (d.abft == 2) {
+    if (d.abft && d.dtype != FTGEMM_F64) {
         // line norms of op(A) (rows) and op(B) (columns) for the thresholds
         const bool fp8 = d.dtype == FTGEMM_FP8_E4M3;
         const int64_t part = std::max<int64_t>(int64_t(1) << 22, 2 * std::max(d.m, d.n));

@@ -470,10 +470,11 @@ __device__ __forceinline__ int owner_reg(int row, int col)
 }
 
 // ONE: the one-sided mode -- only the column checksum of the tile (one
-// entry per row, C^c = C e) is encoded and verified, any disagreement has the
-// tile computed again, and the threshold norms come from g.row_nrm2 /
-// g.col_nrm2 / g.row_max / g.col_max instead of the staged operands.
-template <bool FP8, bool TA, bool TB, bool ABFT, int BM, bool ONE = false>
+// entry per row, C^c = C e) is encoded and verified, and any disagreement has
+// the tile computed again.  PRE (implied by ONE): the threshold norms come
+// from g.row_nrm2 / g.col_nrm2 / g.row_max / g.col_max, taken before the
+// product, instead of from the staged operands.
+template <bool FP8, bool TA, bool TB, bool ABFT, int BM, bool ONE = false, bool PRE = false>
 __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
 {
     using E = Elem<FP8>;
@@ -481,6 +482,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
     constexpr int NI = G::NI, NA = G::NA;
     constexpr bool kMma = !FP8;  // BF16: encoded checksums on the matrix cores
     constexpr bool kOne = ABFT && ONE;
+    constexpr bool kPre = ABFT && (ONE || PRE);
     // the checksum products of step s run during step s + 1
     constexpr bool kLag = kMma && ABFT;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -573,8 +575,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
 
         load(0);
         if (ABFT) {
-            if (!kOne) la.template sum_to<kMma>(sm.xs[0], nrm_a);
-            lb.template sum_to<kMma && !kOne>(sm.ys[0], nrm_b);
+            if (!kOne) la.template sum_to<kMma && !kPre>(sm.xs[0], nrm_a);
+            lb.template sum_to<kMma && !kPre>(sm.ys[0], nrm_b);
         }
         int s = 0;
 #pragma unroll 1
@@ -622,11 +624,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                     __syncthreads();
 #pragma unroll
                     for (int e = 0; e < LA::kNP; ++e) yv[e] = sm.yc[la.p0() + e];
-                    la.template encode<!kOne>(yv, enc_a, nrm_a, amx_a);
+                    la.template encode<!kPre>(yv, enc_a, nrm_a, amx_a);
                     if (!kOne) {
 #pragma unroll
                         for (int e = 0; e < LB::kNP; ++e) xv[e] = sm.xc[lb.p0() + e];
-                        lb.encode(xv, enc_b, nrm_b, amx_b);
+                        lb.template encode<!kPre>(xv, enc_b, nrm_b, amx_b);
                     }
                 }
                 if (s + 1 < nsteps) load(s + 1);
@@ -693,8 +695,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                 }
                 if (ABFT && s + 1 < nsteps) {
                     // operand checksums of step s + 1, published before its barrier
-                    if (!kOne) la.template sum_to<kMma>(sm.xs[stg ^ 1], nrm_a);
-                    lb.template sum_to<kMma && !kOne>(sm.ys[stg ^ 1], nrm_b);
+                    if (!kOne) la.template sum_to<kMma && !kPre>(sm.xs[stg ^ 1], nrm_a);
+                    lb.template sum_to<kMma && !kPre>(sm.ys[stg ^ 1], nrm_b);
                 }
             }
             if (ABFT && faults_on) {
@@ -777,7 +779,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
             la.partials_to(enc_a, sm.u.epi.enc_row);
             if (!kOne) lb.partials_to(enc_b, sm.u.epi.enc_col);
         }
-        if (!kOne) {
+        if (!kPre) {
             la.partials_to(nrm_a, sm.u.epi.nrm_row);
             lb.partials_to(nrm_b, sm.u.epi.nrm_col);
         }
@@ -785,8 +787,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         {
             const double sx = kOne ? 0.0 : sum64(t < E::BK ? (double)vx : 0.0);
             const double sy = sum64(t < E::BK ? (double)vy : 0.0);
-            const double ma = FP8 && !kOne ? max64((double)amx_a) : 0.0;
-            const double mb = FP8 && !kOne ? max64((double)amx_b) : 0.0;
+            const double ma = FP8 && !kPre ? max64((double)amx_a) : 0.0;
+            const double mb = FP8 && !kPre ? max64((double)amx_b) : 0.0;
             if (lane == 0) {
                 sm.wsum[w][0] = sx; sm.wsum[w][1] = sy; sm.wsum[w][3] = ma; sm.wsum[w][4] = mb;
             }
@@ -840,7 +842,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         double nrm2 = 0.0;
         if (is_row) {
             double e = 0, nr = 0;
-            if (kOne)
+            if (kPre)
                 nr = x < hrows ? g.row_nrm2[i0 + x] : 0.0;
             else
 #pragma unroll
@@ -857,8 +859,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
             nrm2 = x < wcols ? g.col_nrm2[j0 + x] : 0.0;
         } else if (is_col) {
             double e = 0, nr = 0;
+            if (kPre)
+                nr = x < wcols ? g.col_nrm2[j0 + x] : 0.0;
+            else
 #pragma unroll
-            for (int v = 0; v < LB::kOuterParts; ++v) nr += sm.u.epi.nrm_col[v][x];
+                for (int v = 0; v < LB::kOuterParts; ++v) nr += sm.u.epi.nrm_col[v][x];
             if (kMma) {
                 e = sm.u.epi.enc_col[0][x];
             } else {
@@ -873,7 +878,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         if (w < G::kVW) {
             const double f = sum64(nrm2);
             if (lane == 0) sm.wsum[w][2] = f;
-            if (kOne && FP8) {
+            if (kPre && FP8) {
                 // the tile's largest magnitudes, from the per-line maxima
                 const double ra = is_row && x < hrows ? g.row_max[i0 + x] : 0.0;
                 const double cb = is_col && x < wcols ? g.col_max[j0 + x] : 0.0;
@@ -1155,13 +1160,13 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
     }
 }
 
-template <bool FP8, bool TA, bool TB, bool ABFT, int BM, bool ONE>
+template <bool FP8, bool TA, bool TB, bool ABFT, int BM, bool ONE, bool PRE>
 __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
 {
     __shared__ Smem<BM> sm;
     int tm_, tn_;
     map_tile(blockIdx.x, g.tiles_m, g.tiles_n, tm_, tn_);
-    tile<FP8, TA, TB, ABFT, BM, ONE>(g, tm_, tn_, sm);
+    tile<FP8, TA, TB, ABFT, BM, ONE, PRE>(g, tm_, tn_, sm);
 }
 
 // Tile rows of the batched kernel (problems of mixed, often small, shapes).
@@ -1220,7 +1225,7 @@ hipError_t launch(const GemmArgs &g, bool ta, bool tb, int mode, hipStream_t str
     const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n;
     if (grid == 0) return hipSuccess;
 #define FTG_LP_CASE(a, b, c, d) \
-    hipLaunchKernelGGL((kernel<FP8, a, b, c, BM, d>), dim3(grid), dim3(NT), 0, stream, g)
+    hipLaunchKernelGGL((kernel<FP8, a, b, c, BM, d, c>), dim3(grid), dim3(NT), 0, stream, g)
 #define FTG_LP_MODE(c, d)                                   \
     do {                                                    \
         if (!ta && !tb) FTG_LP_CASE(false, false, c, d);    \
