@@ -148,16 +148,17 @@ typedef struct {
  *   0  the same kernel with every checksum operation compiled out (the
  *      plain-GEMM baseline);
  *   1  row and column checksums of every tile (Section 2.2): a single
- *      error per tile is located and rebuilt;
+ *      error per tile, or two to four on one row or one column of it, is
+ *      located and corrected (the record names the first element);
  *   2  one-sided (BF16 / FP8 single calls only; FTGEMM_ERR_UNSUPPORTED for
  *      F64 and in batches): only the column checksum C e of each tile is
  *      kept, one entry per row, and a tile with any disagreeing row is
- *      computed again (records: kind RECOMPUTED, col -1).  The threshold
- *      norms of the rows of op(A) and columns of op(B) are taken in one
- *      pass over A and B before the product, using the library's
- *      workspace.  Faults planned on the row checksum have no entry to land
- *      on and are not applied.
- * Other values are rejected (argument position 14). */
+ *      computed again (records: kind RECOMPUTED, col -1).  Faults planned
+ *      on the row checksum have no entry to land on and are not applied.
+ * BF16 / FP8 single calls with abft 1 or 2 take the threshold norms of the
+ * rows of op(A) and columns of op(B) in one pass over A and B before the
+ * product, using the library's workspace (batches compute them in the
+ * tiles).  Other values of abft are rejected (argument position 14). */
 typedef struct {
     ftgemm_dtype dtype;
     ftgemm_op transA, transB;
