@@ -326,7 +326,13 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
         ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, &tm, &tn, &bk);
     GemmArgs g = base_args(d, tm, tn);
     const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
-    if (d.abft && d.dtype != FTGEMM_F64) {
+    // Low precision: the threshold norms in one pass before the product for
+    // the one-sided mode, and for outputs of at least kLargeTileMin tiles
+    // (below that the extra launches cost more than the tiles' own norms).
+    const bool pre = d.dtype != FTGEMM_F64 &&
+                     (d.abft == 2 || (d.abft == 1 && (int64_t)g.tiles_m * g.tiles_n >=
+                                                         ftg::kLargeTileMin));
+    if (pre) {
         // line norms of op(A) (rows) and op(B) (columns) for the thresholds
         const bool fp8 = d.dtype == FTGEMM_FP8_E4M3;
         const int64_t part = std::max<int64_t>(int64_t(1) << 22, 2 * std::max(d.m, d.n));
@@ -392,7 +398,7 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
             HIP_TRY(ftg::launch_splitk_reduce(r, d.abft != 0, stream));
         }
     } else
-        HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft, tm, stream));
+        HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft, pre, tm, stream));
     if (rep && d.abft) {
         HIP_TRY(hipMemcpyAsync(ws->h_counters, ws->counters, sizeof(DevCounters),
                                hipMemcpyDeviceToHost, stream));

@@ -13,9 +13,10 @@ void tiling_f64(int *tm, int *tn, int *bk);
 
 // BF16 / FP8 E4M3 tile kernel (FP32 accumulation and output, one tm x 128
 // output tile per workgroup, tm = 128 or 256 as tiling_lp chose).  mode: 0
-// without checksums, 1 fault-tolerant, 2 one-sided; modes 1 and 2 take
-// their threshold norms from g's line norms (set by the caller).
-hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode, int tm,
+// without checksums, 1 fault-tolerant, 2 one-sided.  pre: the threshold
+// norms come from g's line norms (set by the caller; required by mode 2)
+// instead of the tiles.
+hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode, bool pre, int tm,
                      hipStream_t stream);
 // Tile of an m x n low-precision output in a mode (batched: the batched
 // kernel's tile).

@@ -1220,22 +1220,23 @@ hipError_t launch_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int g
 }
 
 template <bool FP8, int BM>
-hipError_t launch(const GemmArgs &g, bool ta, bool tb, int mode, hipStream_t stream)
+hipError_t launch(const GemmArgs &g, bool ta, bool tb, int mode, bool pre, hipStream_t stream)
 {
     const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n;
     if (grid == 0) return hipSuccess;
-#define FTG_LP_CASE(a, b, c, d) \
-    hipLaunchKernelGGL((kernel<FP8, a, b, c, BM, d, c>), dim3(grid), dim3(NT), 0, stream, g)
-#define FTG_LP_MODE(c, d)                                   \
-    do {                                                    \
-        if (!ta && !tb) FTG_LP_CASE(false, false, c, d);    \
-        else if (!ta && tb) FTG_LP_CASE(false, true, c, d); \
-        else if (ta && !tb) FTG_LP_CASE(true, false, c, d); \
-        else FTG_LP_CASE(true, true, c, d);                 \
+#define FTG_LP_CASE(a, b, c, d, e) \
+    hipLaunchKernelGGL((kernel<FP8, a, b, c, BM, d, e>), dim3(grid), dim3(NT), 0, stream, g)
+#define FTG_LP_MODE(c, d, e)                                   \
+    do {                                                       \
+        if (!ta && !tb) FTG_LP_CASE(false, false, c, d, e);    \
+        else if (!ta && tb) FTG_LP_CASE(false, true, c, d, e); \
+        else if (ta && !tb) FTG_LP_CASE(true, false, c, d, e); \
+        else FTG_LP_CASE(true, true, c, d, e);                 \
     } while (0)
-    if (mode == 2) FTG_LP_MODE(true, true);
-    else if (mode == 1) FTG_LP_MODE(true, false);
-    else FTG_LP_MODE(false, false);
+    if (mode == 2) FTG_LP_MODE(true, true, true);
+    else if (mode == 1 && pre) FTG_LP_MODE(true, false, true);
+    else if (mode == 1) FTG_LP_MODE(true, false, false);
+    else FTG_LP_MODE(false, false, false);
 #undef FTG_LP_MODE
 #undef FTG_LP_CASE
     return hipGetLastError();
@@ -1243,16 +1244,16 @@ hipError_t launch(const GemmArgs &g, bool ta, bool tb, int mode, hipStream_t str
 
 }  // namespace lp
 
-hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode, int tm,
+hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode, bool pre, int tm,
                      hipStream_t stream)
 {
-    if (mode < 0 || mode > 2) return hipErrorInvalidValue;
+    if (mode < 0 || mode > 2 || (mode == 2 && !pre)) return hipErrorInvalidValue;
     if (tm == 256)
-        return fp8 ? lp::launch<true, 256>(g, ta, tb, mode, stream)
-                   : lp::launch<false, 256>(g, ta, tb, mode, stream);
+        return fp8 ? lp::launch<true, 256>(g, ta, tb, mode, pre, stream)
+                   : lp::launch<false, 256>(g, ta, tb, mode, pre, stream);
     if (tm != 128) return hipErrorInvalidValue;
-    return fp8 ? lp::launch<true, 128>(g, ta, tb, mode, stream)
-               : lp::launch<false, 128>(g, ta, tb, mode, stream);
+    return fp8 ? lp::launch<true, 128>(g, ta, tb, mode, pre, stream)
+               : lp::launch<false, 128>(g, ta, tb, mode, pre, stream);
 }
 
 hipError_t launch_lp_batched(const BatchArgs &b, bool fp8, bool ta, bool tb, bool abft, int grid,
