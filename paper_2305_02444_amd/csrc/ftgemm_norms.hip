@@ -102,19 +102,29 @@ __global__ __launch_bounds__(NT) void rows_kernel(const char *X, int64_t ld, int
     }
 }
 
-// Partials of the column chunks, in chunk order.
+// Partials of the column chunks: 64 rows per workgroup, its 4 waves taking
+// every 4th chunk, then the waves' sums added in a fixed order.
 __global__ __launch_bounds__(NT) void rows_finish(const double *part, int nchunks, int64_t R,
                                                   double *nrm2, double *amax)
 {
-    const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (r >= R) return;
+    __shared__ double ssum[4][64], smax[4][64];
+    const int t = threadIdx.x, rl = t & 63, cg = t >> 6;
+    const int64_t r = (int64_t)blockIdx.x * 64 + rl;
     double s = 0.0, m = 0.0;
-    for (int c = 0; c < nchunks; ++c) {
-        s += part[(int64_t)c * R + r];
-        m = fmax(m, part[((int64_t)nchunks + c) * R + r]);
+    if (r < R) {
+#pragma unroll 4
+        for (int c = cg; c < nchunks; c += 4) {
+            s += part[(int64_t)c * R + r];
+            m = fmax(m, part[((int64_t)nchunks + c) * R + r]);
+        }
     }
-    nrm2[r] = s;
-    amax[r] = m;
+    ssum[cg][rl] = s;
+    smax[cg][rl] = m;
+    __syncthreads();
+    if (cg == 0 && r < R) {
+        nrm2[r] = (ssum[0][rl] + ssum[1][rl]) + (ssum[2][rl] + ssum[3][rl]);
+        amax[r] = fmax(fmax(smax[0][rl], smax[1][rl]), fmax(smax[2][rl], smax[3][rl]));
+    }
 }
 
 // Along each stored column: one block per column, 16-byte loads down it.
@@ -168,7 +178,7 @@ hipError_t lines(const void *X, int64_t ld, int64_t R, int64_t Cn, bool along_ro
     nchunks = (Cn + cc - 1) / cc;
     hipLaunchKernelGGL(rows_kernel<FP8>, dim3((unsigned)rblocks, (unsigned)nchunks), dim3(NT), 0,
                        stream, (const char *)X, ld, R, Cn, cc, part, (int)nchunks);
-    hipLaunchKernelGGL(rows_finish, dim3((unsigned)((R + NT - 1) / NT)), dim3(NT), 0, stream,
+    hipLaunchKernelGGL(rows_finish, dim3((unsigned)((R + 63) / 64)), dim3(NT), 0, stream,
                        part, (int)nchunks, R, nrm2, amax);
     return hipGetLastError();
 }
