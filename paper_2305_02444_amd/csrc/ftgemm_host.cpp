@@ -10,6 +10,7 @@
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "../../include/ftgemm.h"
@@ -46,6 +47,9 @@ struct DeviceWs {
     // the line norms of the one-sided low-precision mode
     double *split = nullptr;
     size_t split_bytes = 0;
+    // unfused mode: checksums, sums, norms and its checksum products' slices
+    double *uf = nullptr;
+    size_t uf_bytes = 0;
     // auxiliary counters: [0] record slots, [1 ..] batched work queues
     unsigned int *aux = nullptr;
     unsigned int *h_aux = nullptr;
@@ -268,7 +272,7 @@ int check_args(const ftgemm_gemm_desc &d)
     if (d.dtype == FTGEMM_FP8_E4M3 &&
         !(std::isfinite(d.scaleA) && std::isfinite(d.scaleB) && d.scaleA > 0 && d.scaleB > 0))
         return 14;
-    if (d.abft < 0 || d.abft > 2) return 14;
+    if (d.abft < 0 || d.abft > 3) return 14;
     if (d.m > INT32_MAX / 2 || d.n > INT32_MAX / 2) return d.m > INT32_MAX / 2 ? 3 : 4;
     return 0;
 }
@@ -294,6 +298,189 @@ GemmArgs base_args(const ftgemm_gemm_desc &d, int tm, int tn)
     return g;
 }
 
+// The device report of a single call into rep (waits for the stream).
+ftgemm_status copy_report(DeviceWs &ws, ftgemm_report *rep, hipStream_t stream, int32_t problem)
+{
+    HIP_TRY(hipMemcpyAsync(ws.h_counters, ws.counters, sizeof(DevCounters),
+                           hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ws.h_aux, ws.aux, sizeof(unsigned int), hipMemcpyDeviceToHost,
+                           stream));
+    HIP_TRY(hipMemcpyAsync(ws.h_records, ws.records, sizeof(ftgemm_fault_record) * kDevRecordCap,
+                           hipMemcpyDeviceToHost, stream));
+    if (ws.nplan)
+        HIP_TRY(hipMemcpyAsync(ws.h_echo, ws.echo, sizeof(ftgemm_injection_echo) * ws.nplan,
+                               hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    fill_report(ws, 0, rep, problem);
+    return FTGEMM_OK;
+}
+
+// C = alpha op(A) op(B) + beta C with the checksum-free FP64 kernel (its
+// inner dimension split as for any call: the slices' partial products in
+// wsp, room for their checksums in chk).
+ftgemm_status plain_f64(const double *A, int64_t lda, bool ta, const double *B, int64_t ldb,
+                        bool tb, int64_t m, int64_t n, int64_t k, double alpha, double beta,
+                        double *C, int64_t ldc, double *wsp, double *chk, DeviceWs &ws,
+                        hipStream_t stream)
+{
+    int tm, tn, bk;
+    ftg::tiling_f64(&tm, &tn, &bk);
+    GemmArgs g{};
+    g.A = A; g.B = B; g.C = C;
+    g.m = m; g.n = n; g.k = k; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.alpha = alpha; g.beta = beta;
+    g.tiles_m = (int32_t)((m + tm - 1) / tm);
+    g.tiles_n = (int32_t)((n + tn - 1) / tn);
+    g.counters = ws.counters; g.records = ws.records; g.rec_slot = ws.aux;
+    g.plan = ws.plan; g.echo = ws.echo;
+    int64_t slice_k = k;
+    const int ns = choose_split(m, n, k, tm, tn, bk, &slice_k);
+    if (ns > 1) {
+        g.nslices = ns; g.slice_k = slice_k; g.wsp = wsp; g.chk = chk;
+    }
+    HIP_TRY(ftg::launch_f64(g, ta, tb, false, stream));
+    if (ns > 1) {
+        ftg::ReduceArgs r{};
+        r.C = C; r.wsp = wsp; r.chk = chk; r.m = m; r.n = n; r.ldc = ldc;
+        r.alpha = alpha; r.beta = beta; r.nslices = ns;
+        r.tiles_m = g.tiles_m; r.tiles_n = g.tiles_n;
+        r.counters = ws.counters; r.records = ws.records; r.record_cap = kDevRecordCap;
+        r.rec_slot = ws.aux;
+        HIP_TRY(ftg::launch_splitk_reduce(r, false, stream));
+    }
+    return FTGEMM_OK;
+}
+
+// Room for plain_f64's slices of an m x n product: (partials, checksums).
+std::pair<int64_t, int64_t> plain_split_space(int64_t m, int64_t n, int64_t k)
+{
+    int tm, tn, bk;
+    ftg::tiling_f64(&tm, &tn, &bk);
+    int64_t slice_k = k;
+    const int ns = choose_split(m, n, k, tm, tn, bk, &slice_k);
+    if (ns <= 1) return {0, 0};
+    const int64_t tiles = ((m + tm - 1) / tm) * ((n + tn - 1) / tn);
+    return {ns * m * n, ns * tiles * 2 * (tm + tn)};
+}
+
+// The unfused FP64 fault tolerance (detection only): the same per-tile
+// checksums and thresholds as the fused kernel, formed by separate passes
+// around the checksum-free GEMM.
+ftgemm_status run_unfused(const ftgemm_gemm_desc &d, DeviceWs &ws, bool report,
+                          hipStream_t stream, int32_t problem)
+{
+    constexpr int64_t T = 128;
+    const int64_t m = d.m, n = d.n, k = d.k;
+    const int64_t tm_ = (m + T - 1) / T, tn_ = (n + T - 1) / T;
+    const int64_t kseg = (k + T - 1) / T;
+    const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
+    const bool use_c = d.beta != 0.0;
+    const auto sr = plain_split_space(tm_, n, k), sc = plain_split_space(m, tn_, k);
+    const int64_t part = std::max(std::max(m, n), tm_) * kseg;
+    int64_t need = tm_ * k + k * tn_ + 2 * (tm_ * n + m * tn_) + m + n + tm_ + tn_ + part +
+                   std::max(sr.first, sc.first) + std::max(sr.second, sc.second);
+    if (use_c) need += 2 * (tm_ * n + m * tn_);
+    const size_t bytes = sizeof(double) * (size_t)need;
+    if (bytes > ws.uf_bytes) {
+        if (ws.uf) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(ws.uf));
+            ws.uf = nullptr;
+            ws.uf_bytes = 0;
+        }
+        HIP_TRY(hipMalloc((void **)&ws.uf, bytes));
+        ws.uf_bytes = bytes;
+    }
+    double *p = ws.uf;
+    auto take = [&](int64_t cnt) { double *q = p; p += cnt; return q; };
+    double *X = take(tm_ * k), *Y = take(k * tn_);
+    double *Pr = take(tm_ * n), *Rr = take(tm_ * n), *Pc = take(m * tn_), *Rc = take(m * tn_);
+    double *cr = nullptr, *cr2 = nullptr, *cc = nullptr, *cc2 = nullptr;
+    if (use_c) { cr = take(tm_ * n); cr2 = take(tm_ * n); cc = take(m * tn_); cc2 = take(m * tn_); }
+    double *rown2 = take(m), *coln2 = take(n), *xn2 = take(tm_), *yn2 = take(tn_);
+    double *pw = take(part);
+    double *wsp = take(std::max(sr.first, sc.first)), *chk = take(std::max(sr.second, sc.second));
+    const double *A = (const double *)d.A, *B = (const double *)d.B;
+    double *C = (double *)d.C;
+    const int nplan = ws.nplan;
+    if (report)
+        HIP_TRY(ftg::launch_clear_report(ws.counters, 1, ws.echo, nplan, ws.aux, 1, stream));
+    // C_in sums of every tile line (before C is overwritten)
+    if (use_c) {
+        HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, true, false, cr, tm_, false, stream));
+        HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, true, true, cr2, tm_, false, stream));
+        HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, false, false, cc, m, false, stream));
+        HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, false, true, cc2, m, false, stream));
+    }
+    // operand checksums: X(I, p) = sum_{i in I} op(A)(i, p) (tiles_m x k),
+    // Y(p, J) = sum_{j in J} op(B)(p, j) (k x tiles_n)
+    if (!ta)
+        HIP_TRY(ftg::launch_seg_sums(A, d.lda, m, k, T, true, false, X, tm_, false, stream));
+    else
+        HIP_TRY(ftg::launch_seg_sums(A, d.lda, k, m, T, false, false, X, tm_, true, stream));
+    if (!tb)
+        HIP_TRY(ftg::launch_seg_sums(B, d.ldb, k, n, T, false, false, Y, k, false, stream));
+    else
+        HIP_TRY(ftg::launch_seg_sums(B, d.ldb, n, k, T, true, false, Y, k, true, stream));
+    // |x_I|^2 and |y_J|^2
+    HIP_TRY(ftg::launch_seg_sums(X, tm_, tm_, k, T, false, true, pw, tm_, false, stream));
+    HIP_TRY(ftg::launch_seg_sums(pw, tm_, tm_, kseg, kseg, false, false, xn2, tm_, false, stream));
+    HIP_TRY(ftg::launch_seg_sums(Y, k, k, tn_, k, true, true, yn2, 1, false, stream));
+    // squared norms of the rows of op(A) and the columns of op(B)
+    if (!ta) {
+        HIP_TRY(ftg::launch_seg_sums(A, d.lda, m, k, T, false, true, pw, m, false, stream));
+        HIP_TRY(ftg::launch_seg_sums(pw, m, m, kseg, kseg, false, false, rown2, m, false, stream));
+    } else {
+        HIP_TRY(ftg::launch_seg_sums(A, d.lda, k, m, k, true, true, rown2, 1, false, stream));
+    }
+    if (!tb) {
+        HIP_TRY(ftg::launch_seg_sums(B, d.ldb, k, n, k, true, true, coln2, 1, false, stream));
+    } else {
+        HIP_TRY(ftg::launch_seg_sums(B, d.ldb, n, k, T, false, true, pw, n, false, stream));
+        HIP_TRY(ftg::launch_seg_sums(pw, n, n, kseg, kseg, false, false, coln2, n, false, stream));
+    }
+    // encoded product parts: Pr = X op(B) (tiles_m x n), Pc = op(A) Y (m x tiles_n)
+    if (ftgemm_status st = plain_f64(X, tm_, false, B, d.ldb, tb, tm_, n, k, 1.0, 0.0, Pr, tm_,
+                                     wsp, chk, ws, stream))
+        return st;
+    if (ftgemm_status st = plain_f64(A, d.lda, ta, Y, k, false, m, tn_, k, 1.0, 0.0, Pc, m, wsp,
+                                     chk, ws, stream))
+        return st;
+    // the product itself, checksum-free (split as the plain call would be)
+    {
+        int tm, tn, bk;
+        ftg::tiling_f64(&tm, &tn, &bk);
+        int64_t slice_k = k;
+        const int ns = choose_split(m, n, k, tm, tn, bk, &slice_k);
+        double *mw = nullptr, *mc = nullptr;
+        if (ns > 1) {
+            const size_t wbytes = sizeof(double) * (size_t)ns * m * n;
+            const size_t cbytes = sizeof(double) * (size_t)ns * tm_ * tn_ * 2 * (tm + tn);
+            if (ftgemm_status st = split_space(ws, wbytes + cbytes)) return st;
+            mw = ws.split;
+            mc = ws.split + (size_t)ns * m * n;
+        }
+        if (ftgemm_status st = plain_f64(A, d.lda, ta, B, d.ldb, tb, m, n, k, d.alpha, d.beta, C,
+                                         d.ldc, mw, mc, ws, stream))
+            return st;
+    }
+    HIP_TRY(ftg::launch_uf_inject(C, m, n, d.ldc, d.alpha, ws.plan, nplan, ws.echo, problem,
+                                  stream));
+    // reference sums of the output, then the comparison per tile
+    HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, true, false, Rr, tm_, false, stream));
+    HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, false, false, Rc, m, false, stream));
+    ftg::UfArgs a{};
+    a.Pr = Pr; a.Pc = Pc; a.Rr = Rr; a.Rc = Rc; a.cr = cr; a.cc = cc; a.cr2 = cr2; a.cc2 = cc2;
+    a.row_nrm2 = rown2; a.col_nrm2 = coln2; a.xn2 = xn2; a.yn2 = yn2;
+    a.m = m; a.n = n; a.k = k;
+    a.tiles_m = (int32_t)tm_; a.tiles_n = (int32_t)tn_; a.problem = problem; a.nplan = nplan;
+    a.alpha = d.alpha; a.beta = d.beta;
+    a.counters = ws.counters; a.records = ws.records; a.record_cap = kDevRecordCap;
+    a.rec_slot = ws.aux; a.plan = ws.plan; a.echo = ws.echo;
+    HIP_TRY(ftg::launch_uf_compare(a, stream));
+    return FTGEMM_OK;
+}
+
 ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t stream,
                       int32_t problem = 0)
 {
@@ -312,12 +499,17 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
         return FTGEMM_OK;
     }
     if (d.abft == 2 && d.dtype == FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
+    if (d.abft == 3 && d.dtype != FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
     if (d.dtype != FTGEMM_F64 && d.abft)
         for (const ftgemm_injection &f : g_plan)  // FP32 accumulators have 32 bits
             if (f.mode == FTGEMM_INJ_BITFLIP && f.bit >= 32) return invalid(14);
     DeviceWs *ws = nullptr;
     if (ftgemm_status st = workspace(&ws, 1)) return st;
+    if (d.abft == 3) {
+        if (ftgemm_status st = run_unfused(d, *ws, rep != nullptr, stream, problem)) return st;
+        return rep ? copy_report(*ws, rep, stream, problem) : FTGEMM_OK;
+    }
 
     int tm, tn, bk;
     if (d.dtype == FTGEMM_F64)
@@ -399,21 +591,7 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
         }
     } else
         HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft, pre, tm, stream));
-    if (rep && d.abft) {
-        HIP_TRY(hipMemcpyAsync(ws->h_counters, ws->counters, sizeof(DevCounters),
-                               hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipMemcpyAsync(ws->h_aux, ws->aux, sizeof(unsigned int),
-                               hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipMemcpyAsync(ws->h_records, ws->records,
-                               sizeof(ftgemm_fault_record) * kDevRecordCap,
-                               hipMemcpyDeviceToHost, stream));
-        if (ws->nplan)
-            HIP_TRY(hipMemcpyAsync(ws->h_echo, ws->echo,
-                                   sizeof(ftgemm_injection_echo) * ws->nplan,
-                                   hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        fill_report(*ws, 0, rep, problem);
-    }
+    if (rep && d.abft) return copy_report(*ws, rep, stream, problem);
     return FTGEMM_OK;
 }
 
@@ -573,7 +751,7 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
         if (int pos = check_args(descs[p])) return invalid(pos);
         const ftgemm_gemm_desc &d = descs[p];
         if (d.dtype != descs[0].dtype || (d.abft != 0) != (descs[0].abft != 0) ||
-            d.transA != descs[0].transA || d.transB != descs[0].transB || d.abft == 2)
+            d.transA != descs[0].transA || d.transB != descs[0].transB || d.abft >= 2)
             return FTGEMM_ERR_UNSUPPORTED;
         if (reps && ((reps[p].record_capacity && !reps[p].records) ||
                      (reps[p].echo_capacity && !reps[p].echoes)))
@@ -820,10 +998,11 @@ ftgemm_status ftgemm_query_tiling_ex(const ftgemm_gemm_desc *desc, int32_t *tm, 
     const ftgemm_gemm_desc &d = *desc;
     if (d.dtype != FTGEMM_F64 && d.dtype != FTGEMM_BF16 && d.dtype != FTGEMM_FP8_E4M3)
         return invalid(1);
-    if (d.abft < 0 || d.abft > 2) return invalid(1);
+    if (d.abft < 0 || d.abft > 3) return invalid(1);
     if (d.m < 0 || d.n < 0 || d.k < 0) return invalid(1);
     if (!tm || !tn || !bk || !split_k) return invalid(2);
     if (d.abft == 2 && d.dtype == FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
+    if (d.abft == 3 && d.dtype != FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
     int a = 0, b = 0, c = 0;
     int64_t slice_k = d.k;
     int s = 1;
@@ -871,6 +1050,7 @@ void ftgemm_finalize(void)
         if (ws.h_records) (void)hipHostFree(ws.h_records);
         if (ws.h_echo) (void)hipHostFree(ws.h_echo);
         if (ws.split) (void)hipFree(ws.split);
+        if (ws.uf) (void)hipFree(ws.uf);
         if (ws.aux) (void)hipFree(ws.aux);
         if (ws.h_aux) (void)hipHostFree(ws.h_aux);
         if (ws.exec) (void)hipGraphExecDestroy(ws.exec);

@@ -32,6 +32,38 @@ hipError_t launch_line_norms(const void *X, int64_t ld, int64_t R, int64_t Cn, b
                              bool along_rows, double *nrm2, double *amax, double *part,
                              int64_t part_cap, hipStream_t stream);
 
+// Unfused FP64 fault tolerance (detection only).  Segment sums of a
+// column-major R x Cn matrix of doubles over L consecutive rows (down; one
+// result per segment and column, at out[g + c * ldo]) or columns (across;
+// at out[r + g * ldo]); transpose swaps the two output indices; square sums
+// squares.
+hipError_t launch_seg_sums(const double *Z, int64_t ld, int64_t R, int64_t Cn, int64_t L,
+                           bool down, bool square, double *out, int64_t ldo, bool transpose,
+                           hipStream_t stream);
+// Output faults: C(row, col) += alpha * delta for the plan's ADD faults on
+// accumulators.
+hipError_t launch_uf_inject(double *C, int64_t m, int64_t n, int64_t ldc, double alpha,
+                            const ftgemm_injection *plan, int nplan, ftgemm_injection_echo *echo,
+                            int problem, hipStream_t stream);
+// Per 128 x 128 tile: entries of the tile's rows (Pc, Rc, cc, cc2: m x
+// tiles_n, leading dimension m) and columns (Pr, Rr, cr, cr2: tiles_m x n,
+// leading dimension tiles_m) verified against the thresholds built from the
+// line norms and |x_I|^2 (xn2), |y_J|^2 (yn2).
+struct UfArgs {
+    const double *Pr, *Pc, *Rr, *Rc, *cr, *cc, *cr2, *cc2;
+    const double *row_nrm2, *col_nrm2, *xn2, *yn2;
+    int64_t m, n, k;
+    int32_t tiles_m, tiles_n, problem, nplan;
+    double alpha, beta;
+    DevCounters *counters;
+    ftgemm_fault_record *records;
+    uint32_t record_cap;
+    unsigned int *rec_slot;
+    const ftgemm_injection *plan;
+    ftgemm_injection_echo *echo;
+};
+hipError_t launch_uf_compare(const UfArgs &a, hipStream_t stream);
+
 // Verified reduction of a split inner dimension (FP64): C = alpha * sum_s
 // W_s + beta * C, checked against the slices' encoded checksums.
 struct ReduceArgs {

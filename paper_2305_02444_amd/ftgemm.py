@@ -231,7 +231,7 @@ def make_desc(A, B, Cm, alpha=1.0, beta=0.0, transA=False, transB=False, abft=Tr
     d.dtype = _dtype_code(A) if dtype is None else dtype
     d.transA = OP_T if transA else OP_N
     d.transB = OP_T if transB else OP_N
-    # abft: False / True, or the mode number (0, 1, 2 = one-sided)
+    # abft: False / True, or the mode number (0, 1, 2 = one-sided, 3 = unfused)
     d.abft = int(abft) if not isinstance(abft, bool) else (1 if abft else 0)
     d.m, d.n, d.k = m, n, k
     d.lda, d.ldb, d.ldc = _ld(A), _ld(B), _ld(Cm)

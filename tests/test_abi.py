@@ -60,19 +60,24 @@ def test_gemm_ex_descriptor_checks():
 
 
 def test_abft_modes_checked_on_the_host():
-    """abft outside 0..2 is an argument error; the one-sided mode (2) is
-    refused for FP64 and in batches before anything runs."""
+    """abft outside 0..3 is an argument error; the one-sided mode (2) is
+    refused for FP64, the unfused mode (3) for BF16 and FP8, and both in
+    batches, before anything runs."""
     L = F.lib()
     d = F.GemmDesc()
     d.dtype, d.m, d.n, d.k, d.lda, d.ldb, d.ldc = F.BF16, 4, 4, 4, 4, 4, 4
     d.alpha, d.scaleA, d.scaleB, d.A, d.B, d.C = 1.0, 1.0, 1.0, 1, 1, 1
-    for bad in (-1, 3, 7):
+    for bad in (-1, 4, 7):
         d.abft = bad
         assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
         assert L.ftgemm_last_invalid_arg() == 14
     d.dtype, d.abft = F.F64, 2
     assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_UNSUPPORTED
     d.dtype = F.BF16
+    assert L.ftgemm_gemm_batched(1, C.byref(d), None, None) == F.ERR_UNSUPPORTED
+    d.abft = 3
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_UNSUPPORTED
+    d.dtype = F.F64
     assert L.ftgemm_gemm_batched(1, C.byref(d), None, None) == F.ERR_UNSUPPORTED
 
 
@@ -93,6 +98,11 @@ def test_query_tiling_ex():
     d = F.GemmDesc()
     d.dtype, d.abft, d.m, d.n, d.k = F.F64, 2, 64, 64, 64
     assert L.ftgemm_query_tiling_ex(C.byref(d), *[C.byref(x) for x in v]) == F.ERR_UNSUPPORTED
+    d.dtype, d.abft = F.BF16, 3
+    assert L.ftgemm_query_tiling_ex(C.byref(d), *[C.byref(x) for x in v]) == F.ERR_UNSUPPORTED
+    d.dtype, d.abft = F.F64, 3
+    assert L.ftgemm_query_tiling_ex(C.byref(d), *[C.byref(x) for x in v]) == F.OK
+    assert [x.value for x in v] == list(F.query_tiling(F.F64, 64, 64, 64))
     d.abft = 5
     assert L.ftgemm_query_tiling_ex(C.byref(d), *[C.byref(x) for x in v]) == F.ERR_INVALID_ARG
     d.abft = 1
