@@ -6,7 +6,7 @@ kernel with every checksum operation compiled out, at 8192^3 in FP64 (the
 headline) and BF16 / FP8 (extra legs), with and without injected faults.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
-    python bench.py --profile {f64,bf16,fp8,copy}   (for rocprofv3 passes)
+    python bench.py --profile {f64,f64-unfused,bf16,fp8,copy}   (for rocprofv3 passes)
 
 A step is one full fault-tolerant GEMM call C = alpha*A*B + beta*C
 (alpha = beta = 1, inputs uniform on [-1, 1], column-major N/N) on inputs
@@ -341,13 +341,13 @@ def profile_run(kind, size, calls=3):
         return
     m = n = k = size
     g = torch.Generator(device="cuda").manual_seed(5)
-    if kind == "f64":
+    if kind in ("f64", "f64-unfused"):
         A = F.colmajor_empty(m, k, torch.float64)
         B = F.colmajor_empty(k, n, torch.float64)
         A.uniform_(-1, 1, generator=g)
         B.uniform_(-1, 1, generator=g)
         Cm = F.colmajor_empty(m, n, torch.float64).uniform_(-1, 1, generator=g)
-        d = F.make_desc(A, B, Cm, 1.0, 1.0)
+        d = F.make_desc(A, B, Cm, 1.0, 1.0, abft=3 if kind == "f64-unfused" else True)
     else:
         dt = torch.bfloat16 if kind == "bf16" else torch.float8_e4m3fn
         A = F.colmajor_empty(m, k, torch.float32).normal_(generator=g)
@@ -377,7 +377,7 @@ def main():
     ap.add_argument("--no-low-precision", action="store_true")
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--profile", choices=["f64", "bf16", "fp8", "copy"])
+    ap.add_argument("--profile", choices=["f64", "f64-unfused", "bf16", "fp8", "copy"])
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -432,7 +432,18 @@ def main():
     rb = F.ReportBuffer()
     F.gemm(dA, dB, dC, 1.0, 1.0, report=rb)
     inj = rb.view()
+    # the unfused ablation (separate checksum passes around the plain
+    # GEMM, detection only) under the same faults, then error-free
+    rb = F.ReportBuffer()
+    F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=3), report=rb)
+    inj_uf = rb.view()
+    t_uf_inj, _ = timed(torch, call(3), args.steps, args.warmup)
     F.clear_fault_plan()
+    dC.copy_(dC0)
+    rb = F.ReportBuffer()
+    F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=3), report=rb)
+    clean_uf = rb.view()
+    t_uf, _ = timed(torch, call(3), args.steps, args.warmup)
 
     value = flops / (t_ft * 1e-3) / 1e12
     achieved = flops / (t_ft_ev * 1e-3) / 1e12
@@ -465,6 +476,15 @@ def main():
                      "corrected": int(inj.corrected), "detected": int(inj.detected)},
         "error_free_check": {"detected": int(clean.detected), "max_ratio": clean.max_ratio,
                              "tiles_verified": int(clean.tiles_verified)},
+        "unfused": {"tflops": round(flops / (t_uf * 1e-3) / 1e12, 3),
+                    "ms_per_call": round(t_uf, 4),
+                    "abft_overhead_pct": round(100.0 * (t_uf / t_plain - 1.0), 2),
+                    "error_free_check": {"detected": int(clean_uf.detected),
+                                         "max_ratio": clean_uf.max_ratio,
+                                         "tiles_verified": int(clean_uf.tiles_verified)},
+                    "injected": {"faults_per_call": len(plan),
+                                 "overhead_pct": round(100.0 * (t_uf_inj / t_plain - 1.0), 2),
+                                 "detected": int(inj_uf.detected)}},
     }
     if not args.no_low_precision:
         del dA, dB, dC, dC0

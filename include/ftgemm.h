@@ -155,6 +155,18 @@ typedef struct {
  *      kept, one entry per row, and a tile with any disagreeing row is
  *      computed again (records: kind RECOMPUTED, col -1).  Faults planned
  *      on the row checksum have no entry to land on and are not applied.
+ *   3  unfused (F64 single calls only; FTGEMM_ERR_UNSUPPORTED for BF16 /
+ *      FP8 and in batches): the comparison the fusion is measured against
+ *      (Section 2.2).  The same 128 x 128 tile checksums and thresholds as
+ *      mode 1, formed by separate passes over A, B and C around the
+ *      checksum-free GEMM (segment sums, two thin GEMMs for the encoded
+ *      parts, a compare kernel); detection only: every inconsistent tile
+ *      gets one record of kind UNCORRECTABLE and the output is left as
+ *      computed.  Planned faults: additions on accumulators (applied to the
+ *      finished output as alpha * delta) and on either checksum; bit flips
+ *      are not applied.  Its workspace ((m + n) k / 128 + 8 m n / 128
+ *      doubles, plus the thin GEMMs' split slices) is grown on demand and
+ *      kept.
  * BF16 / FP8 single calls with abft 1 or 2 take the threshold norms of the
  * rows of op(A) and columns of op(B) in one pass over A and B before the
  * product, using the library's workspace (batches compute them in the
@@ -228,7 +240,9 @@ ftgemm_status ftgemm_query_tiling(ftgemm_dtype dtype, int64_t m, int64_t n, int6
  * the other fields are not read): in the one-sided mode FP8 also takes
  * 256 x 128 tiles from 256 tiles on.  Errors: desc NULL or its fields out of
  * range (position 1), an output pointer NULL (position 2); one-sided F64
- * returns FTGEMM_ERR_UNSUPPORTED. */
+ * and unfused BF16 / FP8 return FTGEMM_ERR_UNSUPPORTED.  The unfused mode
+ * reports the tiling of its checksum-free product (its verification tiles
+ * are 128 x 128, as the F64 kernel's). */
 ftgemm_status ftgemm_query_tiling_ex(const ftgemm_gemm_desc *desc, int32_t *tm, int32_t *tn,
                                      int32_t *bk, int32_t *split_k);
 

@@ -403,41 +403,43 @@ ftgemm_status run_unfused(const ftgemm_gemm_desc &d, DeviceWs &ws, bool report,
     const double *A = (const double *)d.A, *B = (const double *)d.B;
     double *C = (double *)d.C;
     const int nplan = ws.nplan;
+    auto seg = [stream](const double *Z, int64_t ld, int64_t R, int64_t Cn, int64_t L, bool down,
+                        bool sq, double *out, double *out2, int64_t ldo, bool tr) {
+        return ftg::launch_seg_sums(Z, ld, R, Cn, L, down, sq, out, out2, ldo, tr, stream);
+    };
     if (report)
         HIP_TRY(ftg::launch_clear_report(ws.counters, 1, ws.echo, nplan, ws.aux, 1, stream));
     // C_in sums of every tile line (before C is overwritten)
     if (use_c) {
-        HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, true, false, cr, tm_, false, stream));
-        HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, true, true, cr2, tm_, false, stream));
-        HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, false, false, cc, m, false, stream));
-        HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, false, true, cc2, m, false, stream));
+        HIP_TRY(seg(C, d.ldc, m, n, T, true, false, cr, cr2, tm_, false));
+        HIP_TRY(seg(C, d.ldc, m, n, T, false, false, cc, cc2, m, false));
     }
     // operand checksums: X(I, p) = sum_{i in I} op(A)(i, p) (tiles_m x k),
     // Y(p, J) = sum_{j in J} op(B)(p, j) (k x tiles_n)
     if (!ta)
-        HIP_TRY(ftg::launch_seg_sums(A, d.lda, m, k, T, true, false, X, tm_, false, stream));
+        HIP_TRY(seg(A, d.lda, m, k, T, true, false, X, nullptr, tm_, false));
     else
-        HIP_TRY(ftg::launch_seg_sums(A, d.lda, k, m, T, false, false, X, tm_, true, stream));
+        HIP_TRY(seg(A, d.lda, k, m, T, false, false, X, nullptr, tm_, true));
     if (!tb)
-        HIP_TRY(ftg::launch_seg_sums(B, d.ldb, k, n, T, false, false, Y, k, false, stream));
+        HIP_TRY(seg(B, d.ldb, k, n, T, false, false, Y, nullptr, k, false));
     else
-        HIP_TRY(ftg::launch_seg_sums(B, d.ldb, n, k, T, true, false, Y, k, true, stream));
+        HIP_TRY(seg(B, d.ldb, n, k, T, true, false, Y, nullptr, k, true));
     // |x_I|^2 and |y_J|^2
-    HIP_TRY(ftg::launch_seg_sums(X, tm_, tm_, k, T, false, true, pw, tm_, false, stream));
-    HIP_TRY(ftg::launch_seg_sums(pw, tm_, tm_, kseg, kseg, false, false, xn2, tm_, false, stream));
-    HIP_TRY(ftg::launch_seg_sums(Y, k, k, tn_, k, true, true, yn2, 1, false, stream));
+    HIP_TRY(seg(X, tm_, tm_, k, T, false, true, pw, nullptr, tm_, false));
+    HIP_TRY(seg(pw, tm_, tm_, kseg, kseg, false, false, xn2, nullptr, tm_, false));
+    HIP_TRY(seg(Y, k, k, tn_, k, true, true, yn2, nullptr, 1, false));
     // squared norms of the rows of op(A) and the columns of op(B)
     if (!ta) {
-        HIP_TRY(ftg::launch_seg_sums(A, d.lda, m, k, T, false, true, pw, m, false, stream));
-        HIP_TRY(ftg::launch_seg_sums(pw, m, m, kseg, kseg, false, false, rown2, m, false, stream));
+        HIP_TRY(seg(A, d.lda, m, k, T, false, true, pw, nullptr, m, false));
+        HIP_TRY(seg(pw, m, m, kseg, kseg, false, false, rown2, nullptr, m, false));
     } else {
-        HIP_TRY(ftg::launch_seg_sums(A, d.lda, k, m, k, true, true, rown2, 1, false, stream));
+        HIP_TRY(seg(A, d.lda, k, m, k, true, true, rown2, nullptr, 1, false));
     }
     if (!tb) {
-        HIP_TRY(ftg::launch_seg_sums(B, d.ldb, k, n, k, true, true, coln2, 1, false, stream));
+        HIP_TRY(seg(B, d.ldb, k, n, k, true, true, coln2, nullptr, 1, false));
     } else {
-        HIP_TRY(ftg::launch_seg_sums(B, d.ldb, n, k, T, false, true, pw, n, false, stream));
-        HIP_TRY(ftg::launch_seg_sums(pw, n, n, kseg, kseg, false, false, coln2, n, false, stream));
+        HIP_TRY(seg(B, d.ldb, n, k, T, false, true, pw, nullptr, n, false));
+        HIP_TRY(seg(pw, n, n, kseg, kseg, false, false, coln2, nullptr, n, false));
     }
     // encoded product parts: Pr = X op(B) (tiles_m x n), Pc = op(A) Y (m x tiles_n)
     if (ftgemm_status st = plain_f64(X, tm_, false, B, d.ldb, tb, tm_, n, k, 1.0, 0.0, Pr, tm_,
@@ -467,8 +469,8 @@ ftgemm_status run_unfused(const ftgemm_gemm_desc &d, DeviceWs &ws, bool report,
     HIP_TRY(ftg::launch_uf_inject(C, m, n, d.ldc, d.alpha, ws.plan, nplan, ws.echo, problem,
                                   stream));
     // reference sums of the output, then the comparison per tile
-    HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, true, false, Rr, tm_, false, stream));
-    HIP_TRY(ftg::launch_seg_sums(C, d.ldc, m, n, T, false, false, Rc, m, false, stream));
+    HIP_TRY(seg(C, d.ldc, m, n, T, true, false, Rr, nullptr, tm_, false));
+    HIP_TRY(seg(C, d.ldc, m, n, T, false, false, Rc, nullptr, m, false));
     ftg::UfArgs a{};
     a.Pr = Pr; a.Pc = Pc; a.Rr = Rr; a.Rc = Rc; a.cr = cr; a.cc = cc; a.cr2 = cr2; a.cc2 = cc2;
     a.row_nrm2 = rown2; a.col_nrm2 = coln2; a.xn2 = xn2; a.yn2 = yn2;

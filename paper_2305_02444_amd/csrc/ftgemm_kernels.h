@@ -36,10 +36,10 @@ hipError_t launch_line_norms(const void *X, int64_t ld, int64_t R, int64_t Cn, b
 // column-major R x Cn matrix of doubles over L consecutive rows (down; one
 // result per segment and column, at out[g + c * ldo]) or columns (across;
 // at out[r + g * ldo]); transpose swaps the two output indices; square sums
-// squares.
+// squares; out2 (may be null) receives the sums of squares in the same pass.
 hipError_t launch_seg_sums(const double *Z, int64_t ld, int64_t R, int64_t Cn, int64_t L,
-                           bool down, bool square, double *out, int64_t ldo, bool transpose,
-                           hipStream_t stream);
+                           bool down, bool square, double *out, double *out2, int64_t ldo,
+                           bool transpose, hipStream_t stream);
 // Output faults: C(row, col) += alpha * delta for the plan's ADD faults on
 // accumulators.
 hipError_t launch_uf_inject(double *C, int64_t m, int64_t n, int64_t ldc, double alpha,
