@@ -598,6 +598,53 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
                 }
                 break;
             }
+        } else if (nbad_r == nbad_c && nbad_r >= 2 && nbad_r <= MAX_LINE_FIXES) {
+            /* As many flagged rows as flagged columns: errors in distinct
+             * rows and columns.  An error shows as the same residual on its
+             * row and on its column, so each flagged row is paired with the
+             * flagged column whose residual agrees with its own within the
+             * two thresholds.  When every row finds exactly one such column
+             * and no column is found twice, each crossing loses its
+             * column's residual (as a line correction does).  Otherwise --
+             * errors of equal size, errors sharing lines, a checksum fault
+             * among them, a residual that is not finite -- the tile is
+             * computed again. */
+            int64_t rows[MAX_LINE_FIXES], cols[MAX_LINE_FIXES], mate[MAX_LINE_FIXES];
+            int64_t nr = 0, nc = 0;
+            for (int64_t ii = 0; ii < h; ++ii)
+                if (!(fabs(Rc[ii] - Pc[ii]) <= tc[ii])) rows[nr++] = ii;
+            for (int64_t jj = 0; jj < w; ++jj)
+                if (!(fabs(Rr[jj] - Pr[jj]) <= tr[jj])) cols[nc++] = jj;
+            int paired = 1;
+            unsigned taken = 0;
+            for (int64_t a = 0; a < nr && paired; ++a) {
+                const double dr = Rc[rows[a]] - Pc[rows[a]];
+                int64_t found = 0;
+                for (int64_t b = 0; b < nc; ++b) {
+                    const double dc = Rr[cols[b]] - Pr[cols[b]];
+                    if (fabs(dr - dc) <= tc[rows[a]] + tr[cols[b]]) { ++found; mate[a] = b; }
+                }
+                if (found != 1 || (taken >> mate[a]) & 1u) paired = 0;
+                else taken |= 1u << mate[a];
+            }
+            if (paired) {
+                const double before = out[rows[0] + cols[mate[0]] * h];
+                for (int64_t a = 0; a < nr; ++a) {
+                    const int64_t jj = cols[mate[a]];
+                    out[rows[a] + jj * h] -= Rr[jj] - Pr[jj];
+                }
+                /* the record names the first flagged row's element */
+                jbad = cols[mate[0]];
+                if (rec) {
+                    rec->kind = KIND_CORRECTED;
+                    rec->col = j0 + jbad;
+                    rec->d_row = Rr[jbad] - Pr[jbad];
+                    rec->tau_row = tr[jbad];
+                    rec->before = before;
+                    rec->after = out[ibad + jbad * h];
+                }
+                break;
+            }
         } else if (nbad_r + nbad_c == 1) {
             /* A single encoded checksum entry disagrees while every sum on
              * the other side matches: the fault hit the checksum path and

@@ -162,15 +162,16 @@ def pin_nonfinite_recovery(orc):
 
 
 def pin_classification(orc):
-    """Two errors in one tile -> recomputed; a fault in an encoded checksum
-    only -> checksum-only with C untouched; a perturbation far below the
-    rounding threshold -> not flagged."""
+    """Two equal errors in one tile (their rows and columns cannot be
+    paired) -> recomputed; a fault in an encoded checksum only ->
+    checksum-only with C untouched; a perturbation far below the rounding
+    threshold -> not flagged."""
     g = np.random.default_rng(16)
     m, n, k = 32, 32, 48
     A = np.asfortranarray(g.uniform(-1, 1, (m, k)))
     B = np.asfortranarray(g.uniform(-1, 1, (k, n)))
     Cff = A @ B
-    two = [O.Injection(1, 2, 3, O.ADD, 50.0), O.Injection(5, 9, 40, O.ADD, -20.0)]
+    two = [O.Injection(1, 2, 3, O.ADD, 50.0), O.Injection(5, 9, 40, O.ADD, 50.0)]
     r = orc.ftgemm(A, B, tm=16, tn=16, bk=16, injections=two)
     assert [d["kind"] for d in r.records] == [O.RECOMPUTED]
     assert r.records[0]["nbad_rows"] == 2 and r.records[0]["nbad_cols"] == 2
@@ -259,6 +260,51 @@ def pin_line_correction(orc):
     assert np.array_equal(r.C, Cff)
 
 
+def pin_crossing_pairs(orc):
+    """Errors in distinct rows and columns of a tile, on integer data: the
+    flagged rows and columns are exactly those where the faulty output
+    differs from the fault-free product (brute force); each row is paired
+    with the column of equal residual, each crossing loses that residual,
+    and the output equals the fault-free product bit for bit.  Errors that
+    cannot be paired one to one -> recomputed: two equal errors, three
+    errors on the corners of a rectangle, a data error beside a fault on
+    each checksum, five errors."""
+    g = synth.rng(94, 0, 0)
+    m, n, k = 32, 32, 24
+    A = np.asfortranarray(g.integers(-8, 9, (m, k)).astype(float))
+    B = np.asfortranarray(g.integers(-8, 9, (k, n)).astype(float))
+    Cin = np.asfortranarray(g.integers(-8, 9, (m, n)).astype(float))
+    Cff = 3.0 * (A @ B) + 2.0 * Cin
+    Inj = O.Injection
+    run = lambda plan: orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=8, injections=plan)
+    # two in tile (0, 0), four in tile (1, 1), three in tile (1, 0)
+    plan = [Inj(9, 2, 3, O.ADD, 100.0), Inj(4, 11, 17, O.ADD, -40.0),
+            Inj(16, 16, 0, O.ADD, 7.0), Inj(20, 30, 8, O.ADD, 9.0), Inj(25, 18, 8, O.ADD, -3.0),
+            Inj(31, 25, 23, O.ADD, 1.0e6),
+            Inj(17, 1, 5, O.ADD, 50.0), Inj(23, 9, 9, O.ADD, 60.0), Inj(30, 14, 20, O.ADD, -70.0)]
+    r = run(plan)
+    assert np.array_equal(r.C, Cff)
+    for d in r.records:
+        i0, j0 = 16 * d["tile_m"], 16 * d["tile_n"]
+        bad = np.argwhere(r.raw[i0:i0 + 16, j0:j0 + 16] != Cff[i0:i0 + 16, j0:j0 + 16])
+        assert d["nbad_rows"] == len(set(bad[:, 0])) == d["nbad_cols"] == len(set(bad[:, 1]))
+    got = sorted((d["kind"], d["row"], d["col"], d["nbad_rows"]) for d in r.records)
+    # the record names the first flagged row and the column it was paired with
+    assert got == [(O.CORRECTED, 4, 11, 2), (O.CORRECTED, 16, 16, 4), (O.CORRECTED, 17, 1, 3)]
+    d = [d for d in r.records if d["row"] == 4][0]
+    assert d["before"] == Cff[4, 11] - 120.0 and d["after"] == Cff[4, 11]
+    assert d["d_row"] == d["d_col"] == -120.0
+    for plan in ([Inj(2, 3, 1, O.ADD, 25.0), Inj(7, 12, 9, O.ADD, 25.0)],
+                 [Inj(2, 3, 1, O.ADD, 25.0), Inj(2, 12, 9, O.ADD, 40.0),
+                  Inj(7, 3, 9, O.ADD, 55.0)],
+                 [Inj(2, 3, 1, O.ADD, 25.0), Inj(7, 12, 9, O.ADD, 40.0, target=O.TGT_ROW_CHECKSUM),
+                  Inj(9, 14, 9, O.ADD, 55.0, target=O.TGT_COL_CHECKSUM)],
+                 [Inj(i, i + 1, 2, O.ADD, 10.0 * (i + 1)) for i in range(0, 15, 3)]):
+        r = run(plan)
+        assert [d["kind"] for d in r.records] == [O.RECOMPUTED], plan
+        assert np.array_equal(r.C, Cff)
+
+
 def pin_one_sided(orc):
     """One-sided mode (only the column checksum, one entry per row;
     recompute on any disagreement).  On integer data: each accumulator fault
@@ -335,5 +381,6 @@ def pin_ragged_and_subset(orc):
 
 ALL_PINS = [pin_gemm_vs_numpy, pin_gemm_integer_exact, pin_blas_special_cases,
             pin_checksum_identities, pin_brute_force_location, pin_exact_recovery,
-            pin_nonfinite_recovery, pin_classification, pin_line_correction, pin_one_sided,
+            pin_nonfinite_recovery, pin_classification, pin_line_correction,
+            pin_crossing_pairs, pin_one_sided,
             pin_no_false_positives, pin_ragged_and_subset]

@@ -20,6 +20,11 @@ MUTANTS = {
     "line_confirmed_without_its_own_residual": (
         "if (fabs(dl - sumd) <= (by_row ? tc[line] : tr[line])) {",
         "if (fabs(sumd) <= (by_row ? tc[line] : tr[line]) || 1) {"),
+    "pair_residual_added_not_subtracted": (
+        "out[rows[a] + jj * h] -= Rr[jj] - Pr[jj];", "out[rows[a] + jj * h] += Rr[jj] - Pr[jj];"),
+    "pairing_not_one_to_one": (
+        "if (found != 1 || (taken >> mate[a]) & 1u) paired = 0;",
+        "if (found < 1) paired = 0;"),
     "transposed_operand_A": (
         "return ta ? A[p + i * lda] : A[i + p * lda];",
         "return ta ? A[i + p * lda] : A[p + i * lda];"),
