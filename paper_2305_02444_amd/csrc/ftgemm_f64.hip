@@ -210,7 +210,7 @@ __device__ __forceinline__ int owner_reg(int row, int col)
 }
 
 template <bool TA, bool TB, bool ABFT>
-__device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
+__device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
 {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w & 1, wn = w >> 1;
@@ -261,6 +261,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
     }
 
     int kind = 0, first_nr = 0, first_nc = 0, first_i = -1, first_j = -1;
+    int npairs = 0;                 // corrections left for the stored tile
+    unsigned rslot = 0xffffffffu;   // record slot (thread 0)
     double rec_before = 0, rec_after = 0;
 
     d4 acc[4][2];
@@ -675,6 +677,51 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 kind = FTGEMM_KIND_CORRECTED;
                 break;
             }
+        } else if (nr == nc && nr >= 2 && nr <= kMaxLineFixes) {
+            // Errors in distinct rows and columns: each flagged row is paired
+            // with the one flagged column whose residual agrees with its own
+            // within the two thresholds; a one-to-one pairing is corrected
+            // (each crossing loses its column's residual), anything else is
+            // computed again.  The pairs go to a table by row in LDS (the
+            // encoded-sum partials are no longer needed); the lanes that
+            // hold the elements apply them to the stored tile (see below),
+            // which keeps this rare path off the registers of the others.
+            int *pcol = reinterpret_cast<int *>(sm.u.epi.enc_row[1]);
+            double *pd = sm.u.epi.enc_row[0];
+            if (t == 0) {
+                unsigned taken = 0;
+                int named = -1;
+                for (int a = 0; a < nr; ++a) {
+                    const int i = sm.bad_r[a];
+                    int found = 0, mate = 0, mb = 0;
+                    for (int b = 0; b < nc; ++b) {
+                        const int j = sm.bad_c[b];
+                        if (fabs(sm.u.epi.d_row[i] - sm.u.epi.d_col[j]) <=
+                            sm.u.epi.tau_row[i] + sm.u.epi.tau_col[j]) {
+                            ++found;
+                            mate = j;
+                            mb = b;
+                        }
+                    }
+                    if (found != 1 || ((taken >> mb) & 1u) || named == -2) {
+                        named = -2;
+                        continue;
+                    }
+                    taken |= 1u << mb;
+                    pcol[i] = mate;
+                    pd[i] = sm.u.epi.d_col[mate];
+                    if (i == first_i) named = mate;
+                }
+                sm.red[3][0] = (double)(named >= 0 ? named : -1);
+            }
+            __syncthreads();
+            const int named = (int)sm.red[3][0];
+            if (named >= 0) {
+                first_j = named;
+                npairs = nr;
+                kind = FTGEMM_KIND_CORRECTED;
+                break;
+            }
         } else if (nr + nc == 1) {
             kind = FTGEMM_KIND_CHECKSUM_ONLY;
             break;
@@ -694,7 +741,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
     if (ABFT) {
         const int t = fresh_tid(), lane = t & 63, w = t >> 6;
         const int wm = w & 1, wn = w >> 1, q = lane >> 4, c16 = lane & 15;
-        if (kind == FTGEMM_KIND_CORRECTED) {
+        if (kind == FTGEMM_KIND_CORRECTED && npairs == 0) {
             // the owner lane of a corrected element knows its old value
             __syncthreads();
             if (w == owner_wave(first_i, first_j) && lane == owner_lane(first_i, first_j)) {
@@ -719,6 +766,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                 atomicAdd(&ct->record_count, 1u);
                 const unsigned slot = atomicAdd(g.rec_slot, 1u);
                 if (slot < g.record_cap) {
+                    rslot = slot;
                     // residuals: from LDS of this attempt (corrected /
                     // checksum-only) or saved from the first attempt
                     const bool again = kind == FTGEMM_KIND_RECOMPUTED ||
@@ -770,6 +818,39 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
                     if (row < hrows && col < wcols)
                         C[(i0 + row) + (j0 + col) * ldc] = acc[mi][ni][r];
                 }
+        if (npairs > 0) {
+            // Paired corrections: the lane that stored each element takes
+            // the pair's residual off it in memory (its own store is ordered
+            // before its atomics on the same address); the named element's
+            // old and new values complete the record.
+            const int *pcol = reinterpret_cast<const int *>(sm.u.epi.enc_row[1]);
+            const double *pd = sm.u.epi.enc_row[0];
+            for (int f = 0; f < npairs; ++f) {
+                const int i = sm.bad_r[f], j = pcol[i];
+                if (w != owner_wave(i, j) || lane != owner_lane(i, j)) continue;
+                unsigned long long *a = reinterpret_cast<unsigned long long *>(
+                    C + (i0 + i) + (j0 + j) * ldc);
+                unsigned long long cur = atomicOr(a, 0ull);
+                double before = __longlong_as_double((long long)cur), after = before - pd[i];
+                for (int it = 0; it < 4; ++it) {
+                    const unsigned long long prev =
+                        atomicCAS(a, cur, (unsigned long long)__double_as_longlong(after));
+                    if (prev == cur) break;
+                    cur = prev;
+                    before = __longlong_as_double((long long)cur);
+                    after = before - pd[i];
+                }
+                if (i == first_i) {
+                    sm.red[2][0] = before;
+                    sm.red[2][1] = after;
+                }
+            }
+            __syncthreads();
+            if (t == 0 && rslot < g.record_cap) {
+                g.records[rslot].before = sm.red[2][0];
+                g.records[rslot].after = sm.red[2][1];
+            }
+        }
     }
 }
 

@@ -475,7 +475,7 @@ __device__ __forceinline__ int owner_reg(int row, int col)
 // from g.row_nrm2 / g.col_nrm2 / g.row_max / g.col_max, taken before the
 // product, instead of from the staged operands.
 template <bool FP8, bool TA, bool TB, bool ABFT, int BM, bool ONE = false, bool PRE = false>
-__device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
+__device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
 {
     using E = Elem<FP8>;
     using G = Geo<BM>;
@@ -520,6 +520,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
     }
 
     int kind = 0, first_nr = 0, first_nc = 0, first_i = -1, first_j = -1;
+    int npairs = 0;                 // corrections left for the stored tile
+    unsigned rslot = 0xffffffffu;   // record slot (thread 0)
     double rec_before = 0, rec_after = 0;
 
     // Checksum products of a staged step (BF16): the x-part rows times this
@@ -1084,6 +1086,51 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                 kind = FTGEMM_KIND_CORRECTED;
                 break;
             }
+        } else if (nr == nc && nr >= 2 && nr <= kMaxLineFixes) {
+            // Errors in distinct rows and columns: each flagged row is paired
+            // with the one flagged column whose residual agrees with its own
+            // within the two thresholds; a one-to-one pairing is corrected
+            // (each crossing loses its column's residual), anything else is
+            // computed again.  The pairs go to a table by row in LDS (the
+            // encoded-sum partials are no longer needed); the lanes that
+            // hold the elements apply them to the stored tile (see below),
+            // which keeps this rare path off the registers of the others.
+            int *pcol = reinterpret_cast<int *>(sm.u.epi.enc_row[1]);
+            double *pd = sm.u.epi.enc_row[0];
+            if (t == 0) {
+                unsigned taken = 0;
+                int named = -1;
+                for (int a = 0; a < nr; ++a) {
+                    const int i = sm.bad_r[a];
+                    int found = 0, mate = 0, mb = 0;
+                    for (int b = 0; b < nc; ++b) {
+                        const int j = sm.bad_c[b];
+                        if (fabs(sm.u.epi.d_row[i] - sm.u.epi.d_col[j]) <=
+                            sm.u.epi.tau_row[i] + sm.u.epi.tau_col[j]) {
+                            ++found;
+                            mate = j;
+                            mb = b;
+                        }
+                    }
+                    if (found != 1 || ((taken >> mb) & 1u) || named == -2) {
+                        named = -2;
+                        continue;
+                    }
+                    taken |= 1u << mb;
+                    pcol[i] = mate;
+                    pd[i] = sm.u.epi.d_col[mate];
+                    if (i == first_i) named = mate;
+                }
+                sm.red[3][0] = (double)(named >= 0 ? named : -1);
+            }
+            __syncthreads();
+            const int named = (int)sm.red[3][0];
+            if (named >= 0) {
+                first_j = named;
+                npairs = nr;
+                kind = FTGEMM_KIND_CORRECTED;
+                break;
+            }
         } else if (nr + nc == 1) {
             kind = FTGEMM_KIND_CHECKSUM_ONLY;
             break;
@@ -1101,7 +1148,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
     if (ABFT) {
         const int t = fresh_tid(), lane = t & 63, w = t >> 6;
         const int wm = w % G::WM, wn = w / G::WM, q = lane >> 4, c16 = lane & 15;
-        if (kind == FTGEMM_KIND_CORRECTED) {
+        if (kind == FTGEMM_KIND_CORRECTED && npairs == 0) {
             __syncthreads();
             if (w == owner_wave<BM>(first_i, first_j) && lane == owner_lane(first_i, first_j)) {
                 sm.red[2][0] = rec_before;
@@ -1125,6 +1172,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                 atomicAdd(&ct->record_count, 1u);
                 const unsigned slot = atomicAdd(g.rec_slot, 1u);
                 if (slot < g.record_cap) {
+                    rslot = slot;
                     const bool again = kind == FTGEMM_KIND_RECOMPUTED ||
                                        kind == FTGEMM_KIND_UNCORRECTABLE;
                     ftgemm_fault_record rc;
@@ -1157,6 +1205,38 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                     if (row < hrows && col < wcols)
                         C[(i0 + row) + (j0 + col) * ldc] = acc[mi][ni][r];
                 }
+        if (npairs > 0) {
+            // Paired corrections: the lane that stored each element takes
+            // the pair's residual off it in memory (its own store is ordered
+            // before its atomics on the same address); the named element's
+            // old and new values complete the record.
+            const int *pcol = reinterpret_cast<const int *>(sm.u.epi.enc_row[1]);
+            const double *pd = sm.u.epi.enc_row[0];
+            for (int f = 0; f < npairs; ++f) {
+                const int i = sm.bad_r[f], j = pcol[i];
+                if (w != owner_wave<BM>(i, j) || lane != owner_lane(i, j)) continue;
+                unsigned *a = reinterpret_cast<unsigned *>(C + (i0 + i) + (j0 + j) * ldc);
+                unsigned cur = atomicOr(a, 0u);
+                float before = __uint_as_float(cur);
+                float after = (float)((double)before - pd[i]);
+                for (int it = 0; it < 4; ++it) {
+                    const unsigned prev = atomicCAS(a, cur, __float_as_uint(after));
+                    if (prev == cur) break;
+                    cur = prev;
+                    before = __uint_as_float(cur);
+                    after = (float)((double)before - pd[i]);
+                }
+                if (i == first_i) {
+                    sm.red[2][0] = (double)before;
+                    sm.red[2][1] = (double)after;
+                }
+            }
+            __syncthreads();
+            if (t == 0 && rslot < g.record_cap) {
+                g.records[rslot].before = sm.red[2][0];
+                g.records[rslot].after = sm.red[2][1];
+            }
+        }
     }
 }
 

@@ -131,8 +131,43 @@ def test_line_corrections():
     assert np.all(np.isfinite(got))
 
 
+def test_crossing_pairs():
+    """Errors in distinct rows and columns of a tile: two, four and three
+    per tile, each flagged row paired with the column of equal residual and
+    corrected; two equal errors, and three on the corners of a rectangle,
+    cannot be paired -> recomputed.  C within 1e-12 of the oracle's; the
+    record names the first flagged row and its paired column, with the
+    oracle's values before and after."""
+    m, n, k = 384, 300, 200
+    A, B, Cin = synth.operands(8, 0, m, n, k, "uniform")
+    F_ = synth.Fault
+    plan = [F_(17, 90, 10, synth.ADD, 30.0), F_(60, 3, 150, synth.ADD, -40.0),      # (0, 0)
+            F_(140, 250, 5, synth.ADD, 2.0), F_(150, 130, 60, synth.ADD, 5.0),      # (1, 1)
+            F_(200, 200, 199, synth.ADD, -3.0), F_(255, 155, 99, synth.ADD, 6.0),
+            F_(260, 280, 0, synth.ADD, 20.0), F_(300, 260, 70, synth.ADD, 8.0),     # (2, 2)
+            F_(383, 299, 199, synth.ADD, -5.0),
+            F_(10, 260, 3, synth.ADD, 7.0), F_(20, 270, 30, synth.ADD, 7.0),        # (0, 2)
+            F_(270, 10, 3, synth.ADD, 4.0), F_(270, 20, 30, synth.ADD, 9.0),        # (2, 0)
+            F_(280, 10, 50, synth.ADD, 11.0)]
+    got, rep, ref = _compare(A, B, Cin, 1.0, 0.5, False, False, plan)
+    kinds = {(r["tile_m"], r["tile_n"]): r["kind"] for r in rep.records}
+    assert kinds == {(0, 0): F.KIND_CORRECTED, (1, 1): F.KIND_CORRECTED,
+                     (2, 2): F.KIND_CORRECTED, (0, 2): F.KIND_RECOMPUTED,
+                     (2, 0): F.KIND_RECOMPUTED}
+    named = sorted((r["row"], r["col"], r["nbad_rows"]) for r in rep.records
+                   if r["kind"] == F.KIND_CORRECTED)
+    assert named == [(17, 90, 2), (140, 250, 4), (260, 280, 3)]
+    by_row = {r["row"]: r for r in ref.records}
+    for r in rep.records:
+        if r["kind"] == F.KIND_CORRECTED:
+            o = by_row[r["row"]]
+            assert abs(r["before"] - o["before"]) <= 1e-12 * abs(o["before"])
+            assert abs(r["after"] - o["after"]) <= 1e-12 * max(1.0, abs(o["after"]))
+
+
 def test_fault_classes():
-    """Two faults in one tile -> recomputed; a fault on an encoded checksum
+    """Two equal faults in one tile (rows and columns that cannot be paired)
+    -> recomputed; a fault on an encoded checksum
     only -> checksum-only, data untouched; a data fault plus a fault on its
     column's encoded checksum -> recomputed; an FP64 exponent flip that
     yields Inf/NaN -> rebuilt; a perturbation far below the threshold ->
@@ -145,7 +180,7 @@ def test_fault_classes():
     cand = np.argwhere((np.abs(part) >= 1) & (np.abs(part) < 2))
     ri, ci = map(int, cand[0])
     plan = [
-        F_(3, 5, 10, synth.ADD, 50.0), F_(40, 90, 200, synth.ADD, -20.0),      # tile (0,0)
+        F_(3, 5, 10, synth.ADD, 50.0), F_(40, 90, 200, synth.ADD, 50.0),       # tile (0,0)
         F_(130, 7, 0, synth.ADD, 3.0, target=synth.TGT_ROW_CHECKSUM),           # tile (1,0)
         F_(10, 200, 5, synth.ADD, 40.0),
         F_(0, 200, 5, synth.ADD, 2.0, target=synth.TGT_ROW_CHECKSUM),           # tile (0,1)

@@ -178,7 +178,8 @@ def test_lp_padded_leading_dimension_of_c(dtype):
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_lp_bitflips_and_fault_classes(dtype):
     """FP32 accumulator bit flips (exponent / high fraction bits) located
-    and rebuilt; a checksum-only fault; two faults in one tile recomputed."""
+    and rebuilt; a checksum-only fault; two equal faults in one tile (rows
+    and columns that cannot be paired) recomputed."""
     m = n = 512
     k = 1024
     A, B, Cin = synth.operands(35, 0, m, n, k, "normal")
@@ -200,7 +201,7 @@ def test_lp_bitflips_and_fault_classes(dtype):
     Fa = synth.Fault
     unit = 1.0 / (sa * sb)  # accumulator units per output unit
     plan = [Fa(128 * a0 + 3, 128 * b0 + 5, 10, synth.ADD, 5e4 * unit),
-            Fa(128 * a0 + 40, 128 * b0 + 90, 900, synth.ADD, -3e4 * unit),
+            Fa(128 * a0 + 40, 128 * b0 + 90, 900, synth.ADD, 5e4 * unit),
             Fa(128 * a1 + 7, 128 * b1 + 1, 0, synth.ADD, 1e5, target=synth.TGT_ROW_CHECKSUM)]
     got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, dtype, plan=plan, q=q)
     assert sorted(r["kind"] for r in rep.records) == sorted([F.KIND_RECOMPUTED,
@@ -255,6 +256,34 @@ def test_lp_line_corrections(dtype, ta, tb):
     kinds = {(r["tile_m"], r["tile_n"]): r["kind"] for r in rep.records}
     assert kinds == {(0, 0): F.KIND_CORRECTED, (1, 1): F.KIND_CORRECTED,
                      (2, 0): F.KIND_CORRECTED, (0, 2): F.KIND_RECOMPUTED}
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_lp_crossing_pairs(dtype):
+    """Errors in distinct rows and columns of a tile (two, four, three per
+    tile) paired by their residuals and corrected; two equal errors ->
+    recomputed.  Rebuilt elements are held to their thresholds, the rest
+    to the format's tolerance, flagged sets exactly."""
+    m, n, k = 384, 300, 200
+    A, B, Cin = synth.operands(37, 1, m, n, k, "normal")
+    q = lp_inputs(A, B, dtype)
+    tm, tn, bk = lp_tiling(dtype, m, n, k)
+    assert (tm, tn) == (128, 128)
+    u = 1.0 / (q[2] * q[3])  # accumulator units per output unit
+    Fa = synth.Fault
+    plan = [Fa(17, 90, 10, synth.ADD, 3e3 * u), Fa(60, 3, 150, synth.ADD, -4e3 * u),   # (0, 0)
+            Fa(140, 250, 5, synth.ADD, 2e3 * u), Fa(150, 130, 60, synth.ADD, 5e3 * u),  # (1, 1)
+            Fa(200, 200, 199, synth.ADD, -3e3 * u), Fa(255, 155, 99, synth.ADD, 6e3 * u),
+            Fa(260, 280, 0, synth.ADD, 2e3 * u), Fa(300, 260, 70, synth.ADD, 8e3 * u),  # (2, 2)
+            Fa(383, 299, 199, synth.ADD, -5e3 * u),
+            Fa(10, 260, 3, synth.ADD, 7e3 * u), Fa(20, 270, 30, synth.ADD, 7e3 * u)]    # (0, 2)
+    got, rep, ref = _compare(A, B, Cin, 1.0, 0.5, dtype, False, False, plan, q=q)
+    kinds = {(r["tile_m"], r["tile_n"]): r["kind"] for r in rep.records}
+    assert kinds == {(0, 0): F.KIND_CORRECTED, (1, 1): F.KIND_CORRECTED,
+                     (2, 2): F.KIND_CORRECTED, (0, 2): F.KIND_RECOMPUTED}
+    named = sorted((r["row"], r["col"], r["nbad_rows"]) for r in rep.records
+                   if r["kind"] == F.KIND_CORRECTED)
+    assert named == [(17, 90, 2), (140, 250, 4), (260, 280, 3)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)

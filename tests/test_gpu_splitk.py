@@ -113,10 +113,11 @@ def test_split_ragged_and_checksum_faults(ta, tb):
 
 
 def test_split_two_faults_one_tile():
-    """Two faults of one tile in the same slice: that slice recomputes; in
-    different slices: each slice rebuilds its own (the oracle, which does
-    not slice, recomputes the tile) -- C is the fault-free product either
-    way."""
+    """Two faults of one tile in the same slice: that slice pairs them by
+    their residuals and corrects both (two equal faults cannot be paired:
+    it recomputes); in different slices: each slice rebuilds its own (the
+    oracle, which does not slice, pairs them) -- C is the fault-free product
+    either way."""
     m, n, k = 256, 128, 8192
     A, B, Cin = synth.operands(52, 0, m, n, k, "uniform")
     tm, tn, bk, s = _tiling(m, n, k)
@@ -124,12 +125,18 @@ def test_split_two_faults_one_tile():
     Fa = synth.Fault
     same = [Fa(3, 4, 10, synth.ADD, 100.0), Fa(50, 60, 20, synth.ADD, 200.0)]
     got, rep, ref, recs, _ = _run(A, B, Cin, 1.0, 1.0, same)
+    assert [(r["row"], r["col"], r["kind"], r["nbad_rows"]) for r in recs] == \
+        [(3, 4, F.KIND_CORRECTED, 2)]
+    assert [(r["row"], r["col"], r["kind"]) for r in ref.records] == [(3, 4, F.KIND_CORRECTED)]
+    equal = [Fa(3, 4, 10, synth.ADD, 100.0), Fa(50, 60, 20, synth.ADD, 100.0)]
+    got, rep, ref, recs, _ = _run(A, B, Cin, 1.0, 1.0, equal)
     assert [r["kind"] for r in recs] == [F.KIND_RECOMPUTED]
+    assert [r["kind"] for r in ref.records] == [F.KIND_RECOMPUTED]
     apart = [Fa(3, 4, 10, synth.ADD, 100.0), Fa(50, 60, k - 5, synth.ADD, 200.0)]
     got, rep, ref, recs, _ = _run(A, B, Cin, 1.0, 1.0, apart)
     assert sorted((r["row"], r["col"], r["kind"]) for r in recs) == \
         [(3, 4, F.KIND_CORRECTED), (50, 60, F.KIND_CORRECTED)]
-    assert [r["kind"] for r in ref.records] == [F.KIND_RECOMPUTED]
+    assert [(r["row"], r["col"], r["kind"]) for r in ref.records] == [(3, 4, F.KIND_CORRECTED)]
 
 
 def test_split_plain_kernel():
