@@ -148,8 +148,11 @@ typedef struct {
  *   0  the same kernel with every checksum operation compiled out (the
  *      plain-GEMM baseline);
  *   1  row and column checksums of every tile (Section 2.2): a single
- *      error per tile, or two to four on one row or one column of it, is
- *      located and corrected (the record names the first element);
+ *      error per tile, two to four on one row or one column of it, or two
+ *      to four in distinct rows and columns (each flagged row paired with
+ *      the flagged column of equal residual), is located and corrected
+ *      (the record names the first flagged row and its element's column);
+ *      patterns that cannot be told apart are computed again;
  *   2  one-sided (BF16 / FP8 single calls only; FTGEMM_ERR_UNSUPPORTED for
  *      F64 and in batches): only the column checksum C e of each tile is
  *      kept, one entry per row, and a tile with any disagreeing row is
