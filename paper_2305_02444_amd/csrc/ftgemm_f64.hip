@@ -261,8 +261,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
     }
 
     int kind = 0, first_nr = 0, first_nc = 0, first_i = -1, first_j = -1;
-    int npairs = 0;                 // corrections left for the stored tile
-    unsigned rslot = 0xffffffffu;   // record slot (thread 0)
+    int npairs = 0;  // corrections left for the stored tile
     double rec_before = 0, rec_after = 0;
 
     d4 acc[4][2];
@@ -765,8 +764,8 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                 atomicAdd(which, 1ull);
                 atomicAdd(&ct->record_count, 1u);
                 const unsigned slot = atomicAdd(g.rec_slot, 1u);
+                sm.red[3][1] = (double)slot;  // for a paired correction's values
                 if (slot < g.record_cap) {
-                    rslot = slot;
                     // residuals: from LDS of this attempt (corrected /
                     // checksum-only) or saved from the first attempt
                     const bool again = kind == FTGEMM_KIND_RECOMPUTED ||
@@ -846,9 +845,10 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                 }
             }
             __syncthreads();
-            if (t == 0 && rslot < g.record_cap) {
-                g.records[rslot].before = sm.red[2][0];
-                g.records[rslot].after = sm.red[2][1];
+            const unsigned slot = (unsigned)sm.red[3][1];
+            if (t == 0 && slot < g.record_cap) {
+                g.records[slot].before = sm.red[2][0];
+                g.records[slot].after = sm.red[2][1];
             }
         }
     }

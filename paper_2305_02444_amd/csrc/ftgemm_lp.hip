@@ -475,7 +475,7 @@ __device__ __forceinline__ int owner_reg(int row, int col)
 // from g.row_nrm2 / g.col_nrm2 / g.row_max / g.col_max, taken before the
 // product, instead of from the staged operands.
 template <bool FP8, bool TA, bool TB, bool ABFT, int BM, bool ONE = false, bool PRE = false>
-__device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
+__device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
 {
     using E = Elem<FP8>;
     using G = Geo<BM>;
@@ -520,8 +520,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
     }
 
     int kind = 0, first_nr = 0, first_nc = 0, first_i = -1, first_j = -1;
-    int npairs = 0;                 // corrections left for the stored tile
-    unsigned rslot = 0xffffffffu;   // record slot (thread 0)
+    int npairs = 0;  // corrections left for the stored tile
     double rec_before = 0, rec_after = 0;
 
     // Checksum products of a staged step (BF16): the x-part rows times this
@@ -1171,8 +1170,8 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                 atomicAdd(which, 1ull);
                 atomicAdd(&ct->record_count, 1u);
                 const unsigned slot = atomicAdd(g.rec_slot, 1u);
+                sm.red[3][1] = (double)slot;  // for a paired correction's values
                 if (slot < g.record_cap) {
-                    rslot = slot;
                     const bool again = kind == FTGEMM_KIND_RECOMPUTED ||
                                        kind == FTGEMM_KIND_UNCORRECTABLE;
                     ftgemm_fault_record rc;
@@ -1232,9 +1231,10 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                 }
             }
             __syncthreads();
-            if (t == 0 && rslot < g.record_cap) {
-                g.records[rslot].before = sm.red[2][0];
-                g.records[rslot].after = sm.red[2][1];
+            const unsigned slot = (unsigned)sm.red[3][1];
+            if (t == 0 && slot < g.record_cap) {
+                g.records[slot].before = sm.red[2][0];
+                g.records[slot].after = sm.red[2][1];
             }
         }
     }
