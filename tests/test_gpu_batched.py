@@ -124,6 +124,58 @@ def test_small_batch_matches_oracle_and_loop(dtype):
         assert flagged(reps2[p].view().records) == flagged(views[p].records)
 
 
+@pytest.mark.parametrize("dtype", [pytest.param(F.F64, id="f64"), pytest.param(F.BF16, id="bf16")])
+def test_batch_several_errors_per_tile(dtype):
+    """The persistent kernel's tiles correct what single calls correct:
+    errors in distinct rows and columns paired by residual, errors along
+    one row, and send two equal errors to a recompute; flagged sets as the
+    oracle's, outputs bitwise equal to the loop of single launches.
+    Rebuilt low-precision elements are held to their tile's thresholds."""
+    shapes = [(200, 300, 150), (128, 128, 64), (300, 200, 257)]
+    Fa = synth.Fault
+    plan = [Fa(5, 7, 3, synth.ADD, 30.0), Fa(40, 90, 100, synth.ADD, -70.0),        # (0,0) pair
+            Fa(150, 130, 7, synth.ADD, 20.0), Fa(150, 200, 140, synth.ADD, 45.0),    # (1,1) line
+            Fa(3, 9, 0, synth.ADD, 11.0), Fa(60, 20, 30, synth.ADD, -17.0),          # three pairs
+            Fa(100, 127, 63, synth.ADD, 23.0),
+            Fa(130, 140, 5, synth.ADD, 50.0), Fa(170, 190, 200, synth.ADD, 50.0)]    # equal
+    for f, p in zip(plan, [0, 0, 0, 0, 1, 1, 1, 2, 2]):
+        f.problem = p
+    say("batch of %d, %d faults (pairs, line, equal)" % (len(shapes), len(plan)))
+    host, dev, descs = _batch(shapes, dtype, 65, alpha=1.0, beta=0.0)
+    F.set_fault_plan(plan)
+    reps = [F.ReportBuffer() for _ in shapes]
+    F.gemm_batched(descs, reps)
+    got = _outputs(dev, dtype)
+    host2, dev2, descs2 = _batch(shapes, dtype, 65, alpha=1.0, beta=0.0)
+    F.gemm_batched(descs2, [F.ReportBuffer() for _ in shapes], loop=True)
+    got2 = _outputs(dev2, dtype)
+    F.clear_fault_plan()
+    kinds = []
+    for p, (m, n, k) in enumerate(shapes):
+        assert np.array_equal(got[p], got2[p]), p
+        dA, dB, Cin = host[p]
+        ref = O.default().ftgemm(dA, dB, Cin, 1.0, 0.0, tm=128, tn=128,
+                                 bk=F.query_tiling(dtype, m, n, k)[2],
+                                 acc_bits=64 if dtype == F.F64 else 32,
+                                 injections=to_oracle([f for f in plan if f.problem == p]),
+                                 mma=lp_mma(dtype))
+        recs = reps[p].view().records
+        assert flagged(recs) == flagged(ref.records), p
+        kinds += sorted((p, r["kind"], r["nbad_rows"], r["nbad_cols"]) for r in recs)
+        mask = np.ones(got[p].shape, dtype=bool)
+        if dtype != F.F64:
+            bounds = {(r["tile_m"], r["tile_n"]): max(r["tau_row"], r["tau_col"])
+                      for r in recs if r["kind"] == F.KIND_CORRECTED}
+            for i, j in np.argwhere(ref.raw != ref.C):
+                bound = bounds.get((i // 128, j // 128))
+                if bound is not None:
+                    assert abs(got[p][i, j] - ref.C[i, j]) <= bound
+                    mask[i, j] = False
+        assert normwise(got[p][mask], ref.C[mask]) <= TOL[dtype], p
+    assert kinds == [(0, F.KIND_CORRECTED, 1, 2), (0, F.KIND_CORRECTED, 2, 2),
+                     (1, F.KIND_CORRECTED, 3, 3), (2, F.KIND_RECOMPUTED, 2, 2)]
+
+
 def test_graph_replay_new_data_and_beta():
     """Same shapes twice (the captured graph and the tuned schedule are
     reused) with different data; then beta != 0 (no tuning: C is read)."""

@@ -24,9 +24,11 @@ T = 128
 Fa = synth.Fault
 
 
-def gpu_unfused(A, B, Cin, alpha, beta, ta=False, tb=False, plan=()):
+def gpu_unfused(A, B, Cin, alpha, beta, ta=False, tb=False, plan=(), ldc_pad=0):
     import torch
-    dA, dB, dC = F.to_device(A), F.to_device(B), F.to_device(Cin)
+    m = Cin.shape[0]
+    dA, dB = F.to_device(A), F.to_device(B)
+    dC = F.to_device(Cin, ld=m + ldc_pad if ldc_pad else None)
     F.set_fault_plan(plan)
     rb = F.ReportBuffer()
     F.gemm_ex(F.make_desc(dA, dB, dC, alpha, beta, ta, tb, abft=3), report=rb)
@@ -93,6 +95,31 @@ def test_unfused_fault_free_bits():
     assert np.array_equal(got, plain)
     assert not rep.records and rep.tiles_verified == 8 * 6
     assert 0 < rep.max_ratio < 1
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 3, 5), (129, 127, 17), (64, 200, 1)])
+def test_unfused_small_shapes(m, n, k):
+    """Shapes below and just above one tile, beta != 0, with C's leading
+    dimension padded: no tile flagged, the output that of the call without
+    checksums, and one fault in the last tile detected."""
+    A, B, Cin = synth.operands(73, m + n + k, m, n, k, "uniform")
+    got, rep = gpu_unfused(A, B, Cin, 0.75, -1.5, ldc_pad=5)
+    plain, _ = gpu_f64(A, B, Cin, 0.75, -1.5, abft=False, ldc_pad=5)
+    assert np.array_equal(got, plain)
+    assert not rep.records and rep.tiles_verified == (-(-m // T)) * (-(-n // T))
+    plan = [Fa(m - 1, n - 1, k - 1, synth.ADD, 1e3)]
+    got, rep, ref = _compare(A, B, Cin, 0.75, -1.5, False, False, plan)
+    assert rep.detected == 1 and rep.records[0]["row"] == m - 1 and rep.records[0]["col"] == n - 1
+
+
+def test_unfused_beta_zero_ignores_c():
+    """beta = 0 never reads C: NaN in C does not reach the output or the
+    checksums."""
+    m, n, k = 300, 260, 140
+    A, B, _ = synth.operands(74, 0, m, n, k, "normal", False, True)
+    Cnan = np.asfortranarray(np.full((m, n), np.nan))
+    got, rep, ref = _compare(A, B, Cnan, 1.25, 0.0, False, True, [])
+    assert np.all(np.isfinite(got)) and not rep.records
 
 
 def test_unfused_rejects_low_precision():
