@@ -432,6 +432,16 @@ def main():
     rb = F.ReportBuffer()
     F.gemm(dA, dB, dC, 1.0, 1.0, report=rb)
     inj = rb.view()
+    # two faults in each of 64 other tiles, in different rows and columns
+    # (corrected by pairing the flagged rows and columns)
+    plan2 = synth.crossing_pairs_plan(synth.rng(20, m + 1, synth.STREAM_PLAN), m, n, k, 128, 128,
+                                      -(-tiles // 64), synth.log_magnitude(sigma))
+    F.set_fault_plan(plan2)
+    t_pairs, _ = timed(torch, call(True), args.steps, args.warmup)
+    rb = F.ReportBuffer()
+    F.gemm(dA, dB, dC, 1.0, 1.0, report=rb)
+    inj2 = rb.view()
+    F.set_fault_plan(plan)
     # the unfused ablation (separate checksum passes around the plain
     # GEMM, detection only) under the same faults, then error-free
     rb = F.ReportBuffer()
@@ -474,6 +484,13 @@ def main():
                      "tflops": round(flops / (t_inj * 1e-3) / 1e12, 3),
                      "overhead_pct": round(100.0 * (t_inj / t_plain - 1.0), 2),
                      "corrected": int(inj.corrected), "detected": int(inj.detected)},
+        "injected_two_per_tile": {"faults_per_call": len(plan2),
+                                  "tiles": len(plan2) // 2,
+                                  "tflops": round(flops / (t_pairs * 1e-3) / 1e12, 3),
+                                  "overhead_pct": round(100.0 * (t_pairs / t_plain - 1.0), 2),
+                                  "corrected": int(inj2.corrected),
+                                  "recomputed": int(inj2.recomputed),
+                                  "detected": int(inj2.detected)},
         "error_free_check": {"detected": int(clean.detected), "max_ratio": clean.max_ratio,
                              "tiles_verified": int(clean.tiles_verified)},
         "unfused": {"tflops": round(flops / (t_uf * 1e-3) / 1e12, 3),

@@ -128,6 +128,30 @@ def additive_plan(g, m, n, k, tm, tn, count, magnitude):
     return plan
 
 
+def crossing_pairs_plan(g, m, n, k, tm, tn, count, magnitude):
+    """Two faults in each of count distinct tiles, in different rows and
+    different columns of the tile (tiles with a single row or column are
+    skipped); magnitude(g) draws each delta, redrawn until the two differ
+    by more than 1 in 1000."""
+    tm_ = -(-m // tm)
+    tn_ = -(-n // tn)
+    plan = []
+    for (ti, tj) in tiles_without_replacement(g, tm_, tn_, count):
+        h, w = min(tm, m - ti * tm), min(tn, n - tj * tn)
+        if h < 2 or w < 2:
+            continue
+        rows = g.choice(h, size=2, replace=False)
+        cols = g.choice(w, size=2, replace=False)
+        d1 = float(magnitude(g))
+        d2 = float(magnitude(g))
+        while abs(d1 - d2) <= 1e-3 * max(abs(d1), abs(d2)):
+            d2 = float(magnitude(g))
+        for r, c, d in ((rows[0], cols[0], d1), (rows[1], cols[1], d2)):
+            plan.append(Fault(ti * tm + int(r), tj * tn + int(c), int(g.integers(0, max(k, 1))),
+                              ADD, d))
+    return plan
+
+
 def log_magnitude(sigma: float, lo_exp: float = 0.0, hi_exp: float = 6.0):
     """Random-sign delta of size 10^U(lo, hi) * sigma."""
     def draw(g):
