@@ -58,6 +58,12 @@ struct GemmArgs {
     // the rows of op(A) (m each) and the columns of op(B) (n each), over
     // the whole inner dimension, computed before the product
     const double *row_nrm2, *row_max, *col_nrm2, *col_max;
+    // with the norms above (low precision): the operand checksums of every
+    // tile, taken in the same pass -- xsum[tile_m * ldxs + p] = sum over the
+    // tile's rows i of op(A)(i, p), ysum[tile_n * ldxs + p] = sum over the
+    // tile's columns j of op(B)(p, j), FP32 (null: formed in the tiles)
+    const float *xsum, *ysum;
+    int64_t ldxs;
 };
 
 // Slice checksum workspace: for slice s and tile t (tile_m + tile_n *

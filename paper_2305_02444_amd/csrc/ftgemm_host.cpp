@@ -527,10 +527,16 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
                      (d.abft == 2 || (d.abft == 1 && (int64_t)g.tiles_m * g.tiles_n >=
                                                          ftg::kLargeTileMin));
     if (pre) {
-        // line norms of op(A) (rows) and op(B) (columns) for the thresholds
+        // line norms of op(A) (rows) and op(B) (columns) for the thresholds,
+        // and in the same pass the operand checksums of every tile: of op(A)
+        // over each tile's rows, of op(B) over each tile's columns (FP32,
+        // tiles_m + tiles_n rows of k; the one-sided mode needs op(B)'s only)
         const bool fp8 = d.dtype == FTGEMM_FP8_E4M3;
         const int64_t part = std::max<int64_t>(int64_t(1) << 22, 2 * std::max(d.m, d.n));
-        if (ftgemm_status st = split_space(*ws, sizeof(double) * (2 * (d.m + d.n) + part)))
+        const int64_t nx = d.abft == 2 ? 0 : (int64_t)g.tiles_m * d.k;
+        const int64_t nsum = nx + (int64_t)g.tiles_n * d.k;
+        if (ftgemm_status st = split_space(
+                *ws, sizeof(double) * (2 * (d.m + d.n) + part) + sizeof(float) * nsum))
             return st;
         double *nb = ws->split;
         g.row_nrm2 = nb;
@@ -538,12 +544,18 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
         g.col_nrm2 = nb + 2 * d.m;
         g.col_max = nb + 2 * d.m + d.n;
         double *pw = nb + 2 * (d.m + d.n);
+        float *xs = (float *)(pw + part);
+        g.xsum = nx ? xs : nullptr;
+        g.ysum = xs + nx;
+        g.ldxs = d.k;
         // op(A) row i is stored row i (N) or stored column i (T); op(B)
         // column j is stored column j (N) or stored row j (T)
         HIP_TRY(ftg::launch_line_norms(d.A, d.lda, ta ? d.k : d.m, ta ? d.m : d.k, fp8, !ta,
-                                       nb, nb + d.m, pw, part, stream));
+                                       nb, nb + d.m, pw, part, nx ? xs : nullptr, tm, d.k,
+                                       stream));
         HIP_TRY(ftg::launch_line_norms(d.B, d.ldb, tb ? d.n : d.k, tb ? d.k : d.n, fp8, tb,
-                                       nb + 2 * d.m, nb + 2 * d.m + d.n, pw, part, stream));
+                                       nb + 2 * d.m, nb + 2 * d.m + d.n, pw, part, xs + nx, tn,
+                                       d.k, stream));
     }
     int64_t slice_k = d.k;
     const int nslices =

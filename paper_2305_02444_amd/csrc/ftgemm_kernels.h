@@ -27,10 +27,17 @@ void tiling_lp(bool fp8, int mode, int64_t m, int64_t n, bool batched, int *tm, 
 // Squared norms and largest magnitudes of the lines of a column-major R x Cn
 // matrix of BF16 / E4M3 codes: of each row (along_rows; R results) or of
 // each column (Cn results).  Row sums use part (at least 2 R doubles; more
-// lets the columns be split into more chunks).
+// lets the columns be split into more chunks).  seg (may be null) receives,
+// in the same pass, FP32 sums over segments of seg_len lines across the
+// other index: along_rows, of each column over seg_len consecutive rows at
+// seg[(row / seg_len) * seg_ld + column]; otherwise of each row over
+// seg_len consecutive columns at seg[(column / seg_len) * seg_ld + row].
+// seg_len: a power-of-two multiple of 16 bytes of elements, at most 64 of
+// them; seg_ld at least Cn (along_rows) or R.
 hipError_t launch_line_norms(const void *X, int64_t ld, int64_t R, int64_t Cn, bool fp8,
                              bool along_rows, double *nrm2, double *amax, double *part,
-                             int64_t part_cap, hipStream_t stream);
+                             int64_t part_cap, float *seg, int seg_len, int64_t seg_ld,
+                             hipStream_t stream);
 
 // Unfused FP64 fault tolerance (detection only).  Segment sums of a
 // column-major R x Cn matrix of doubles over L consecutive rows (down; one

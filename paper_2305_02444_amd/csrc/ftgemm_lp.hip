@@ -485,6 +485,8 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
     constexpr bool kPre = ABFT && (ONE || PRE);
     // the checksum products of step s run during step s + 1
     constexpr bool kLag = kMma && ABFT;
+    // kPre: the operand checksums x_p, y_p come from g.xsum, g.ysum (taken
+    // with the norms before the product) instead of the staged registers
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w % G::WM, wn = w / G::WM;
     const int q = lane >> 4, c16 = lane & 15;
@@ -507,6 +509,15 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         const int64_t k0 = (int64_t)s * E::BK;
         la.load(i0, k0, m, k);
         lb.load(j0, k0, n, k);
+    };
+    // kPre: this step's x_p, y_p at p = s BK + t (threads t < BK; zero past k)
+    float px = 0.0f, py = 0.0f;
+    auto load_sums = [&](int s) {
+        if (t < E::BK) {
+            const int64_t p = (int64_t)s * E::BK + t;
+            py = p < k ? g.ysum[(int64_t)tile_n * g.ldxs + p] : 0.0f;
+            if (!kOne) px = p < k ? g.xsum[(int64_t)tile_m * g.ldxs + p] : 0.0f;
+        }
     };
 
     int nf = 0;
@@ -575,9 +586,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         }
 
         load(0);
-        if (ABFT) {
-            if (!kOne) la.template sum_to<kMma && !kPre>(sm.xs[0], nrm_a);
-            lb.template sum_to<kMma && !kPre>(sm.ys[0], nrm_b);
+        if (ABFT && kPre) {
+            load_sums(0);
+        } else if (ABFT) {
+            if (!kOne) la.template sum_to<kMma>(sm.xs[0], nrm_a);
+            lb.template sum_to<kMma>(sm.ys[0], nrm_b);
         }
         int s = 0;
 #pragma unroll 1
@@ -599,11 +612,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                     // extra rows, for the checksum products of step s (run
                     // during step s + 1, after its barrier)
                     if (t < E::BK) {
-                        const float yp = gather_lp<LB::kParts>(sm.ys[stg], t);
+                        const float yp = kPre ? py : gather_lp<LB::kParts>(sm.ys[stg], t);
                         vy = fmaf(yp, yp, vy);
                         put_parts(sm.u.st[stg].B, TN, t, yp);
                         if (!kOne) {
-                            const float xp = gather_lp<LA::kParts>(sm.xs[stg], t);
+                            const float xp = kPre ? px : gather_lp<LA::kParts>(sm.xs[stg], t);
                             vx = fmaf(xp, xp, vx);
                             put_parts(sm.u.st[stg].A, BM, t, xp);
                         }
@@ -613,11 +626,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                     // thread per p), then the encoded checksums and norms of
                     // step s, before the registers take step s + 1
                     if (t < E::BK) {
-                        const float yp = gather_lp<LB::kParts>(sm.ys[stg], t);
+                        const float yp = kPre ? py : gather_lp<LB::kParts>(sm.ys[stg], t);
                         vy = fmaf(yp, yp, vy);
                         sm.yc[t] = yp;
                         if (!kOne) {
-                            const float xp = gather_lp<LA::kParts>(sm.xs[stg], t);
+                            const float xp = kPre ? px : gather_lp<LA::kParts>(sm.xs[stg], t);
                             vx = fmaf(xp, xp, vx);
                             sm.xc[t] = xp;
                         }
@@ -632,7 +645,10 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                         lb.template encode<!kPre>(xv, enc_b, nrm_b, amx_b);
                     }
                 }
-                if (s + 1 < nsteps) load(s + 1);
+                if (s + 1 < nsteps) {
+                    load(s + 1);
+                    if (ABFT && kPre) load_sums(s + 1);
+                }
 #pragma unroll
                 for (int kk = 0; kk < E::NKK; ++kk) {
                     if (!FP8) {
@@ -694,10 +710,10 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                                     fa[mi], fb[ni], acc[mi][ni], 0, 0, 0, 127, 0, 127);
                     }
                 }
-                if (ABFT && s + 1 < nsteps) {
+                if (ABFT && !kPre && s + 1 < nsteps) {
                     // operand checksums of step s + 1, published before its barrier
-                    if (!kOne) la.template sum_to<kMma && !kPre>(sm.xs[stg ^ 1], nrm_a);
-                    lb.template sum_to<kMma && !kPre>(sm.ys[stg ^ 1], nrm_b);
+                    if (!kOne) la.template sum_to<kMma>(sm.xs[stg ^ 1], nrm_a);
+                    lb.template sum_to<kMma>(sm.ys[stg ^ 1], nrm_b);
                 }
             }
             if (ABFT && faults_on) {
@@ -1328,6 +1344,10 @@ hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode, bo
                      hipStream_t stream)
 {
     if (mode < 0 || mode > 2 || (mode == 2 && !pre)) return hipErrorInvalidValue;
+    // the kernels that take their norms from g also take the operand
+    // checksums from it (op(A)'s only in two-sided mode)
+    if (pre && mode != 0 && (!g.ysum || (mode == 1 && !g.xsum) || g.ldxs < g.k))
+        return hipErrorInvalidValue;
     if (tm == 256)
         return fp8 ? lp::launch<true, 256>(g, ta, tb, mode, pre, stream)
                    : lp::launch<false, 256>(g, ta, tb, mode, pre, stream);
