@@ -170,8 +170,10 @@ typedef struct {
  *      are not applied.  Its workspace ((m + n) k / 128 + 8 m n / 128
  *      doubles, plus the thin GEMMs' split slices) is grown on demand and
  *      kept.
- * BF16 / FP8 single calls with abft 1 or 2 take the threshold norms of the
- * rows of op(A) and columns of op(B) in one pass over A and B before the
+ * BF16 / FP8 single calls with abft 2, and with abft 1 when the output
+ * holds at least 256 tiles, take the threshold norms of the rows of op(A)
+ * and columns of op(B), and the FP32 operand checksums of every tile
+ * ((tiles_m + tiles_n) k floats), in one pass over A and B before the
  * product, using the library's workspace (batches compute them in the
  * tiles).  Other values of abft are rejected (argument position 14). */
 typedef struct {
