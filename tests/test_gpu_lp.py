@@ -231,6 +231,32 @@ def test_lp_256_row_tiles(ta, tb):
     assert rep.tiles_verified == 16 * 16
 
 
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+def test_lp_fp8_two_sided_from_the_norms_pass(ta, tb):
+    """Two-sided FP8 on 128 x 128 tiles with at least 256 of them, so the
+    threshold norms and both operand checksums come from the pass over A
+    and B before the product: ragged in every dimension (k not a multiple
+    of the step), every transpose (each operand's checksums then come from
+    the other of the pass's two kernels), faults in the last row and
+    column tiles and the interior, checked against the oracle on the whole
+    output."""
+    dtype = F.FP8_E4M3
+    m, n, k = 3999, 2001, 301
+    tm, tn, bk = lp_tiling(dtype, m, n, k)
+    assert (tm, tn) == (128, 128)
+    A, B, Cin = synth.operands(32, 1, m, n, k, "normal", ta, tb)
+    q = lp_inputs(A, B, dtype)
+    unit = 1.0 / (q[2] * q[3])  # accumulator units per output unit
+    Fa = synth.Fault
+    plan = [Fa(m - 1, n - 1, k - 1, synth.ADD, 2e3 * unit),      # corner tile, last step
+            Fa(3968 + 20, 70, 200, synth.ADD, -5e3 * unit),      # last row tile
+            Fa(127, 1920 + 7, 0, synth.ADD, 1e4 * unit),         # last column tile, first step
+            Fa(1000, 1000, 150, synth.ADD, 3e3 * unit)]          # interior
+    got, rep, ref = _compare(A, B, Cin, 0.9, -1.1, dtype, ta, tb, plan, q=q)
+    assert rep.corrected == 4 == rep.detected
+    assert rep.tiles_verified == 32 * 16
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, True)])
 def test_lp_line_corrections(dtype, ta, tb):
