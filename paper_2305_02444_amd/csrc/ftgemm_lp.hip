@@ -606,6 +606,18 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                 const int stg = s & 1;  // stage and checksum buffers of step s
                 la.store(sm.u.st[stg].A);
                 lb.store(sm.u.st[stg].B);
+                if (ABFT && kPre && !kMma && t < E::BK) {
+                    // x_p, y_p of step s (taken before the product) are
+                    // staged with the tiles, so the step's one barrier
+                    // publishes them too: flat in this stage's partial
+                    // buffers, which the sums from registers would use
+                    vy = fmaf(py, py, vy);
+                    (&sm.ys[stg][0][0])[t] = py;
+                    if (!kOne) {
+                        vx = fmaf(px, px, vx);
+                        (&sm.xs[stg][0][0])[t] = px;
+                    }
+                }
                 __syncthreads();
                 if (ABFT && kMma) {
                     // x_p, y_p of step s are complete: their parts go to the
@@ -623,25 +635,30 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                     }
                 } else if (ABFT) {
                     // x_p, y_p of step s are complete: combined once (one
-                    // thread per p), then the encoded checksums and norms of
+                    // thread per p; already staged when taken before the
+                    // product), then the encoded checksums and norms of
                     // step s, before the registers take step s + 1
-                    if (t < E::BK) {
-                        const float yp = kPre ? py : gather_lp<LB::kParts>(sm.ys[stg], t);
-                        vy = fmaf(yp, yp, vy);
-                        sm.yc[t] = yp;
-                        if (!kOne) {
-                            const float xp = kPre ? px : gather_lp<LA::kParts>(sm.xs[stg], t);
-                            vx = fmaf(xp, xp, vx);
-                            sm.xc[t] = xp;
+                    const float *ycs = kPre ? &sm.ys[stg][0][0] : sm.yc;
+                    const float *xcs = kPre ? &sm.xs[stg][0][0] : sm.xc;
+                    if (!kPre) {
+                        if (t < E::BK) {
+                            const float yp = gather_lp<LB::kParts>(sm.ys[stg], t);
+                            vy = fmaf(yp, yp, vy);
+                            sm.yc[t] = yp;
+                            if (!kOne) {
+                                const float xp = gather_lp<LA::kParts>(sm.xs[stg], t);
+                                vx = fmaf(xp, xp, vx);
+                                sm.xc[t] = xp;
+                            }
                         }
+                        __syncthreads();
                     }
-                    __syncthreads();
 #pragma unroll
-                    for (int e = 0; e < LA::kNP; ++e) yv[e] = sm.yc[la.p0() + e];
+                    for (int e = 0; e < LA::kNP; ++e) yv[e] = ycs[la.p0() + e];
                     la.template encode<!kPre>(yv, enc_a, nrm_a, amx_a);
                     if (!kOne) {
 #pragma unroll
-                        for (int e = 0; e < LB::kNP; ++e) xv[e] = sm.xc[lb.p0() + e];
+                        for (int e = 0; e < LB::kNP; ++e) xv[e] = xcs[lb.p0() + e];
                         lb.template encode<!kPre>(xv, enc_b, nrm_b, amx_b);
                     }
                 }
