@@ -393,10 +393,43 @@ struct LpLoader {
     // this thread's inner values) and squared norms over this step.
     // (FP8: amx tracks the largest magnitude for the truncation term.)
     // (kNrm false: the encoded checksum only.)
-    template <bool kNrm = true>
+    // (kPk, FP8 without norms: packed conversions, below; the one-sided
+    // tiles use them -- in the two-sided FP8 tile they measured slower)
+    template <bool kNrm = true, bool kPk = false>
     __device__ __forceinline__ void encode(const float (&v)[kNP], float (&enc)[kOuter],
                                            float (&nrm)[kOuter], float &amx) const
     {
+        static_assert(!(kPk && kNrm), "packed conversions take no norms");
+        if (FP8 && kPk) {
+            // two E4M3 codes of one 16-bit half per conversion: inner pairs
+            // (e, e + 1) of a chunk, or outer pairs (r, r + 1) of a raw
+            // column; each enc[r] still takes its terms in ascending e
+            if (kInner) {
+#pragma unroll
+                for (int r = 0; r < kOuter; ++r)
+#pragma unroll
+                    for (int e = 0; e < kNP; e += 2) {
+                        const int d = w[r][e >> 2];
+                        const auto a = (e & 2) ? __builtin_amdgcn_cvt_pk_f32_fp8(d, true)
+                                               : __builtin_amdgcn_cvt_pk_f32_fp8(d, false);
+                        enc[r] = fmaf(a[0], v[e], enc[r]);
+                        enc[r] = fmaf(a[1], v[e + 1], enc[r]);
+                    }
+            } else {
+#pragma unroll
+                for (int e = 0; e < kNP; ++e)
+#pragma unroll
+                    for (int r = 0; r < kOuter; r += 2) {
+                        const int g = r >> 3, o = r & 7;
+                        const int d = col_dw(g, e, o >> 2);
+                        const auto a = (o & 2) ? __builtin_amdgcn_cvt_pk_f32_fp8(d, true)
+                                               : __builtin_amdgcn_cvt_pk_f32_fp8(d, false);
+                        enc[r] = fmaf(a[0], v[e], enc[r]);
+                        enc[r + 1] = fmaf(a[1], v[e], enc[r + 1]);
+                    }
+            }
+            return;
+        }
 #pragma unroll
         for (int r = 0; r < kOuter; ++r)
 #pragma unroll
@@ -655,7 +688,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                     }
 #pragma unroll
                     for (int e = 0; e < LA::kNP; ++e) yv[e] = ycs[la.p0() + e];
-                    la.template encode<!kPre>(yv, enc_a, nrm_a, amx_a);
+                    la.template encode<!kPre, kOne>(yv, enc_a, nrm_a, amx_a);
                     if (!kOne) {
 #pragma unroll
                         for (int e = 0; e < LB::kNP; ++e) xv[e] = xcs[lb.p0() + e];
