@@ -5,6 +5,7 @@ test_oracle_mutants.py) and raises AssertionError when the pin fails.
 """
 import numpy as np
 
+from golden_io import read_threshold_example
 from oracle import oracle as O
 from paper_2305_02444_amd import synth
 
@@ -379,8 +380,140 @@ def pin_ragged_and_subset(orc):
     assert len(r.records) == 1
 
 
+def pin_threshold_worked_example(orc):
+    """The threshold of every checksum entry of a 4 x 4 tile equals the
+    value worked out by hand in tests/golden/threshold_example.txt, for FP64
+    and FP32 accumulation and for a multiplier that truncates its products
+    (each term of the bound has its own factor there, so dropping or
+    mis-scaling any one of them changes the values)."""
+    d = read_threshold_example()
+    kw = dict(Cin=d["Cin"], alpha=d["alpha"], beta=d["beta"], tm=4, tn=4, bk=2,
+              lam=d["lambda"])
+    for acc_bits, u in ((64, 2.0 ** -53), (32, 2.0 ** -24)):
+        tr, tc = orc.tile_thresholds(d["A"], d["B"], 0, 0, acc_bits=acc_bits, **kw)
+        assert np.allclose(tr, d["tau_row_u"] * u, rtol=1e-15, atol=0), (acc_bits, tr / u)
+        assert np.allclose(tc, d["tau_col_u"] * u, rtol=1e-15, atol=0), (acc_bits, tc / u)
+    g = 2.0 ** d["mma_grid_log2"]
+    tr, tc = orc.tile_thresholds(d["A"], d["B"], 0, 0, acc_bits=32,
+                                 mma=(g, int(d["mma_group"])), **kw)
+    u = 2.0 ** -24
+    assert np.allclose(tr, d["tau_row_u"] * u + d["tau_row_mma_64ths"] / 64.0, rtol=1e-15,
+                       atol=0)
+    assert np.allclose(tc, d["tau_col_u"] * u + d["tau_col_mma_64ths"] / 64.0, rtol=1e-15,
+                       atol=0)
+
+
+def _bf16(x):
+    """Round to the nearest bfloat16 (ties to even), returned as float64:
+    products of two such values are exact in FP32."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _fp32_tile_residuals(A, B, Cin, alpha, beta):
+    """Residuals R - P of one tile computed the way an FP32-accumulating
+    kernel forms them, written out here independently of the oracle: the
+    product accumulated step by step in FP32, the operand checksums x and y
+    summed in FP32, the encoded products x.B and A.y accumulated in FP32,
+    the beta part and the reference sums in FP64."""
+    h, k = A.shape
+    w = B.shape[1]
+    A32, B32 = A.astype(np.float32), B.astype(np.float32)
+    acc = np.zeros((h, w), np.float32)
+    for p in range(k):
+        acc = (acc + np.outer(A32[:, p], B32[p, :])).astype(np.float32)
+    out = (np.float32(alpha) * acc + np.float32(beta) * Cin.astype(np.float32))
+    out = out.astype(np.float32).astype(np.float64)
+    x = np.zeros(k, np.float32)
+    y = np.zeros(k, np.float32)
+    for i in range(h):
+        x = (x + A32[i, :]).astype(np.float32)
+    for j in range(w):
+        y = (y + B32[:, j]).astype(np.float32)
+    Pr = np.zeros(w, np.float32)
+    Pc = np.zeros(h, np.float32)
+    for p in range(k):
+        Pr = (Pr + x[p] * B32[p, :]).astype(np.float32)
+        Pc = (Pc + A32[:, p] * y[p]).astype(np.float32)
+    dr = out.sum(axis=0) - (alpha * Pr.astype(np.float64) + beta * Cin.sum(axis=0))
+    dc = out.sum(axis=1) - (alpha * Pc.astype(np.float64) + beta * Cin.sum(axis=1))
+    return dr, dc
+
+
+def pin_threshold_sound_and_tight(orc):
+    """The threshold bounds real rounding and is not absurdly loose.  The
+    test forms each tile's residuals with its own FP32 accumulation (and the
+    FP64 ones with numpy's matmul, a different summation order from the
+    oracle's); over several seeds and inner dimensions the largest |d|/tau
+    must lie in [1e-4, 1).  Same-sign data (partial sums that only grow)
+    push the FP32 residual to about 5% of tau at every k, so a threshold
+    missing its sqrt(k) growth or using the FP64 unit roundoff for FP32
+    accumulation fails; mean-zero data keep it near 1e-3, so a threshold
+    a hundred times too large fails too."""
+    h = w = 32
+    for dist in ("normal", "positive"):
+        for k in (256, 4096):
+            worst = 0.0
+            for seed in range(3):
+                g = np.random.default_rng([97, seed, k])
+                if dist == "normal":
+                    A = _bf16(g.standard_normal((h, k)))
+                    B = _bf16(g.standard_normal((k, w)))
+                else:
+                    A = _bf16(g.uniform(0.0, 1.0, (h, k)))
+                    B = _bf16(g.uniform(0.0, 1.0, (k, w)))
+                Cin = _bf16(g.standard_normal((h, w)))
+                A, B, Cin = (np.asfortranarray(v) for v in (A, B, Cin))
+                dr, dc = _fp32_tile_residuals(A, B, Cin, 1.0, 1.0)
+                tr, tc = orc.tile_thresholds(A, B, 0, 0, Cin, 1.0, 1.0, tm=h, tn=w, bk=16,
+                                             acc_bits=32)
+                worst = max(worst, np.max(np.abs(dr) / tr), np.max(np.abs(dc) / tc))
+            assert 1e-4 <= worst < 1.0, ("fp32", dist, k, worst)
+    # FP64 accumulation: numpy's matmul (blocked, FMA) against the oracle's
+    # thresholds; the residuals are pure rounding and stay far inside tau
+    for seed in range(3):
+        A, B, Cin = synth.operands(97, seed, 48, 40, 2048, "uniform")
+        C = A @ B + Cin
+        x, y = A.sum(axis=0), B.sum(axis=1)
+        dr = C.sum(axis=0) - (x @ B + Cin.sum(axis=0))
+        dc = C.sum(axis=1) - (A @ y + Cin.sum(axis=1))
+        tr, tc = orc.tile_thresholds(A, B, 0, 0, Cin, 1.0, 1.0, tm=48, tn=40, bk=16)
+        worst = max(np.max(np.abs(dr) / tr), np.max(np.abs(dc) / tc))
+        assert 1e-5 <= worst < 1.0, ("fp64", seed, worst)
+
+
+def pin_gemm_entries_vs_numpy(orc):
+    """Single entries of the plain GEMM (used to check large runs on
+    sampled outputs) equal numpy's matmul, for every transpose, with padded
+    leading dimensions, beta = 0 with NaN in C_in, and a prefix of k."""
+    g = np.random.default_rng(17)
+    m, n, k = 41, 35, 57
+    for ta in (False, True):
+        for tb in (False, True):
+            sa = (k, m) if ta else (m, k)
+            sb = (n, k) if tb else (k, n)
+            A = np.asfortranarray(g.uniform(-1, 1, (sa[0] + 3, sa[1])))[:sa[0]]
+            B = np.asfortranarray(g.uniform(-1, 1, (sb[0] + 2, sb[1])))[:sb[0]]
+            Cin = np.asfortranarray(g.uniform(-1, 1, (m + 4, n)))[:m]
+            rows = g.integers(0, m, 50)
+            cols = g.integers(0, n, 50)
+            oa, ob = _ops(A, B, ta, tb)
+            got = orc.gemm_entries(A, B, rows, cols, Cin, -1.5, 0.25, ta, tb)
+            ref = (-1.5 * (oa @ ob) + 0.25 * Cin)[rows, cols]
+            assert np.max(np.abs(got - ref)) < 1e-13, (ta, tb)
+            nanC = np.full((m, n), np.nan, order="F")
+            got = orc.gemm_entries(A, B, rows, cols, nanC, 2.0, 0.0, ta, tb)
+            assert np.max(np.abs(got - 2.0 * (oa @ ob)[rows, cols])) < 1e-13
+            got = orc.gemm_entries(A, B, rows, cols, None, 1.0, 0.0, ta, tb, k=20)
+            ref = (oa[:, :20] @ ob[:20, :])[rows, cols]
+            assert np.max(np.abs(got - ref)) < 1e-13
+
+
 ALL_PINS = [pin_gemm_vs_numpy, pin_gemm_integer_exact, pin_blas_special_cases,
             pin_checksum_identities, pin_brute_force_location, pin_exact_recovery,
             pin_nonfinite_recovery, pin_classification, pin_line_correction,
             pin_crossing_pairs, pin_one_sided,
-            pin_no_false_positives, pin_ragged_and_subset]
+            pin_no_false_positives, pin_ragged_and_subset, pin_threshold_sound_and_tight,
+            pin_threshold_worked_example, pin_gemm_entries_vs_numpy]

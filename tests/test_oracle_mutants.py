@@ -31,6 +31,22 @@ MUTANTS = {
     "wrong_row_index_in_column_sum": (
         "s += out[ii + jj * h];\n            Rc[ii] = s;",
         "s += out[jj + ii * h];\n            Rc[ii] = s;"),
+    "threshold_drops_sqrt_k": (
+        "double sk = sqrt((double)k);", "double sk = 1.0;"),
+    "threshold_drops_sqrt_h": (
+        "double sh = sqrt((double)h);", "double sh = 1.0;"),
+    "threshold_unit_roundoffs_swapped": (
+        "const double u = (P->acc_bits == 32) ? ldexp(1.0, -24) : ldexp(1.0, -53);",
+        "const double u = (P->acc_bits == 32) ? ldexp(1.0, -53) : ldexp(1.0, -24);"),
+    "threshold_drops_beta_term": (
+        " + 2.0 * u * fabs(beta) * nrm_cin);", ");"),
+    "threshold_lambda_a_tenth": (
+        "return lambda * (fabs(alpha)", "return 0.1 * lambda * (fabs(alpha)"),
+    "threshold_drops_truncation_term": (
+        "P->lambda * fabs(alpha) * trunc * sqrt((double)h) * ma * nb[jj];", "0.0;"),
+    "entries_read_cin_transposed": (
+        "out[t] = (beta == 0.0) ? alpha * s : alpha * s + beta * Cin[i + j * ldc];",
+        "out[t] = (beta == 0.0) ? alpha * s : alpha * s + beta * Cin[j + i * ldc];"),
     "threshold_zero": (
         "return lambda * (fabs(alpha)", "return 0.0 * (fabs(alpha)"),
     "fault_one_step_late": (
