@@ -648,12 +648,25 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
             }
         } else if (nbad_r + nbad_c == 1) {
             /* A single encoded checksum entry disagrees while every sum on
-             * the other side matches: the fault hit the checksum path and
-             * the data is left as it is.  (Several entries on one side with
-             * none on the other cannot come from one checksum fault: such a
-             * tile is computed again below.) */
-            if (rec) rec->kind = KIND_CHECKSUM_ONLY;
-            break;
+             * the other side matches.  A data error of size D shows as D on
+             * both sides, each up to its own rounding, so it can hide on the
+             * other side only if |D| <= 2 tau there, which puts the flagged
+             * residual within its own tau plus twice the largest tau of the
+             * other side.  Beyond that bound the fault hit the checksum path
+             * and the data is left as it is; within it the tile is computed
+             * again.  (Several entries on one side with none on the other
+             * cannot come from one checksum fault: such a tile is computed
+             * again below.) */
+            const int by_col = (nbad_c == 1);
+            const double d = by_col ? Rr[jbad] - Pr[jbad] : Rc[ibad] - Pc[ibad];
+            double other = 0.0;
+            for (int64_t x = 0; x < (by_col ? h : w); ++x)
+                other = fmax(other, by_col ? tc[x] : tr[x]);
+            const double bound = (by_col ? tr[jbad] : tc[ibad]) + 2.0 * other;
+            if (!(fabs(d) <= bound)) {
+                if (rec) rec->kind = KIND_CHECKSUM_ONLY;
+                break;
+            }
         }
         /* Several faults, or a correction that does not verify: compute the
          * tile again (the planned faults are not repeated). */

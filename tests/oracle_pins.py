@@ -268,8 +268,10 @@ def pin_crossing_pairs(orc):
     with the column of equal residual, each crossing loses that residual,
     and the output equals the fault-free product bit for bit.  Errors that
     cannot be paired one to one -> recomputed: two equal errors, three
-    errors on the corners of a rectangle, a data error beside a fault on
-    each checksum, five errors."""
+    errors of distinct sizes on the corners of a rectangle, a data error
+    beside a fault on each checksum, five errors.  Three on a rectangle's
+    corners with the two off the shared corner equal cannot be told from a
+    pair, and are corrected as one (the stated limit)."""
     g = synth.rng(94, 0, 0)
     m, n, k = 32, 32, 24
     A = np.asfortranarray(g.integers(-8, 9, (m, k)).astype(float))
@@ -295,6 +297,20 @@ def pin_crossing_pairs(orc):
     d = [d for d in r.records if d["row"] == 4][0]
     assert d["before"] == Cff[4, 11] - 120.0 and d["after"] == Cff[4, 11]
     assert d["d_row"] == d["d_col"] == -120.0
+    # The limit of one row and one column checksum per tile: three errors
+    # on the corners of a rectangle, the two off the shared corner equal,
+    # leave the same residuals as two errors in distinct rows and columns
+    # (rows 2 and 7: 65 and 40; columns 3 and 12: 65 and 40).  The reading
+    # with fewer errors is taken: the pair is corrected, which leaves four
+    # wrong elements whose row and column sums all agree.  The record's
+    # counts (two rows, two columns) tell a paired correction from a single
+    # one.
+    r = run([Inj(2, 3, 1, O.ADD, 25.0), Inj(2, 12, 9, O.ADD, 40.0), Inj(7, 3, 9, O.ADD, 40.0)])
+    assert [(d["kind"], d["row"], d["col"], d["nbad_rows"], d["nbad_cols"])
+            for d in r.records] == [(O.CORRECTED, 2, 3, 2, 2)]
+    diff = r.C - Cff
+    assert sorted(map(tuple, np.argwhere(diff != 0).tolist())) == [(2, 3), (2, 12), (7, 3), (7, 12)]
+    assert not diff.sum(axis=0).any() and not diff.sum(axis=1).any()
     for plan in ([Inj(2, 3, 1, O.ADD, 25.0), Inj(7, 12, 9, O.ADD, 25.0)],
                  [Inj(2, 3, 1, O.ADD, 25.0), Inj(2, 12, 9, O.ADD, 40.0),
                   Inj(7, 3, 9, O.ADD, 55.0)],
@@ -304,6 +320,51 @@ def pin_crossing_pairs(orc):
         r = run(plan)
         assert [d["kind"] for d in r.records] == [O.RECOMPUTED], plan
         assert np.array_equal(r.C, Cff)
+
+
+def pin_single_flag_rule(orc):
+    """A lone disagreeing checksum entry is taken for a checksum fault only
+    when a data error could not have hidden on the other side.  On integer
+    data (fault-free residuals exactly zero) with FP32 thresholds, whose two
+    sides differ by the operands' norms: a data error larger than its
+    column's threshold but within its row's flags one side only; brute
+    force shows the output really changed, and the tile is computed again
+    (the output equals the fault-free product bit for bit).  A checksum
+    fault beyond the entry's threshold plus twice the other side's largest
+    is classified checksum-only with the output untouched; a smaller one,
+    indistinguishable from a hidden data error, is computed again."""
+    g = synth.rng(95, 0, 0)
+    m = n = 16
+    k = 64
+    # rows of A and columns of B with norms spread over two orders of size
+    A = g.integers(-8, 9, (m, k)).astype(float) * np.repeat([1.0, 4.0, 16.0, 64.0], 4)[:, None]
+    B = g.integers(-8, 9, (k, n)).astype(float) * np.repeat([1.0, 4.0, 16.0, 64.0], 4)[None, :]
+    A, B = np.asfortranarray(A), np.asfortranarray(B)
+    Cin = np.asfortranarray(g.integers(-8, 9, (m, n)).astype(float))
+    Cff = A @ B + Cin
+    kw = dict(Cin=Cin, alpha=1.0, beta=1.0, tm=16, tn=16, bk=16, acc_bits=32)
+    tr, tc = orc.tile_thresholds(A, B, 0, 0, **kw)
+    Inj = O.Injection
+    # column 0 has the smallest row-checksum threshold, row 15 the largest
+    # column-checksum threshold
+    j, i = int(np.argmin(tr)), int(np.argmax(tc))
+    assert tc[i] > 4.0 * tr[j]
+    delta = 0.5 * (tr[j] + tc[i])          # above tr[j], below tc[i]
+    r = orc.ftgemm(A, B, injections=[Inj(i, j, 5, O.ADD, delta)], **kw)
+    assert np.argwhere(r.raw != Cff).tolist() == [[i, j]]
+    assert [(d["kind"], d["nbad_rows"], d["nbad_cols"], d["col"]) for d in r.records] == \
+        [(O.RECOMPUTED, 0, 1, j)]
+    assert np.array_equal(r.C, Cff)
+    bound_c = tr[j] + 2.0 * tc.max()
+    bound_r = tc[i] + 2.0 * tr.max()
+    for target, size, bound, kind in (
+            (O.TGT_ROW_CHECKSUM, 1.5 * bound_c, bound_c, O.CHECKSUM_ONLY),
+            (O.TGT_ROW_CHECKSUM, 0.5 * (tr[j] + bound_c), bound_c, O.RECOMPUTED),
+            (O.TGT_COL_CHECKSUM, 1.5 * bound_r, bound_r, O.CHECKSUM_ONLY),
+            (O.TGT_COL_CHECKSUM, 0.5 * (tc[i] + bound_r), bound_r, O.RECOMPUTED)):
+        r = orc.ftgemm(A, B, injections=[Inj(i, j, 5, O.ADD, size, target=target)], **kw)
+        assert [d["kind"] for d in r.records] == [kind], (target, size, bound)
+        assert np.array_equal(r.raw, Cff) and np.array_equal(r.C, Cff)
 
 
 def pin_one_sided(orc):
@@ -516,4 +577,5 @@ ALL_PINS = [pin_gemm_vs_numpy, pin_gemm_integer_exact, pin_blas_special_cases,
             pin_nonfinite_recovery, pin_classification, pin_line_correction,
             pin_crossing_pairs, pin_one_sided,
             pin_no_false_positives, pin_ragged_and_subset, pin_threshold_sound_and_tight,
-            pin_threshold_worked_example, pin_gemm_entries_vs_numpy]
+            pin_threshold_worked_example, pin_gemm_entries_vs_numpy,
+            pin_single_flag_rule]

@@ -47,6 +47,12 @@ MUTANTS = {
     "entries_read_cin_transposed": (
         "out[t] = (beta == 0.0) ? alpha * s : alpha * s + beta * Cin[i + j * ldc];",
         "out[t] = (beta == 0.0) ? alpha * s : alpha * s + beta * Cin[j + i * ldc];"),
+    "single_flag_always_checksum_only": (
+        "const double bound = (by_col ? tr[jbad] : tc[ibad]) + 2.0 * other;",
+        "const double bound = -1.0;"),
+    "single_flag_bound_ignores_other_side": (
+        "const double bound = (by_col ? tr[jbad] : tc[ibad]) + 2.0 * other;",
+        "const double bound = (by_col ? tr[jbad] : tc[ibad]);"),
     "threshold_zero": (
         "return lambda * (fabs(alpha)", "return 0.0 * (fabs(alpha)"),
     "fault_one_step_late": (
