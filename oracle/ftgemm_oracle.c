@@ -205,6 +205,9 @@ typedef struct {
     int32_t mma_group;         /* instruction's group sums (see threshold)  */
     int32_t one_sided;         /* 1: only the column checksum (one entry    */
                                /* per row), recompute on any disagreement   */
+    int32_t pad;
+    int64_t slice_k;           /* 0, or the inner length of each slice of a */
+                               /* split inner dimension (see ft_tile_split) */
 } oracle_params;
 
 /* Flip one bit of an accumulator held at the given precision. */
@@ -430,9 +433,16 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
                    const double *Cin, double *Cout, int64_t ldo, double *Craw,
                    int64_t tile_m, int64_t tile_n,
                    const oracle_injection *inj, int64_t ninj,
-                   oracle_echo *echo, oracle_record *rec, double *max_ratio)
+                   oracle_echo *echo, oracle_record *rec, double *max_ratio,
+                   int local, double *pub, double *pub_tau)
 {
+    /* local: Cout and Craw hold only this tile (leading dimension ldo).
+     * pub / pub_tau (may be NULL): the tile's final encoded checksums and
+     * their thresholds, row checksums (one per column) first, then the
+     * column checksums (one per row); an entry found to be a checksum fault
+     * is replaced by the reference sum of the verified output. */
     const int64_t i0 = tile_m * P->tm, j0 = tile_n * P->tn;
+    const int64_t oi = local ? 0 : i0, oj = local ? 0 : j0;
     const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 : P->tm;
     const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;
     const double alpha = P->alpha, beta = P->beta;
@@ -481,7 +491,7 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
         if (Craw && attempt_faults)
             for (int64_t jj = 0; jj < w; ++jj)
                 for (int64_t ii = 0; ii < h; ++ii)
-                    Craw[(i0 + ii) + (j0 + jj) * ldo] = out[ii + jj * h];
+                    Craw[(oi + ii) + (oj + jj) * ldo] = out[ii + jj * h];
 
         /* Reference checksums: sums of the computed output. */
         for (int64_t jj = 0; jj < w; ++jj) {
@@ -665,6 +675,7 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
             const double bound = (by_col ? tr[jbad] : tc[ibad]) + 2.0 * other;
             if (!(fabs(d) <= bound)) {
                 if (rec) rec->kind = KIND_CHECKSUM_ONLY;
+                if (by_col) Pr[jbad] = Rr[jbad]; else Pc[ibad] = Rc[ibad];
                 break;
             }
         }
@@ -676,7 +687,12 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
 
     for (int64_t jj = 0; jj < w; ++jj)
         for (int64_t ii = 0; ii < h; ++ii)
-            Cout[(i0 + ii) + (j0 + jj) * ldo] = out[ii + jj * h];
+            Cout[(oi + ii) + (oj + jj) * ldo] = out[ii + jj * h];
+    if (pub)
+        for (int64_t x = 0; x < w + h; ++x) {
+            pub[x] = x < w ? Pr[x] : Pc[x - w];
+            pub_tau[x] = x < w ? tr[x] : tc[x - w];
+        }
 
     free(acc); free(out); free(Pr); free(Pc); free(Rr); free(Rc); free(tr); free(tc);
     return produced;
@@ -714,6 +730,175 @@ void oracle_tile_checksums(const oracle_params *P, const double *A, const double
     free(tr); free(tc); free(acc);
 }
 
+/* One output tile of a split inner dimension (the parts of Section 2.3
+ * taken along k).  The inner range is cut into slices of slice_k indices
+ * (the last one shorter); each slice's partial product
+ * W_s = op(A)(I, K_s) op(B)(K_s, J) is computed, verified and corrected as a
+ * tile of its own (alpha 1, beta 0) with the faults whose k_index lies in it
+ * (checksum faults past the end go to the last slice).  Checksums are
+ * linear, so the encoded checksums of the result are alpha times the sum of
+ * the slices' (each slice's checksum-fault entry replaced by its verified
+ * reference sum) plus beta times the sums of C_in; the result
+ * out = alpha sum_s W_s + beta C_in is verified against them, with the
+ * slices' thresholds times |alpha| plus lambda u ((S + 3) sum|out| +
+ * 2 |beta| ||C_in||) for the rounding of the reduction itself (S terms,
+ * alpha, the beta term, the reference sum), and classified as a single tile
+ * is; a reduction that does not verify is formed again from the slices.
+ * Returns the number of records (slices first, in order, then the
+ * reduction); at most rec_room are written. */
+static int ft_tile_split(const oracle_params *P, const double *A, const double *B,
+                         const double *Cin, double *Cout, int64_t ldo, double *Craw,
+                         int64_t tile_m, int64_t tile_n,
+                         const oracle_injection *inj, int64_t ninj, oracle_echo *echo,
+                         oracle_record *recs, int rec_room, double *max_ratio)
+{
+    const int64_t i0 = tile_m * P->tm, j0 = tile_n * P->tn;
+    const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 : P->tm;
+    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;
+    const int64_t S = (P->k + P->slice_k - 1) / P->slice_k;
+    const double alpha = P->alpha, beta = P->beta;
+    const double u = ldexp(1.0, -53);
+    double *W = calloc((size_t)(h * w), sizeof(double));      /* sum of the slices */
+    double *Wraw = calloc((size_t)(h * w), sizeof(double));
+    double *Ws = malloc(sizeof(double) * h * w), *Wr = malloc(sizeof(double) * h * w);
+    double *pub = malloc(sizeof(double) * (w + h)), *ptau = malloc(sizeof(double) * (w + h));
+    double *Psum = calloc((size_t)(w + h), sizeof(double));
+    double *Tsum = calloc((size_t)(w + h), sizeof(double));
+    oracle_injection *li = malloc(sizeof(oracle_injection) * (ninj > 0 ? ninj : 1));
+    oracle_echo *le = malloc(sizeof(oracle_echo) * (ninj > 0 ? ninj : 1));
+    int64_t *map = malloc(sizeof(int64_t) * (ninj > 0 ? ninj : 1));
+    int nrec = 0;
+
+    for (int64_t s = 0; s < S; ++s) {
+        const int64_t kb = s * P->slice_k;
+        const int64_t len = (P->k - kb < P->slice_k) ? P->k - kb : P->slice_k;
+        oracle_params Ps = *P;
+        Ps.k = len;
+        Ps.alpha = 1.0;
+        Ps.beta = 0.0;
+        Ps.slice_k = 0;
+        const double *As = P->ta ? A + kb : A + kb * P->lda;
+        const double *Bs = P->tb ? B + kb * P->ldb : B + kb;
+        int64_t nl = 0;
+        for (int64_t q = 0; inj && q < ninj; ++q) {
+            const oracle_injection *f = &inj[q];
+            const int in = f->k_index >= kb &&
+                           (f->k_index < kb + len || (f->target != TGT_ACC && s == S - 1));
+            if (!in) continue;
+            li[nl] = *f;
+            li[nl].k_index = f->k_index - kb;
+            le[nl].applied = 0;
+            map[nl++] = q;
+        }
+        oracle_record r;
+        memset(&r, 0, sizeof r);
+        double mr = 0.0;
+        const int got = ft_tile(&Ps, As, Bs, Cin, Ws, h, Wr, tile_m, tile_n, li, nl, le,
+                                &r, &mr, 1, pub, ptau);
+        if (mr > *max_ratio) *max_ratio = mr;
+        for (int64_t q = 0; echo && q < nl; ++q)
+            if (le[q].applied) {
+                echo[map[q]].applied = 1;
+                echo[map[q]].before = le[q].before;
+                echo[map[q]].after = le[q].after;
+            }
+        if (got) {
+            if (nrec < rec_room) recs[nrec] = r;
+            ++nrec;
+        }
+        for (int64_t t = 0; t < h * w; ++t) { W[t] += Ws[t]; Wraw[t] += Wr[t]; }
+        for (int64_t x = 0; x < w + h; ++x) { Psum[x] += pub[x]; Tsum[x] += ptau[x]; }
+    }
+
+    /* The verified reduction. */
+    double *out = malloc(sizeof(double) * h * w);
+    for (int64_t jj = 0; jj < w; ++jj)
+        for (int64_t ii = 0; ii < h; ++ii) {
+            const double c = Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+            double v = alpha * W[ii + jj * h], vr = alpha * Wraw[ii + jj * h];
+            if (beta != 0.0) { v = v + beta * c; vr = vr + beta * c; }
+            out[ii + jj * h] = v;
+            if (Craw) Craw[(i0 + ii) + (j0 + jj) * ldo] = vr;
+        }
+    double *Pe = malloc(sizeof(double) * (w + h)), *Re = malloc(sizeof(double) * (w + h));
+    double *Te = malloc(sizeof(double) * (w + h)), *De = malloc(sizeof(double) * (w + h));
+    for (int64_t x = 0; x < w + h; ++x) {
+        const int col = x < w;           /* row checksum of a column */
+        const int64_t e = col ? x : x - w, len = col ? h : w;
+        double R = 0.0, a = 0.0, cs = 0.0, c2 = 0.0;
+        for (int64_t y = 0; y < len; ++y) {
+            const int64_t ii = col ? y : e, jj = col ? e : y;
+            const double v = out[ii + jj * h];
+            R += v;
+            a += fabs(v);
+            if (beta != 0.0) {
+                const double c = Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+                cs += c;
+                c2 += c * c;
+            }
+        }
+        double Pv = alpha * Psum[x];
+        if (beta != 0.0) Pv += beta * cs;
+        Pe[x] = Pv;
+        Re[x] = R;
+        Te[x] = fabs(alpha) * Tsum[x] +
+                P->lambda * u * ((double)(S + 3) * a + 2.0 * fabs(beta) * sqrt(c2));
+        De[x] = R - Pv;
+    }
+    int64_t nbad_c = 0, nbad_r = 0, jbad = -1, ibad = -1;
+    for (int64_t x = 0; x < w + h; ++x)
+        if (!(fabs(De[x]) <= Te[x])) {
+            if (x < w) { if (nbad_c++ == 0) jbad = x; }
+            else if (nbad_r++ == 0) ibad = x - w;
+        }
+    if (nbad_c || nbad_r) {
+        oracle_record r;
+        memset(&r, 0, sizeof r);
+        r.tile_m = tile_m; r.tile_n = tile_n;
+        r.row = ibad >= 0 ? i0 + ibad : -1;
+        r.col = jbad >= 0 ? j0 + jbad : -1;
+        r.nbad_rows = (int32_t)nbad_r; r.nbad_cols = (int32_t)nbad_c;
+        r.d_row = jbad >= 0 ? De[jbad] : 0.0;
+        r.tau_row = jbad >= 0 ? Te[jbad] : 0.0;
+        r.d_col = ibad >= 0 ? De[w + ibad] : 0.0;
+        r.tau_col = ibad >= 0 ? Te[w + ibad] : 0.0;
+        /* Formed again from the same slices the sums come out the same:
+         * whatever does not verify here stays uncorrectable. */
+        r.kind = KIND_UNCORRECTABLE;
+        if (nbad_r == 1 && nbad_c == 1) {
+            double sr = 0.0, sc = 0.0;
+            for (int64_t ii = 0; ii < h; ++ii)
+                if (ii != ibad) sc += out[ii + jbad * h];
+            for (int64_t jj = 0; jj < w; ++jj)
+                if (jj != jbad) sr += out[ibad + jj * h];
+            const double fixed = Pe[jbad] - sc;
+            if (fabs(sr + fixed - Pe[w + ibad]) <= Te[w + ibad]) {
+                r.kind = KIND_CORRECTED;
+                r.before = out[ibad + jbad * h];
+                r.after = fixed;
+                out[ibad + jbad * h] = fixed;
+            }
+        } else if (nbad_r + nbad_c == 1) {
+            const int by_col = (nbad_c == 1);
+            const double d = by_col ? De[jbad] : De[w + ibad];
+            double other = 0.0;
+            for (int64_t x = 0; x < (by_col ? h : w); ++x)
+                other = fmax(other, by_col ? Te[w + x] : Te[x]);
+            if (!(fabs(d) <= (by_col ? Te[jbad] : Te[w + ibad]) + 2.0 * other))
+                r.kind = KIND_CHECKSUM_ONLY;
+        }
+        if (nrec < rec_room) recs[nrec] = r;
+        ++nrec;
+    }
+    for (int64_t jj = 0; jj < w; ++jj)
+        for (int64_t ii = 0; ii < h; ++ii)
+            Cout[(i0 + ii) + (j0 + jj) * ldo] = out[ii + jj * h];
+
+    free(W); free(Wraw); free(Ws); free(Wr); free(pub); free(ptau); free(Psum); free(Tsum);
+    free(li); free(le); free(map); free(out); free(Pe); free(Re); free(Te); free(De);
+    return nrec;
+}
+
 /* Fault-tolerant GEMM over the tile grid.  tiles: list of tile indices
  * (tile_m + tile_n * tiles_m) to process, or NULL for all tiles.  Records of
  * detected faults go to rec (at most rec_cap are stored; the return value is
@@ -740,22 +925,27 @@ int64_t oracle_ftgemm(const oracle_params *P, const double *A, const double *B,
             echo[q].k_index = inj[q].k_index; echo[q].applied = 0;
             echo[q].before = echo[q].after = 0.0;
         }
+    const int split = P->slice_k > 0 && P->slice_k < P->k;
+    const int room = split ? (int)((P->k + P->slice_k - 1) / P->slice_k) + 1 : 1;
 #pragma omp parallel for schedule(dynamic, 1) reduction(max : mr)
     for (int64_t t = 0; t < total; ++t) {
         int64_t id = tiles ? tiles[t] : t;
-        oracle_record r;
-        memset(&r, 0, sizeof r);
+        oracle_record *r = calloc((size_t)room, sizeof(oracle_record));
         double local = 0.0;
-        int got = ft_tile(P, A, B, Cin, Cout, ldo, Craw, id % tiles_m, id / tiles_m,
-                          inj, ninj, echo, &r, &local);
+        int got = split
+            ? ft_tile_split(P, A, B, Cin, Cout, ldo, Craw, id % tiles_m, id / tiles_m,
+                            inj, ninj, echo, r, room, &local)
+            : ft_tile(P, A, B, Cin, Cout, ldo, Craw, id % tiles_m, id / tiles_m,
+                      inj, ninj, echo, r, &local, 0, NULL, NULL);
         if (local > mr) mr = local;
-        if (got) {
+        for (int g = 0; g < got && g < room; ++g) {
             int64_t slot;
 #pragma omp atomic capture
             slot = nrec++;
             if (rec && slot < rec_cap)
-                rec[slot] = r;
+                rec[slot] = r[g];
         }
+        free(r);
     }
     if (max_ratio)
         *max_ratio = mr;

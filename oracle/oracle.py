@@ -70,7 +70,8 @@ class _Params(C.Structure):
                 ("alpha", C.c_double), ("beta", C.c_double), ("tm", C.c_int64),
                 ("tn", C.c_int64), ("bk", C.c_int64), ("acc_bits", C.c_int32),
                 ("correct", C.c_int32), ("lam", C.c_double), ("mma_grid", C.c_double),
-                ("mma_group", C.c_int32), ("one_sided", C.c_int32)]
+                ("mma_group", C.c_int32), ("one_sided", C.c_int32), ("pad", C.c_int32),
+                ("slice_k", C.c_int64)]
 
 
 @dataclass
@@ -188,25 +189,30 @@ class Oracle:
 
     # -- fault-tolerant GEMM ----------------------------------------------
     def _params(self, A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, correct, lam,
-                mma=(0.0, 1), one_sided=False):
+                mma=(0.0, 1), one_sided=False, slice_k=0):
         m, n, k = _dims(A, B, ta, tb)
         return _Params(int(ta), int(tb), m, n, k, max(1, A.shape[0]), max(1, B.shape[0]),
                        max(1, Cin.shape[0]), alpha, beta, tm, tn, bk, acc_bits,
-                       int(correct), lam, float(mma[0]), int(mma[1]), int(bool(one_sided)))
+                       int(correct), lam, float(mma[0]), int(mma[1]), int(bool(one_sided)), 0,
+                       int(slice_k))
 
     def ftgemm(self, A, B, Cin=None, alpha=1.0, beta=0.0, ta=False, tb=False, tm=128,
                tn=128, bk=16, acc_bits=64, injections=(), tiles=None, correct=True,
-               lam=DEFAULT_LAMBDA, mma=(0.0, 1), one_sided=False):
+               lam=DEFAULT_LAMBDA, mma=(0.0, 1), one_sided=False, slice_k=0):
         """Fault-tolerant GEMM, tile by tile (Sections 2.2 and 2.3).  mma:
         (grid, group) of a multiplier that truncates its in-instruction
         sums, which widens the thresholds; (0, 1) for exact sums.
         one_sided: only the column checksum (one entry per row) is kept, and
-        a tile with any disagreeing row is computed again."""
+        a tile with any disagreeing row is computed again.
+        slice_k: 0, or the length of the slices of a split inner dimension;
+        each slice is verified as a tile of its own and the reduction of the
+        slices is verified against their summed checksums (records: one per
+        slice that found something, then one for the reduction)."""
         A, B = _f64(A), _f64(B)
         m, n, k = _dims(A, B, ta, tb)
         Cin = np.zeros((max(m, 1), max(n, 1)), order="F") if Cin is None else _f64(Cin)
         P = self._params(A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, correct, lam,
-                         mma, one_sided)
+                         mma, one_sided, slice_k)
         out = np.full((m, n), np.nan, order="F")
         raw = np.full((m, n), np.nan, order="F")
         inj = list(injections)
@@ -221,7 +227,8 @@ class Oracle:
             tl_arr = np.ascontiguousarray(tiles, dtype=np.int64)
             tl, nt = tl_arr.ctypes.data_as(C.POINTER(C.c_int64)), tl_arr.size
         ntiles = (-(-m // tm)) * (-(-n // tn)) if m > 0 and n > 0 else 0
-        cap = max(ntiles if tiles is None else nt, 1)
+        per_tile = (-(-k // slice_k) + 1) if 0 < slice_k < k else 1
+        cap = max(ntiles if tiles is None else nt, 1) * per_tile
         recs = (_Rec * cap)()
         mr = C.c_double(0.0)
         nrec = self.L.oracle_ftgemm(C.byref(P), _dptr(A), _dptr(B), _dptr(Cin), _dptr(out),

@@ -367,6 +367,52 @@ def pin_single_flag_rule(orc):
         assert np.array_equal(r.raw, Cff) and np.array_equal(r.C, Cff)
 
 
+def pin_split_inner_dimension(orc):
+    """A split inner dimension: slices of slice_k indices, each verified as a
+    tile of its own, then the verified reduction.  On integer data every
+    partial sum is exact, so: the split result equals the fault-free
+    product bit for bit with no record; two faults of one tile in different
+    slices are each located by brute force on the slice partials (the raw
+    output differs from the product exactly there) and rebuilt by their
+    slice (two CORRECTED records, output exact); a checksum fault in a slice
+    is classified checksum-only there and its entry replaced by the
+    verified sum, so the reduction agrees (no reduction record); faults
+    planned past the end of the inner dimension: an accumulator fault is
+    not applied, a checksum fault goes to the last slice."""
+    g = synth.rng(96, 0, 0)
+    m, n, k = 40, 36, 70
+    A = np.asfortranarray(g.integers(-8, 9, (k, m)).astype(float))   # op(A) = A^T
+    B = np.asfortranarray(g.integers(-8, 9, (k, n)).astype(float))
+    Cin = np.asfortranarray(g.integers(-8, 9, (m, n)).astype(float))
+    Cff = 2.0 * (A.T @ B) - 1.0 * Cin
+    Inj = O.Injection
+    kw = dict(ta=True, tm=16, tn=16, bk=8, slice_k=24)    # slices of 24, 24, 22
+    r = orc.ftgemm(A, B, Cin, 2.0, -1.0, **kw)
+    assert np.array_equal(r.C, Cff) and not r.records
+    # unsplit on random data: the same product within rounding
+    Ar, Br, Cr = synth.operands(96, 1, 50, 45, 100, "normal")
+    a = orc.ftgemm(Ar, Br, Cr, 1.0, 1.0, tm=16, tn=16, bk=8, slice_k=32)
+    b = orc.ftgemm(Ar, Br, Cr, 1.0, 1.0, tm=16, tn=16, bk=8)
+    assert np.max(np.abs(a.C - b.C)) < 1e-12 * np.max(np.abs(b.C)) and not a.records
+    # two faults in tile (0, 0): k 5 (slice 0) and 50 (slice 2)
+    r = orc.ftgemm(A, B, Cin, 2.0, -1.0, injections=[
+        Inj(3, 4, 5, O.ADD, 100.0), Inj(9, 12, 50, O.ADD, -30.0)], **kw)
+    assert np.argwhere(r.raw != Cff).tolist() == [[3, 4], [9, 12]]
+    assert [(d["kind"], d["row"], d["col"], d["tile_m"], d["tile_n"]) for d in r.records] == \
+        [(O.CORRECTED, 3, 4, 0, 0), (O.CORRECTED, 9, 12, 0, 0)]
+    assert np.array_equal(r.C, Cff)
+    assert [d["before"] - d["after"] for d in r.records] == [100.0, -30.0]  # slice partials
+    # a row-checksum fault in slice 1 of tile (1, 1), and faults past the end
+    r = orc.ftgemm(A, B, Cin, 2.0, -1.0, injections=[
+        Inj(20, 21, 30, O.ADD, 500.0, target=O.TGT_ROW_CHECKSUM),
+        Inj(33, 2, k + 5, O.ADD, 77.0),
+        Inj(35, 30, k + 5, O.ADD, 900.0, target=O.TGT_COL_CHECKSUM)], **kw)
+    assert np.array_equal(r.C, Cff)
+    assert [(d["kind"], d["row"], d["col"]) for d in r.records] == \
+        [(O.CHECKSUM_ONLY, -1, 21), (O.CHECKSUM_ONLY, 35, -1)]
+    assert [e["applied"] for e in r.echo] == [True, False, True]
+
+
 def pin_one_sided(orc):
     """One-sided mode (only the column checksum, one entry per row;
     recompute on any disagreement).  On integer data: each accumulator fault
@@ -578,4 +624,4 @@ ALL_PINS = [pin_gemm_vs_numpy, pin_gemm_integer_exact, pin_blas_special_cases,
             pin_crossing_pairs, pin_one_sided,
             pin_no_false_positives, pin_ragged_and_subset, pin_threshold_sound_and_tight,
             pin_threshold_worked_example, pin_gemm_entries_vs_numpy,
-            pin_single_flag_rule]
+            pin_single_flag_rule, pin_split_inner_dimension]

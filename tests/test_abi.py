@@ -160,3 +160,60 @@ def test_status_strings():
     L = F.lib()
     for s in range(5):
         assert L.ftgemm_status_string(s).startswith(b"FTGEMM")
+
+
+def test_operand_windows_wider_than_the_loaders_reach_are_refused():
+    """A step of an operand is read through one buffer window of at most
+    2^31 - 1 bytes with 32-bit offsets.  A leading dimension that makes the
+    window wider would read zeros or wrapped addresses with no sign (the
+    checksums are summed from the same staged values), so it is refused on
+    the host with the operand's position; the largest leading dimension
+    that fits is accepted (checked up to the argument checks: the call then
+    stops at the quick return alpha = 0, beta = 1)."""
+    L = F.lib()
+    lim = 2 ** 31 - 1
+
+    def desc(dtype, ta, tb, m, n, k, lda, ldb):
+        d = F.GemmDesc()
+        d.dtype, d.transA, d.transB = dtype, ta, tb
+        d.m, d.n, d.k, d.lda, d.ldb, d.ldc = m, n, k, lda, ldb, m
+        d.alpha, d.beta, d.scaleA, d.scaleB, d.A, d.B, d.C = 1.0, 0.0, 1.0, 1.0, 1, 1, 1
+        return d
+
+    # FP64, A not transposed: its rows run along the stored rows, so a step
+    # spans 32 stored columns: 31 ld + 128 elements of 8 bytes
+    ok = (lim // 8 - 128) // 31
+    d = desc(F.F64, 0, 0, 512, 512, 512, ok + 1, 512)
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 8
+    # A transposed: a step spans the tile's 128 rows of op(A), as stored columns
+    ok_t = (lim // 8 - 32) // 127
+    d = desc(F.F64, 1, 0, 512, 512, 512, ok_t + 1, 512)
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 8
+    # B not transposed (inner index along the stored rows): 128 stored columns
+    d = desc(F.F64, 0, 0, 512, 512, 512, 512, ok_t + 1)
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 10
+    # BF16 and FP8 tiles reach 256 outer indices
+    ok_bf = (lim // 2 - 64) // 255
+    d = desc(F.BF16, 1, 0, 512, 512, 512, ok_bf + 1, 512)
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 8
+    d = desc(F.FP8_E4M3, 0, 1, 512, 512, 512, 512, (lim - 256) // 127 + 1)
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 10
+    # the same in a batch
+    d = desc(F.F64, 1, 0, 512, 512, 512, ok_t + 1, 512)
+    assert L.ftgemm_gemm_batched(1, C.byref(d), None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 8
+    # one stored column longer than the window: the dimension's position
+    d = desc(F.F64, 1, 0, 64, 64, lim // 8 + 1, lim // 8 + 1, lim // 8 + 1)
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 5
+    # the largest leading dimensions that fit pass the checks
+    for d in (desc(F.F64, 0, 0, 512, 512, 512, ok, 512),
+              desc(F.F64, 1, 1, 512, 512, 512, ok_t, ok),
+              desc(F.BF16, 1, 0, 512, 512, 512, ok_bf, 512)):
+        d.alpha, d.beta = 0.0, 1.0
+        assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.OK

@@ -53,6 +53,12 @@ MUTANTS = {
     "single_flag_bound_ignores_other_side": (
         "const double bound = (by_col ? tr[jbad] : tc[ibad]) + 2.0 * other;",
         "const double bound = (by_col ? tr[jbad] : tc[ibad]);"),
+    "split_checksum_fault_entry_not_replaced": (
+        "if (by_col) Pr[jbad] = Rr[jbad]; else Pc[ibad] = Rc[ibad];", ""),
+    "split_fault_lands_in_the_next_slice": (
+        "const int in = f->k_index >= kb &&", "const int in = f->k_index >= kb + 8 &&"),
+    "split_reduction_drops_beta": (
+        "if (beta != 0.0) { v = v + beta * c; vr = vr + beta * c; }", ""),
     "threshold_zero": (
         "return lambda * (fabs(alpha)", "return 0.0 * (fabs(alpha)"),
     "fault_one_step_late": (
