@@ -55,11 +55,16 @@ def read_traffic(name, files):
         return None
 
 
-def timed(torch, fn, steps, warmup):
-    """Average per-call time (ms) over `steps` calls, from HIP events on
-    the launch stream; returns (ms_per_call_total, ms_per_call_events)."""
+def timed(torch, fn, steps, warmup, reset=None):
+    """Average per-call time (ms) over `steps` calls, from HIP events on the
+    launch stream around each call.  reset (optional) runs before every
+    call, outside the events: it restores C from a pristine copy, since
+    with beta != 0 C is read and written.  Returns (ms_per_call, ms_total /
+    steps), the second including the resets."""
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
+        if reset:
+            reset()
         fn()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -69,6 +74,8 @@ def timed(torch, fn, steps, warmup):
     torch.cuda.synchronize()
     start.record(stream)
     for s in range(steps):
+        if reset:
+            reset()
         ev[s][0].record(stream)
         fn()
         ev[s][1].record(stream)
@@ -76,33 +83,44 @@ def timed(torch, fn, steps, warmup):
     torch.cuda.synchronize()
     total = start.elapsed_time(end) / steps
     per = sum(a.elapsed_time(b) for a, b in ev) / steps
-    return total, per
+    return per, total
 
 
-def cpu_baseline(A, B, Cin, m, n, k, budget_s=12.0):
-    """The oracle (untuned) on the host cores, on a bounded sample of tiles
-    of the same problem; rate in useful TFLOP/s (2 * tile flops / time)."""
+def cpu_baseline(A, B, Cin, m, n, k, budget_s=(8.0, 6.0)):
+    """The oracle (untuned) on the host cores, built there with -O3
+    -march=native -fopenmp, on a bounded sample of tiles of the same
+    problem, with all cores and with one; rate in useful TFLOP/s
+    (2 * tile flops / time)."""
     import numpy as np
     from oracle import oracle as O
-    orc = O.default()
+    orc = O.native()
     tiles_m = -(-m // 128)
     ntiles = tiles_m * (-(-n // 128))
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
     g = np.random.default_rng(1234)
-    cal = min(ntiles, max(cores, 4))
-    t0 = time.perf_counter()
-    orc.ftgemm(A, B, Cin, 1.0, 1.0, tiles=g.choice(ntiles, cal, replace=False))
-    per_tile = (time.perf_counter() - t0) / cal
-    count = int(min(ntiles, max(cal, budget_s / max(per_tile, 1e-6))))
-    tiles = g.choice(ntiles, count, replace=False)
-    t0 = time.perf_counter()
-    orc.ftgemm(A, B, Cin, 1.0, 1.0, tiles=tiles)
-    dt = time.perf_counter() - t0
-    flops = 2.0 * 128 * 128 * k * count
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of %d 128x128 output tiles of the %dx%dx%d FP64 fault-tolerant "
-                      "GEMM (encode, multiply, verify per tile), %.1f s" % (count, ntiles, m,
-                                                                           n, k, dt)}
+
+    def rate(threads, budget):
+        orc.set_threads(threads)
+        cal = min(ntiles, max(threads, 2))
+        t0 = time.perf_counter()
+        orc.ftgemm(A, B, Cin, 1.0, 1.0, tiles=g.choice(ntiles, cal, replace=False))
+        per_tile = (time.perf_counter() - t0) / cal
+        count = int(min(ntiles, max(cal, budget / max(per_tile, 1e-6))))
+        tiles = g.choice(ntiles, count, replace=False)
+        t0 = time.perf_counter()
+        orc.ftgemm(A, B, Cin, 1.0, 1.0, tiles=tiles)
+        dt = time.perf_counter() - t0
+        return 2.0 * 128 * 128 * k * count / dt / 1e12, count, dt
+
+    v_all, c_all, dt_all = rate(cores, budget_s[0])
+    v_one, c_one, dt_one = rate(1, budget_s[1])
+    orc.set_threads(cores)
+    return {"value": v_all, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "value_1_thread": v_one,
+            "build": "gcc -O3 -march=native -fopenmp on the host timed",
+            "sample": "%d (all cores, %.1f s) and %d (1 thread, %.1f s) of %d 128x128 output "
+                      "tiles of the %dx%dx%d FP64 fault-tolerant GEMM (encode, multiply, verify "
+                      "per tile)" % (c_all, dt_all, c_one, dt_one, ntiles, m, n, k)}
 
 
 def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
@@ -146,8 +164,9 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
             dC0[i0:i0 + 256, j0:j0 + 256].to(torch.float64)
         got = dC[i0:i0 + 256, j0:j0 + 256].to(torch.float64)
         errs.append(float((got - ref).abs().max() / ref.abs().max()))
-    t_ft, t_ft_ev = timed(torch, call(True), steps, warmup)
-    t_plain, _ = timed(torch, call(False), steps, warmup)
+    reset = lambda: dC.copy_(dC0)
+    t_ft, _ = timed(torch, call(True), steps, warmup, reset)
+    t_plain, _ = timed(torch, call(False), steps, warmup, reset)
     tm, tn, bk, _ = F.query_tiling(dtype, m, n, k)
     tiles = (-(-m // tm)) * (-(-n // tn))
     gp = synth.rng(wid, size, synth.STREAM_PLAN)
@@ -155,8 +174,9 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
     # the rounding threshold unless the accumulator is exactly zero
     plan = synth.bitflip_plan(gp, m, n, k, tm, tn, -(-tiles // 64), bits=[27, 28, 29, 30])
     F.set_fault_plan(plan)
-    t_inj, _ = timed(torch, call(True), steps, warmup)
+    t_inj, _ = timed(torch, call(True), steps, warmup, reset)
     rb = F.ReportBuffer()
+    dC.copy_(dC0)
     F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype), report=rb)
     inj = rb.view()
     F.clear_fault_plan()
@@ -183,14 +203,15 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
     F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=2, scaleA=sa, scaleB=sb, dtype=dtype),
               report=rb1)
     clean1 = rb1.view()
-    t_one, _ = timed(torch, call(2), steps, warmup)
+    t_one, _ = timed(torch, call(2), steps, warmup, reset)
     tm1, tn1, bk1, _ = F.query_tiling_ex(dtype, m, n, k, abft=2)
     tiles1 = (-(-m // tm1)) * (-(-n // tn1))
     plan1 = synth.bitflip_plan(synth.rng(wid, size, synth.STREAM_PLAN), m, n, k, tm1, tn1,
                                -(-tiles1 // 64), bits=[27, 28, 29, 30])
     F.set_fault_plan(plan1)
-    t_one_inj, _ = timed(torch, call(2), steps, warmup)
+    t_one_inj, _ = timed(torch, call(2), steps, warmup, reset)
     rb1 = F.ReportBuffer()
+    dC.copy_(dC0)
     F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=2, scaleA=sa, scaleB=sb, dtype=dtype),
               report=rb1)
     inj1 = rb1.view()
@@ -207,7 +228,7 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
                      "overhead_pct": round(100.0 * (t_one_inj / t_plain - 1.0), 2),
                      "detected": int(inj1.detected), "recomputed": int(inj1.recomputed)},
     }
-    achieved = flops / (t_ft_ev * 1e-3) / 1e12
+    achieved = flops / (t_ft * 1e-3) / 1e12
     return {
         "tflops": round(flops / (t_ft * 1e-3) / 1e12, 3),
         "ms_per_call": round(t_ft, 4),
@@ -243,19 +264,24 @@ def split_leg(torch, F, synth, steps, warmup):
         g = torch.Generator(device="cuda").manual_seed(m + n + k)
         A = F.colmajor_empty(m, k, torch.float64).normal_(generator=g)
         B = F.colmajor_empty(k, n, torch.float64).normal_(generator=g)
-        C = F.colmajor_empty(m, n, torch.float64).normal_(generator=g)
+        C0 = F.colmajor_empty(m, n, torch.float64).normal_(generator=g)
+        C = C0.clone()
+        reset = lambda: C.copy_(C0)
         flops = 2.0 * m * n * k
         slices = F.query_tiling(F.F64, m, n, k)[3]
         F.clear_fault_plan()
-        t_ft, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0)), steps, warmup)
+        t_ft, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0)), steps, warmup,
+                        reset)
         t_pl, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0, abft=False)),
-                        steps, warmup)
+                        steps, warmup, reset)
         tiles = (-(-m // 128)) * (-(-n // 128))
         plan = synth.additive_plan(synth.rng(50, k, synth.STREAM_PLAN), m, n, k, 128, 128,
                                    max(1, tiles // 32), synth.log_magnitude((k + 1.0) ** 0.5))
         F.set_fault_plan(plan)
-        t_inj, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0)), steps, warmup)
+        t_inj, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0)), steps, warmup,
+                         reset)
         rb = F.ReportBuffer()
+        reset()
         F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0), report=rb)
         v = rb.view()
         F.clear_fault_plan()
@@ -266,7 +292,7 @@ def split_leg(torch, F, synth, steps, warmup):
                     "injected": {"faults_per_call": len(plan),
                                  "overhead_pct": round(100.0 * (t_inj / t_pl - 1.0), 2),
                                  "corrected": int(v.corrected), "detected": int(v.detected)}})
-        del A, B, C
+        del A, B, C, C0
         torch.cuda.empty_cache()
     return out
 
@@ -420,16 +446,18 @@ def main():
     clean = rb.view()
 
     F.clear_fault_plan()
-    t_ft, t_ft_ev = timed(torch, call(True), args.steps, args.warmup)
-    t_plain, t_plain_ev = timed(torch, call(False), args.steps, args.warmup)
+    reset = lambda: dC.copy_(dC0)
+    t_ft, t_ft_wall = timed(torch, call(True), args.steps, args.warmup, reset)
+    t_plain, _ = timed(torch, call(False), args.steps, args.warmup, reset)
 
     tiles = (m // 128) * (n // 128)
     g = synth.rng(20, m, synth.STREAM_PLAN)
     sigma = float(np.sqrt(k / 9.0 + 1.0 / 3.0))
     plan = synth.additive_plan(g, m, n, k, 128, 128, -(-tiles // 64), synth.log_magnitude(sigma))
     F.set_fault_plan(plan)
-    t_inj, t_inj_ev = timed(torch, call(True), args.steps, args.warmup)
+    t_inj, _ = timed(torch, call(True), args.steps, args.warmup, reset)
     rb = F.ReportBuffer()
+    reset()
     F.gemm(dA, dB, dC, 1.0, 1.0, report=rb)
     inj = rb.view()
     # two faults in each of 64 other tiles, in different rows and columns
@@ -437,26 +465,28 @@ def main():
     plan2 = synth.crossing_pairs_plan(synth.rng(20, m + 1, synth.STREAM_PLAN), m, n, k, 128, 128,
                                       -(-tiles // 64), synth.log_magnitude(sigma))
     F.set_fault_plan(plan2)
-    t_pairs, _ = timed(torch, call(True), args.steps, args.warmup)
+    t_pairs, _ = timed(torch, call(True), args.steps, args.warmup, reset)
     rb = F.ReportBuffer()
+    reset()
     F.gemm(dA, dB, dC, 1.0, 1.0, report=rb)
     inj2 = rb.view()
     F.set_fault_plan(plan)
     # the unfused ablation (separate checksum passes around the plain
     # GEMM, detection only) under the same faults, then error-free
     rb = F.ReportBuffer()
+    reset()
     F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=3), report=rb)
     inj_uf = rb.view()
-    t_uf_inj, _ = timed(torch, call(3), args.steps, args.warmup)
+    t_uf_inj, _ = timed(torch, call(3), args.steps, args.warmup, reset)
     F.clear_fault_plan()
     dC.copy_(dC0)
     rb = F.ReportBuffer()
     F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=3), report=rb)
     clean_uf = rb.view()
-    t_uf, _ = timed(torch, call(3), args.steps, args.warmup)
+    t_uf, _ = timed(torch, call(3), args.steps, args.warmup, reset)
 
     value = flops / (t_ft * 1e-3) / 1e12
-    achieved = flops / (t_ft_ev * 1e-3) / 1e12
+    achieved = value
     traffic = read_traffic("ftgemm_f64_8192_counters.txt",
                            ["ftgemm_f64.hip", "ftgemm_device.h"]) if m == 8192 else None
     out = {

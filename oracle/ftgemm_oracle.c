@@ -952,6 +952,23 @@ int64_t oracle_ftgemm(const oracle_params *P, const double *A, const double *B,
     return nrec;
 }
 
+/* Threads the OpenMP loops use from now on (the CPU baseline is timed at
+ * one thread and at all of them); returns the previous setting. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int32_t oracle_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    const int32_t prev = (int32_t)omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return prev;
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* Sizes of the structures, so the Python side can check its mirror. */
 int64_t oracle_sizeof(int which)
 {

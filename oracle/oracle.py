@@ -29,10 +29,15 @@ CORRECTED, CHECKSUM_ONLY, RECOMPUTED, UNCORRECTABLE = 1, 2, 3, 4
 DEFAULT_LAMBDA = 8.0
 
 
-def compile_source(src: str, out: str) -> str:
-    """gcc, plain -O3 with OpenMP; portable x86-64 code (no -march)."""
+LIB_NATIVE = os.path.join(HERE, "libftgemm_oracle_native.so")
+
+
+def compile_source(src: str, out: str, native: bool = False) -> str:
+    """gcc -O3 with OpenMP: portable x86-64 code, or (native) code for the
+    host it is built on (-march=native), as the CPU baseline is timed."""
     tmp = out + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+    arch = ["-march=native"] if native else []
+    subprocess.check_call(["gcc", "-O3"] + arch + ["-std=c11", "-fPIC", "-shared", "-fopenmp",
                            "-Wall", "-o", tmp, src, "-lm"])
     os.replace(tmp, out)
     return out
@@ -42,6 +47,13 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         compile_source(SRC, LIB)
     return LIB
+
+
+def native() -> "Oracle":
+    """The same source built for the host it runs on (compiled on first use,
+    there: the build container's CPU may differ from the one timed)."""
+    compile_source(SRC, LIB_NATIVE, native=True)
+    return Oracle(LIB_NATIVE)
 
 
 class _Inj(C.Structure):
@@ -138,11 +150,17 @@ class Oracle:
                                              C.c_int64, dp, dp]
         L.oracle_tile_checksums.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_int64,
                                             C.c_int64, dp, dp, dp, dp]
+        L.oracle_set_threads.restype = C.c_int32
+        L.oracle_set_threads.argtypes = [C.c_int32]
         L.oracle_sizeof.restype = C.c_int64
         L.oracle_sizeof.argtypes = [C.c_int]
         for idx, cls in enumerate((_Inj, _Rec, _Echo, _Params)):
             assert L.oracle_sizeof(idx) == C.sizeof(cls), cls
         self.L = L
+
+    def set_threads(self, n: int) -> int:
+        """OpenMP threads of the following calls; returns the previous count."""
+        return int(self.L.oracle_set_threads(int(n)))
 
     # -- number formats ---------------------------------------------------
     def decode_bf16(self, bits):

@@ -722,8 +722,31 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                 break;
             }
         } else if (nr + nc == 1) {
-            kind = FTGEMM_KIND_CHECKSUM_ONLY;
-            break;
+            // A lone disagreement.  A data error shows on both sides, each
+            // up to its own rounding, so it stays below every threshold of
+            // the other side only if it is at most twice the largest of
+            // them; the flagged residual is then within its own threshold
+            // plus that.  Beyond this bound only the checksum path can have
+            // been hit and the data stays as it is; within it the tile is
+            // computed again.
+            const bool by_col = nc == 1;
+            if (w == 0) {
+                const double *tau_o = by_col ? sm.u.epi.tau_row : sm.u.epi.tau_col;
+                const int cnt = by_col ? hrows : wcols;
+                double o = 0.0;
+                for (int x = lane; x < cnt; x += 64) o = fmax(o, tau_o[x]);
+                o = max64(o);
+                if (lane == 0) sm.red[3][0] = o;
+            }
+            __syncthreads();
+            const double d = by_col ? sm.u.epi.d_col[first_j] : sm.u.epi.d_row[first_i];
+            const double bound =
+                (by_col ? sm.u.epi.tau_col[first_j] : sm.u.epi.tau_row[first_i]) +
+                2.0 * sm.red[3][0];
+            if (!(fabs(d) <= bound)) {
+                kind = FTGEMM_KIND_CHECKSUM_ONLY;
+                break;
+            }
         }
         // Several disagreements, or a rebuilt value that does not confirm:
         // keep the first attempt's residuals for the record, then compute

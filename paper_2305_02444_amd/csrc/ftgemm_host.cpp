@@ -248,6 +248,36 @@ size_t elem_size(ftgemm_dtype dt)
     return dt == FTGEMM_F64 ? 8 : dt == FTGEMM_BF16 ? 2 : 1;
 }
 
+// The loaders address one step of an operand through a buffer resource of at
+// most 2^31 - 1 bytes with 32-bit byte offsets, and the norms pass reads one
+// stored column per resource.  A call whose windows do not fit would read
+// zeros or wrapped addresses without any sign, so it is refused: position 8
+// or 10 when the leading dimension makes a step's window too wide, 3, 4 or 5
+// when one stored column of an operand alone exceeds it.
+int check_windows(const ftgemm_gemm_desc &d)
+{
+    const int64_t lim = INT32_MAX;
+    const int64_t eb = (int64_t)elem_size(d.dtype);
+    // largest outer extent of a tile, and the inner span of one step
+    const int64_t outer = d.dtype == FTGEMM_F64 ? 128 : 256;
+    const int64_t span = d.dtype == FTGEMM_F64 ? 32 : d.dtype == FTGEMM_BF16 ? 64 : 128;
+    struct Op { bool outer_contig; int64_t rows, cols, ld; int pos_ld, pos_rows; };
+    const Op ops[2] = {
+        {d.transA == FTGEMM_OP_N, d.transA == FTGEMM_OP_N ? d.m : d.k,
+         d.transA == FTGEMM_OP_N ? d.k : d.m, d.lda, 8, d.transA == FTGEMM_OP_N ? 3 : 5},
+        {d.transB == FTGEMM_OP_T, d.transB == FTGEMM_OP_N ? d.k : d.n,
+         d.transB == FTGEMM_OP_N ? d.n : d.k, d.ldb, 10, d.transB == FTGEMM_OP_N ? 5 : 4}};
+    if (d.m == 0 || d.n == 0 || d.k == 0) return 0;
+    for (const Op &o : ops) {
+        if (o.rows * eb > lim) return o.pos_rows;
+        const int64_t scols = o.outer_contig ? std::min(span, o.cols) : std::min(outer, o.cols);
+        const int64_t srows = o.outer_contig ? std::min(outer, o.rows) : std::min(span, o.rows);
+        // elements from the window's first element to the last one a step reads
+        if (scols > 1 && o.ld > (lim / eb - srows) / (scols - 1)) return o.pos_ld;
+    }
+    return 0;
+}
+
 // Argument checks in BLAS order; returns 0 or the 1-based position.
 int check_args(const ftgemm_gemm_desc &d)
 {
@@ -274,7 +304,7 @@ int check_args(const ftgemm_gemm_desc &d)
         return 14;
     if (d.abft < 0 || d.abft > 3) return 14;
     if (d.m > INT32_MAX / 2 || d.n > INT32_MAX / 2) return d.m > INT32_MAX / 2 ? 3 : 4;
-    return 0;
+    return check_windows(d);
 }
 
 GemmArgs base_args(const ftgemm_gemm_desc &d, int tm, int tn)

@@ -170,8 +170,22 @@ __global__ __launch_bounds__(NT) void reduce_kernel(ReduceArgs r)
                 break;
             }
         } else if (nr + nc == 1) {
-            kind = FTGEMM_KIND_CHECKSUM_ONLY;
-            break;
+            // a checksum fault only beyond the entry's threshold plus twice
+            // the other side's largest (a data error shows on both sides)
+            if (t == 0) {
+                const int side_o = nc == 1 ? 0 : 1;
+                const int cnt = nc == 1 ? hrows : wcols;
+                double o = 0.0;
+                for (int x2 = 0; x2 < cnt; ++x2) o = fmax(o, sm.tau[side_o][x2]);
+                const double dd = nc == 1 ? sm.d[1][bj] : sm.d[0][bi];
+                const double own = nc == 1 ? sm.tau[1][bj] : sm.tau[0][bi];
+                sm.red[2][0] = !(fabs(dd) <= own + 2.0 * o) ? 1.0 : 0.0;
+            }
+            __syncthreads();
+            if (sm.red[2][0] != 0.0) {
+                kind = FTGEMM_KIND_CHECKSUM_ONLY;
+                break;
+            }
         }
         __syncthreads();
         if (t == 0) { sm.nbad[0] = sm.nbad[1] = 0; sm.bad[0] = sm.bad[1] = T; }

@@ -110,3 +110,50 @@ def lp_mma(dtype):
 def lp_tiling(dtype, m, n, k):
     tm, tn, bk, sk = F.query_tiling(dtype, m, n, k)
     return tm, tn, bk
+
+
+# -- rounding bound of a rebuilt element -------------------------------------
+
+U32 = 2.0 ** -24
+LAMBDA = 8.0
+
+
+def _enc_error(chk, vec, parts):
+    """lambda-sigma model of the FP32 rounding of one encoded checksum
+    sum_p chk_p vec_p accumulated in order of p: the partial sums' roundings
+    (u sqrt(sum_k S_k^2)), the products' roundings, and the roundings inside
+    each chk_p, an FP32 sum whose partial sums are parts[:, p]."""
+    prod = chk * vec
+    S = np.cumsum(prod)
+    e_acc = np.sqrt(np.sum(S * S))
+    e_prod = np.sqrt(np.sum(prod * prod))
+    X = np.sqrt(np.sum(parts * parts, axis=0))
+    e_chk = np.sqrt(np.sum((X * vec) ** 2))
+    return LAMBDA * U32 * (e_acc + e_prod + e_chk)
+
+
+def rebuild_bound(dA, dB, ta, tb, alpha, tm, tn, got, exact, i, j):
+    """How far an element rebuilt from its tile's FP32 checksums may lie from
+    the exact product.  Rebuilt from column j's checksum it is
+    P_j - sum_{i' != i} out(i', j): its error is the encoded checksum's own
+    rounding error plus the other outputs' errors in the column, which the
+    test measures exactly (got - exact); from row i's checksum likewise.
+    The checksum's rounding is modelled from the actual partial sums (a
+    lambda = 8 standard-deviation bound, about sqrt(k) tighter than the
+    detection threshold's norm bound), and the rebuilt value's own FP32
+    rounding is added.  The larger of the two sides is returned."""
+    oA = dA.T if ta else dA
+    oB = dB.T if tb else dB
+    i0, j0 = (i // tm) * tm, (j // tn) * tn
+    I = slice(i0, min(i0 + tm, oA.shape[0]))
+    J = slice(j0, min(j0 + tn, oB.shape[1]))
+    # from the column: x = e^T A_I, encoded sum_p x_p B(p, j)
+    part_x = np.cumsum(oA[I, :], axis=0)
+    e_col = abs(alpha) * _enc_error(part_x[-1], oB[:, j], part_x)
+    other_c = np.sum(got[I, j] - exact[I, j]) - (got[i, j] - exact[i, j])
+    # from the row: y = B_J e, encoded sum_p A(i, p) y_p
+    part_y = np.cumsum(oB[:, J], axis=1).T
+    e_row = abs(alpha) * _enc_error(part_y[-1], oA[i, :], part_y)
+    other_r = np.sum(got[i, J] - exact[i, J]) - (got[i, j] - exact[i, j])
+    own = 2.0 * U32 * abs(exact[i, j])
+    return max(abs(other_c) + e_col, abs(other_r) + e_row) + own

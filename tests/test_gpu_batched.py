@@ -9,7 +9,7 @@ the same tile code, so their outputs must be bitwise equal."""
 import numpy as np
 import pytest
 
-from gpu_util import flagged, lp_mma, normwise, say, to_oracle
+from gpu_util import flagged, lp_mma, normwise, rebuild_bound, say, to_oracle
 from oracle import oracle as O
 from paper_2305_02444_amd import ftgemm as F
 from paper_2305_02444_amd import synth
@@ -80,11 +80,15 @@ def _check_problem(p, got, host, shapes, plan, rep, dtype, alpha, beta, tiles=No
                              acc_bits=64 if dtype == F.F64 else 32, injections=to_oracle(pp),
                              tiles=tiles, mma=lp_mma(dtype))
     mask = ~np.isnan(ref.C)
-    for r in rep.records:
-        if r["kind"] == F.KIND_CORRECTED and dtype != F.F64:
-            mask[r["row"], r["col"]] = False
-            assert abs(got[r["row"], r["col"]] - ref.C[r["row"], r["col"]]) <= \
-                max(r["tau_row"], r["tau_col"])
+    if dtype != F.F64:
+        # rebuilt elements: held to the rounding bound of a rebuild
+        corrected = {(r["tile_m"], r["tile_n"]) for r in rep.records
+                     if r["kind"] == F.KIND_CORRECTED}
+        for i, j in np.argwhere(mask & (ref.raw != ref.C)):
+            if (i // 128, j // 128) in corrected:
+                assert abs(got[i, j] - ref.C[i, j]) <= \
+                    rebuild_bound(dA, dB, False, False, alpha, 128, 128, got, ref.C, i, j)
+                mask[i, j] = False
     assert normwise(got[mask], ref.C[mask]) <= TOL[dtype], p
     recs = rep.records
     if tiles is not None:
@@ -164,12 +168,12 @@ def test_batch_several_errors_per_tile(dtype):
         kinds += sorted((p, r["kind"], r["nbad_rows"], r["nbad_cols"]) for r in recs)
         mask = np.ones(got[p].shape, dtype=bool)
         if dtype != F.F64:
-            bounds = {(r["tile_m"], r["tile_n"]): max(r["tau_row"], r["tau_col"])
-                      for r in recs if r["kind"] == F.KIND_CORRECTED}
+            corrected = {(r["tile_m"], r["tile_n"]) for r in recs
+                         if r["kind"] == F.KIND_CORRECTED}
             for i, j in np.argwhere(ref.raw != ref.C):
-                bound = bounds.get((i // 128, j // 128))
-                if bound is not None:
-                    assert abs(got[p][i, j] - ref.C[i, j]) <= bound
+                if (i // 128, j // 128) in corrected:
+                    assert abs(got[p][i, j] - ref.C[i, j]) <= \
+                        rebuild_bound(dA, dB, False, False, 1.0, 128, 128, got[p], ref.C, i, j)
                     mask[i, j] = False
         assert normwise(got[p][mask], ref.C[mask]) <= TOL[dtype], p
     assert kinds == [(0, F.KIND_CORRECTED, 1, 2), (0, F.KIND_CORRECTED, 2, 2),

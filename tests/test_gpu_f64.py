@@ -234,10 +234,11 @@ def test_c2_square_full_compare(size):
     assert rep.corrected == len(plan) == rep.detected
 
 
-def test_c2_8192_sampled_tiles():
-    """Full size 8192^3 as timed by the benchmark; the oracle checks every
-    tile that holds a fault plus sampled clean and corner tiles."""
-    size = 8192
+@pytest.mark.parametrize("size", [4096, 8192])
+def test_c2_sampled_tiles(size):
+    """4096^3 and the full 8192^3 timed by the benchmark; error-free, then
+    one fault per 64 tiles: the oracle checks every tile that holds a fault
+    (up to 24) plus sampled clean and corner tiles."""
     A, B, Cin = synth.operands(20, size, size, size, size, "uniform")
     sigma = np.sqrt(size / 9.0 + 1.0 / 3.0)
     tiles_m = size // 128
@@ -248,6 +249,9 @@ def test_c2_8192_sampled_tiles():
     extra = [0, tiles_m * tiles_m - 1, tiles_m - 1] + list(synth.rng(20, 1, 9).choice(
         tiles_m * tiles_m, 8, replace=False))
     tiles = sorted(set(faulty[:24]) | set(int(t) for t in extra))
+    got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, False, False, [], tiles=tiles)
+    assert not rep.records and 0 < rep.max_ratio < 1
+    assert rep.tiles_verified == tiles_m * tiles_m
     got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, False, False, plan, tiles=tiles)
     assert rep.corrected == len(plan) == rep.detected
     assert rep.tiles_verified == tiles_m * tiles_m
