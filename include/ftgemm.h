@@ -217,6 +217,28 @@ ftgemm_status ftgemm_gemm_ex(const ftgemm_gemm_desc *desc, ftgemm_report *report
 ftgemm_status ftgemm_gemm_batched(int32_t count, const ftgemm_gemm_desc *problems,
                                   ftgemm_report *reports, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * same call as ftgemm_gemm_ex, and the same kernels, with nothing
+ * allocated.  The device memory it needs besides A, B and C -- the report
+ * counters, 1024 record slots, and the fault plan with its echo slots -- is
+ * a fixed 128 KiB array per GPU inside the library, which each GPU the
+ * library runs on keeps until the process ends.  So that nothing grows with
+ * the problem, the FP64 inner dimension is never split (slower on outputs
+ * of few tiles) and BF16 / FP8 tiles form their threshold norms and operand
+ * checksums themselves, with no pass over A and B before the product (C is
+ * the same; a rebuilt element may differ from ftgemm_gemm_ex's in its last
+ * FP32 bits).  Refused with FTGEMM_ERR_UNSUPPORTED: abft 2 and 3 (their
+ * workspace grows with the problem) and an armed fault plan longer than
+ * 256 entries.  Records beyond 1024 are dropped (still counted).  Every
+ * call on a GPU shares that GPU's array and keeps the last call's contents
+ * in it: calls that overlap on one GPU (on different streams, or from
+ * different threads without synchronising) race and must not be issued.
+ * A report, when asked for, is filled before the call returns (it waits for
+ * the stream), through host staging inside the library. */
+ftgemm_status ftgemm_gemm_ex_noalloc(const ftgemm_gemm_desc *desc, ftgemm_report *report,
+                                     void *stream);
+
 /* The same problems launched one by one (the baseline the persistent
  * launch is measured against). */
 ftgemm_status ftgemm_gemm_batched_loop(int32_t count, const ftgemm_gemm_desc *problems,

@@ -202,10 +202,27 @@ double unpack_ratio(unsigned long long bits)
     return v;
 }
 
+// Host copies of a report area: counters per problem, the record-slot
+// counter, the record slots and the echo slots of the plan's faults.
+struct HostReport {
+    const DevCounters *h_counters;
+    const unsigned int *h_aux;
+    const ftgemm_fault_record *h_records;
+    const ftgemm_injection_echo *h_echo;
+    int nplan;
+    uint32_t rec_cap;
+};
+
+HostReport host_report(const DeviceWs &ws)
+{
+    return HostReport{ws.h_counters, ws.h_aux, ws.h_records, ws.h_echo, ws.nplan, kDevRecordCap};
+}
+
 // Copy the report area of problem `p` (and the echo slots of its faults)
 // into the caller's report; the stream has been synchronised.
-void fill_report(const DeviceWs &ws, int p, ftgemm_report *rep, int32_t problem)
+void fill_report(const HostReport &ws, int p, ftgemm_report *rep, int32_t problem)
 {
+    const uint32_t rec_cap = ws.rec_cap;
     const DevCounters &c = ws.h_counters[p];
     rep->tiles_verified = c.tiles_verified;
     rep->detected = c.detected;
@@ -217,7 +234,7 @@ void fill_report(const DeviceWs &ws, int p, ftgemm_report *rep, int32_t problem)
     rep->record_count = 0;
     rep->echo_count = 0;
     // record slots are shared by the problems of a call (h_aux[0] taken)
-    const uint32_t nslot = ws.h_aux[0] < kDevRecordCap ? ws.h_aux[0] : kDevRecordCap;
+    const uint32_t nslot = ws.h_aux[0] < rec_cap ? ws.h_aux[0] : rec_cap;
     uint32_t kept = 0;
     for (uint32_t r = 0; r < nslot; ++r) {
         const ftgemm_fault_record &src = ws.h_records[r];
@@ -341,7 +358,7 @@ ftgemm_status copy_report(DeviceWs &ws, ftgemm_report *rep, hipStream_t stream, 
         HIP_TRY(hipMemcpyAsync(ws.h_echo, ws.echo, sizeof(ftgemm_injection_echo) * ws.nplan,
                                hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    fill_report(ws, 0, rep, problem);
+    fill_report(host_report(ws), 0, rep, problem);
     return FTGEMM_OK;
 }
 
@@ -926,12 +943,113 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
                                    sizeof(ftgemm_injection_echo) * ws->nplan,
                                    hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
-        for (int32_t p = 0; p < count; ++p) fill_report(*ws, p, &reps[p], p);
+        for (int32_t p = 0; p < count; ++p) fill_report(host_report(*ws), p, &reps[p], p);
     }
     return FTGEMM_OK;
 }
 
+// Host staging of the no-allocation path's report copy-back: file-scope
+// arrays, so that path allocates nothing (used with g_mu held).
+DevCounters g_na_counters[1];
+unsigned int g_na_aux[kAuxWords];
+ftgemm_fault_record g_na_records[ftg::kNoAllocRecords];
+ftgemm_injection_echo g_na_echo[ftg::kNoAllocPlan];
+
 }  // namespace
+
+namespace ftg {
+
+// ftgemm_gemm_ex with every piece of device memory the call needs taken
+// from `scratch` (the caller's per-device array of kNoAllocBytes): the
+// counters, the record slots (kNoAllocRecords), the fault plan and its
+// echo slots (kNoAllocPlan).  Nothing grows with m, n or k: the FP64 inner
+// dimension is never split, and low-precision tiles form their threshold
+// norms and operand checksums themselves (no pass before the product).
+ftgemm_status run_noalloc(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t stream,
+                          unsigned char *scratch, size_t bytes)
+{
+    t_last_invalid = 0;
+    if (int pos = check_args(d)) return invalid(pos);
+    if (rep && ((rep->record_capacity && !rep->records) || (rep->echo_capacity && !rep->echoes)))
+        return invalid(14);
+    if (rep) std::memset(rep, 0, offsetof(ftgemm_report, record_capacity));
+    if (d.m == 0 || d.n == 0) return FTGEMM_OK;
+    const bool c_is_f64 = d.dtype == FTGEMM_F64;
+    if (d.alpha == 0.0 || d.k == 0) {
+        if (d.beta == 1.0) return FTGEMM_OK;
+        HIP_TRY(ftg::launch_scale(d.C, c_is_f64, d.m, d.n, d.ldc, d.beta, stream));
+        return FTGEMM_OK;
+    }
+    // the one-sided and unfused modes need workspace that grows with the
+    // problem
+    if (d.abft == 2 || d.abft == 3) return FTGEMM_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_mu);
+    const int nplan = d.abft ? (int)g_plan.size() : 0;
+    if (nplan > kNoAllocPlan) {
+        report_hip_failure("ftgemm_gemm_ex_noalloc: fault plan longer than its 256 slots",
+                           hipErrorInvalidValue);
+        return FTGEMM_ERR_UNSUPPORTED;
+    }
+    if (d.dtype != FTGEMM_F64 && d.abft)
+        for (const ftgemm_injection &f : g_plan)  // FP32 accumulators have 32 bits
+            if (f.mode == FTGEMM_INJ_BITFLIP && f.bit >= 32) return invalid(14);
+    // carve the scratch array (256-byte aligned parts)
+    size_t off = 0;
+    auto take = [&](size_t nbytes) {
+        unsigned char *q = scratch + off;
+        off += (nbytes + 255) & ~size_t(255);
+        return q;
+    };
+    DevCounters *counters = (DevCounters *)take(sizeof(DevCounters));
+    unsigned int *aux = (unsigned int *)take(sizeof(unsigned int) * kAuxWords);
+    ftgemm_fault_record *records =
+        (ftgemm_fault_record *)take(sizeof(ftgemm_fault_record) * kNoAllocRecords);
+    ftgemm_injection *plan = (ftgemm_injection *)take(sizeof(ftgemm_injection) * kNoAllocPlan);
+    ftgemm_injection_echo *echo =
+        (ftgemm_injection_echo *)take(sizeof(ftgemm_injection_echo) * kNoAllocPlan);
+    if (off > bytes) return FTGEMM_ERR_HIP;
+
+    int tm, tn, bk;
+    if (d.dtype == FTGEMM_F64)
+        ftg::tiling_f64(&tm, &tn, &bk);
+    else
+        ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, &tm, &tn, &bk);
+    GemmArgs g = base_args(d, tm, tn);
+    const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
+    g.counters = counters;
+    g.records = records;
+    g.record_cap = kNoAllocRecords;
+    g.rec_slot = aux;
+    g.nplan = nplan;
+    g.plan = plan;
+    g.echo = echo;
+    if (nplan)
+        HIP_TRY(hipMemcpyAsync(plan, g_plan.data(), sizeof(ftgemm_injection) * nplan,
+                               hipMemcpyHostToDevice, stream));
+    // the counters, record slots and echo slots start from zero every call
+    // (the array keeps the last call's contents)
+    if (d.abft) HIP_TRY(ftg::launch_clear_report(counters, 1, echo, nplan, aux, 1, stream));
+    if (d.dtype == FTGEMM_F64)
+        HIP_TRY(ftg::launch_f64(g, ta, tb, d.abft != 0, stream));
+    else
+        HIP_TRY(ftg::launch_lp(g, d.dtype == FTGEMM_FP8_E4M3, ta, tb, d.abft, false, tm, stream));
+    if (!(rep && d.abft)) return FTGEMM_OK;
+    HIP_TRY(hipMemcpyAsync(g_na_counters, counters, sizeof(DevCounters), hipMemcpyDeviceToHost,
+                           stream));
+    HIP_TRY(hipMemcpyAsync(g_na_aux, aux, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(g_na_records, records, sizeof(ftgemm_fault_record) * kNoAllocRecords,
+                           hipMemcpyDeviceToHost, stream));
+    if (nplan)
+        HIP_TRY(hipMemcpyAsync(g_na_echo, echo, sizeof(ftgemm_injection_echo) * nplan,
+                               hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    fill_report(HostReport{g_na_counters, g_na_aux, g_na_records, g_na_echo, nplan,
+                           (uint32_t)kNoAllocRecords},
+                0, rep, 0);
+    return FTGEMM_OK;
+}
+
+}  // namespace ftg
 
 extern "C" {
 

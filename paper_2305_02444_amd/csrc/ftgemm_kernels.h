@@ -111,6 +111,15 @@ struct BatchArgs {
 };
 hipError_t launch_f64_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int grid,
                               hipStream_t stream);
+
+// The no-allocation entry point: device scratch of kNoAllocBytes per GPU
+// (a file-scope array of ftgemm_noalloc.hip) holding the counters,
+// kNoAllocRecords record slots and kNoAllocPlan fault-plan and echo slots.
+constexpr size_t kNoAllocBytes = 128 * 1024;
+constexpr int kNoAllocRecords = 1024;
+constexpr int kNoAllocPlan = 256;
+ftgemm_status run_noalloc(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t stream,
+                          unsigned char *scratch, size_t bytes);
 hipError_t launch_lp_batched(const BatchArgs &b, bool fp8, bool ta, bool tb, bool abft, int grid,
                              hipStream_t stream);
 

@@ -90,6 +90,8 @@ def lib():
                                   vp, i64, C.POINTER(Report), vp]
         L.ftgemm_gemm_ex.restype = C.c_int
         L.ftgemm_gemm_ex.argtypes = [C.POINTER(GemmDesc), C.POINTER(Report), vp]
+        L.ftgemm_gemm_ex_noalloc.restype = C.c_int
+        L.ftgemm_gemm_ex_noalloc.argtypes = [C.POINTER(GemmDesc), C.POINTER(Report), vp]
         for name in ("ftgemm_gemm_batched", "ftgemm_gemm_batched_loop"):
             f = getattr(L, name)
             f.restype = C.c_int
@@ -257,6 +259,12 @@ def gemm(A, B, Cm, alpha=1.0, beta=0.0, transA=False, transB=False, report=None,
 def gemm_ex(desc: GemmDesc, report=None, stream=None):
     rp = C.byref(report.rep) if report is not None else None
     _check(lib().ftgemm_gemm_ex(C.byref(desc), rp, _stream(stream)), "ftgemm_gemm_ex")
+
+
+def gemm_ex_noalloc(desc: GemmDesc, report=None, stream=None):
+    rp = C.byref(report.rep) if report is not None else None
+    _check(lib().ftgemm_gemm_ex_noalloc(C.byref(desc), rp, _stream(stream)),
+           "ftgemm_gemm_ex_noalloc")
 
 
 def gemm_batched(descs, reports=None, stream=None, loop=False):
