@@ -516,8 +516,13 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
     constexpr bool kMma = !FP8;  // BF16: encoded checksums on the matrix cores
     constexpr bool kOne = ABFT && ONE;
     constexpr bool kPre = ABFT && (ONE || PRE);
-    // the checksum products of step s run during step s + 1
-    constexpr bool kLag = kMma && ABFT;
+    // with the operand checksums computed in the tiles, the checksum products
+    // of step s run during step s + 1 (its x/y parts are complete only after
+    // step s's barrier); with them taken before the product, the parts are
+    // staged with the tiles and the products run in their own step, on the
+    // wave's own fragments
+    constexpr bool kLag = kMma && ABFT && !kPre;
+    constexpr bool kInStep = kMma && ABFT && kPre;
     // kPre: the operand checksums x_p, y_p come from g.xsum, g.ysum (taken
     // with the norms before the product) instead of the staged registers
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -639,6 +644,16 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                 const int stg = s & 1;  // stage and checksum buffers of step s
                 la.store(sm.u.st[stg].A);
                 lb.store(sm.u.st[stg].B);
+                if (kInStep && t < E::BK) {
+                    // the parts of step s's x_p, y_p (taken before the
+                    // product) go to the stage's extra rows with the tiles
+                    vy = fmaf(py, py, vy);
+                    put_parts(sm.u.st[stg].B, TN, t, py);
+                    if (!kOne) {
+                        vx = fmaf(px, px, vx);
+                        put_parts(sm.u.st[stg].A, BM, t, px);
+                    }
+                }
                 if (ABFT && kPre && !kMma && t < E::BK) {
                     // x_p, y_p of step s (taken before the product) are
                     // staged with the tiles, so the step's one barrier
@@ -652,21 +667,21 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                     }
                 }
                 __syncthreads();
-                if (ABFT && kMma) {
+                if (kLag) {
                     // x_p, y_p of step s are complete: their parts go to the
                     // extra rows, for the checksum products of step s (run
                     // during step s + 1, after its barrier)
                     if (t < E::BK) {
-                        const float yp = kPre ? py : gather_lp<LB::kParts>(sm.ys[stg], t);
+                        const float yp = gather_lp<LB::kParts>(sm.ys[stg], t);
                         vy = fmaf(yp, yp, vy);
                         put_parts(sm.u.st[stg].B, TN, t, yp);
                         if (!kOne) {
-                            const float xp = kPre ? px : gather_lp<LA::kParts>(sm.xs[stg], t);
+                            const float xp = gather_lp<LA::kParts>(sm.xs[stg], t);
                             vx = fmaf(xp, xp, vx);
                             put_parts(sm.u.st[stg].A, BM, t, xp);
                         }
                     }
-                } else if (ABFT) {
+                } else if (ABFT && !kMma) {
                     // x_p, y_p of step s are complete: combined once (one
                     // thread per p; already staged when taken before the
                     // product), then the encoded checksums and norms of
@@ -719,6 +734,35 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                             for (int ni = 0; ni < NI; ++ni)
                                 acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                                     fa[mi], fb[ni], acc[mi][ni], 0, 0, 0);
+                        if (kInStep) {
+                            // this wave's check blocks are among its own
+                            // fragments: B block wm (columns WC wn + 16 wm)
+                            // and A blocks NA wn + h; the wave index is
+                            // uniform, so the choice is a scalar branch
+                            const int wm_s = __builtin_amdgcn_readfirstlane(wm);
+                            const int wn_s = __builtin_amdgcn_readfirstlane(wn);
+                            const unsigned char(*sA)[SROW] = sm.u.st[stg].A;
+                            const unsigned char(*sB)[SROW] = sm.u.st[stg].B;
+                            const bf8v fyb =
+                                *(const bf8v *)&sB[TN + c16][16 * swz(TN + c16, 4 * kk + q)];
+                            if (!kOne) {
+                                const bf8v fxa =
+                                    *(const bf8v *)&sA[BM + c16][16 * swz(BM + c16, 4 * kk + q)];
+#pragma unroll
+                                for (int ni = 0; ni < NI; ++ni)
+                                    if (ni == wm_s)
+                                        acc_r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                            fxa, fb[ni], acc_r, 0, 0, 0);
+                            }
+#pragma unroll
+                            for (int g2 = 0; g2 < G::WN; ++g2)
+                                if (g2 == wn_s) {
+#pragma unroll
+                                    for (int h = 0; h < NA; ++h)
+                                        acc_c[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                            fa[NA * g2 + h], fyb, acc_c[h], 0, 0, 0);
+                                }
+                        }
                         if (kLag) {
                             if (s > 0)
                                 check_products(sm.u.st[stg ^ 1], kk, hold_b[kk], hold_a[kk], acc_r,
