@@ -55,6 +55,20 @@ def read_traffic(name, files):
         return None
 
 
+def with_table(F, text, fn):
+    """Run fn() with a tuning table holding these lines, then an empty one."""
+    import tempfile
+    fd, path = tempfile.mkstemp(suffix=".tune")
+    with os.fdopen(fd, "w") as fh:
+        fh.write(text)
+    try:
+        F.load_tune_table(path)
+        return fn()
+    finally:
+        F.load_tune_table(None)
+        os.unlink(path)
+
+
 def timed(torch, fn, steps, warmup, reset=None):
     """Average per-call time (ms) over `steps` calls, from HIP events on the
     launch stream around each call.  reset (optional) runs before every
@@ -168,6 +182,14 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
     t_ft, _ = timed(torch, call(True), steps, warmup, reset)
     t_plain, _ = timed(torch, call(False), steps, warmup, reset)
     tm, tn, bk, _ = F.query_tiling(dtype, m, n, k)
+    tm0 = F.query_tiling_ex(dtype, m, n, k, abft=0)[0]
+    # the same kernel with checksums compiled out on the fault-tolerant
+    # call's own tile (the plain call's default tile may differ)
+    if tm0 != tm:
+        t_plain_same, _ = with_table(F, "tile %d 0 %d\n" % (dtype, tm),
+                                     lambda: timed(torch, call(False), steps, warmup, reset))
+    else:
+        t_plain_same = t_plain
     tiles = (-(-m // tm)) * (-(-n // tn))
     gp = synth.rng(wid, size, synth.STREAM_PLAN)
     # exponent flips (bits 27..30) of FP32 accumulators: always far above
@@ -233,7 +255,10 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
         "tflops": round(flops / (t_ft * 1e-3) / 1e12, 3),
         "ms_per_call": round(t_ft, 4),
         "plain_tflops": round(flops / (t_plain * 1e-3) / 1e12, 3),
+        "plain_tile": [tm0, tn, bk],
         "abft_overhead_pct": round(100.0 * (t_ft / t_plain - 1.0), 2),
+        "plain_same_tile_tflops": round(flops / (t_plain_same * 1e-3) / 1e12, 3),
+        "abft_overhead_same_tile_pct": round(100.0 * (t_ft / t_plain_same - 1.0), 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[name],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK[name], 4),
                      "traffic": read_traffic("ftgemm_%s_8192_counters.txt" % name,
@@ -316,17 +341,34 @@ def batched_leg(torch, F, synth, np, dtype, steps, warmup):
         descs_plain.append(F.make_desc(A, B, C, 1.0, 0.0, abft=False, dtype=dtype))
         flops += 2.0 * m * n * k
     F.clear_fault_plan()
-    F.gemm_batched(descs)  # tunes the schedule and captures the graph
+    F.gemm_batched(descs)  # tunes the tiles and the schedule, captures the graph
+    rows = F.batch_tiling(descs)
     t_b, _ = timed(torch, lambda: F.gemm_batched(descs), steps, warmup)
     F.gemm_batched(descs_plain)
+    rows_plain = F.batch_tiling(descs_plain)
     t_bp, _ = timed(torch, lambda: F.gemm_batched(descs_plain), steps, warmup)
+    per_choice = {}
+    if dtype != F.F64:
+        # each tile choice fixed by the table, fault-tolerant against plain
+        for label, mstar in (("all_128", 10 ** 9), ("256_from_512", 512),
+                             ("256_from_256", 256)):
+            def both():
+                F.gemm_batched(descs)
+                a, _ = timed(torch, lambda: F.gemm_batched(descs), steps, warmup)
+                F.gemm_batched(descs_plain)
+                b, _ = timed(torch, lambda: F.gemm_batched(descs_plain), steps, warmup)
+                return a, b
+            a, b = with_table(F, "batch_mstar %d\n" % mstar, both)
+            per_choice[label] = {"tflops": round(flops / (a * 1e-3) / 1e12, 3),
+                                 "plain_tflops": round(flops / (b * 1e-3) / 1e12, 3),
+                                 "abft_overhead_pct": round(100.0 * (a / b - 1.0), 2)}
     t_l, _ = timed(torch, lambda: F.gemm_batched(descs, loop=True), max(2, steps // 4), 1)
     gp = synth.rng(70, dtype, synth.STREAM_PLAN)
     plan = []
     for p, (m, n, k) in enumerate(shapes):
-        tiles = (-(-m // 128)) * (-(-n // 128))
+        tiles = (-(-m // rows[p])) * (-(-n // 128))
         cnt = min(synth.truncated_poisson(gp, 1.0, 3), tiles)
-        for f in synth.additive_plan(gp, m, n, k, 128, 128, cnt,
+        for f in synth.additive_plan(gp, m, n, k, rows[p], 128, cnt,
                                      synth.log_magnitude((k / 9.0) ** 0.5, 1.0, 6.0)):
             f.problem = p
             plan.append(f)
@@ -336,7 +378,8 @@ def batched_leg(torch, F, synth, np, dtype, steps, warmup):
     F.gemm_batched(descs, reps)
     views = [r.view() for r in reps]
     F.clear_fault_plan()
-    return {"problems": len(shapes), "gflop_per_call": round(flops / 1e9, 1),
+    out = {"problems": len(shapes), "gflop_per_call": round(flops / 1e9, 1),
+            "tile_rows_256": rows.count(256), "tile_rows_256_plain": rows_plain.count(256),
             "tflops": round(flops / (t_b * 1e-3) / 1e12, 3),
             "ms_per_call": round(t_b, 4),
             "plain_tflops": round(flops / (t_bp * 1e-3) / 1e12, 3),
@@ -347,6 +390,9 @@ def batched_leg(torch, F, synth, np, dtype, steps, warmup):
                          "overhead_pct": round(100.0 * (t_bi / t_bp - 1.0), 2),
                          "corrected": sum(int(v.corrected) for v in views),
                          "detected": sum(int(v.detected) for v in views)}}
+    if per_choice:
+        out["per_tile_choice"] = per_choice
+    return out
 
 
 def profile_run(kind, size, calls=3):

@@ -209,11 +209,18 @@ ftgemm_status ftgemm_gemm_ex(const ftgemm_gemm_desc *desc, ftgemm_report *report
  *     FTGEMM_ERR_INVALID_ARG with the position of its bad field.
  *   reports: NULL or a host array of `count` reports, one per problem; the
  *     fault plan's `problem` field is the index in `problems`.
- * The work order is tuned on the first call with a batch of a given shape
- * when every beta is 0 (C is then write-only, so the trial runs are
- * harmless); later calls with that shape reuse it.  The device arrays of
- * per-problem arguments and the captured graph belong to the library and
- * are reused while the batch's size and the plan stay the same. */
+ * Tiles: 128 x 128 for FP64 problems (inner step 32).  A BF16 / FP8
+ * problem takes 128 x 128 tiles, or 256 x 128 tiles when it has at least
+ * m* rows; m* (none, 1024, 512 or 256) and the work order (cost-ordered
+ * single queue, given order, or one queue per XCD) are tuned by timing the
+ * candidates on the batch itself, the first time a batch of its shape is
+ * seen with every beta 0 (C is then write-only, so the trial runs are
+ * harmless), and remembered for that shape, in the tuning table too (see
+ * ftgemm_load_tune_table); other batches of an unknown shape take the
+ * defaults (no 256-row tiles, cost order).  ftgemm_batch_tiling tells the
+ * rows each problem's tiles take.  The device arrays of per-problem
+ * arguments and the captured graph belong to the library and are reused
+ * while the batch's size and the plan stay the same. */
 ftgemm_status ftgemm_gemm_batched(int32_t count, const ftgemm_gemm_desc *problems,
                                   ftgemm_report *reports, void *stream);
 
@@ -243,6 +250,29 @@ ftgemm_status ftgemm_gemm_ex_noalloc(const ftgemm_gemm_desc *desc, ftgemm_report
  * launch is measured against). */
 ftgemm_status ftgemm_gemm_batched_loop(int32_t count, const ftgemm_gemm_desc *problems,
                                        ftgemm_report *reports, void *stream);
+
+/* Rows of the tiles each of `count` problems takes in ftgemm_gemm_batched
+ * now (128 or 256; see there), into tile_rows[count].  Errors: count < 0
+ * (position 1), problems NULL (2), tile_rows NULL (3). */
+ftgemm_status ftgemm_batch_tiling(int32_t count, const ftgemm_gemm_desc *problems,
+                                  int32_t *tile_rows);
+
+/* Replace the tuning table with the one in the text file `path` (NULL: an
+ * empty table).  Its lines, '#' starting a comment:
+ *   tile <dtype> <abft> <rows>   single BF16 (1) / FP8 (2) calls in mode
+ *                                abft (0..2) take tiles of rows = 128 or 256
+ *                                instead of the default choice
+ *   batch_mstar <m>              in low-precision batches, problems of at
+ *                                least m rows take 256-row tiles (the
+ *                                threshold is then not tuned; -1: tuned)
+ *   batch <sig> <order> <m>      a batch tuned before (written by the
+ *                                library: shape signature, work order,
+ *                                threshold, -1 for none)
+ * Batches tuned from then on are appended to the file.  Without a call, the
+ * file the environment variable FTGEMM_TUNE_TABLE names (if any) is read at
+ * first use.  Errors: the file cannot be read or has a malformed line
+ * (position 1; the table is left unchanged). */
+ftgemm_status ftgemm_load_tune_table(const char *path);
 
 /* Arm the fault plan (test hook): it applies to every following call until
  * replaced; n == 0 clears it.  The plan is copied. */

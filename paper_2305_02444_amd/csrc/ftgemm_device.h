@@ -34,7 +34,7 @@ struct GemmArgs {
     double alpha, beta;                 // alpha already carries FP8 scales
     int32_t problem;
     int32_t tiles_m, tiles_n;           // verification grid
-    int32_t pad0;
+    int32_t tile_rows;                  // rows of its tiles (low-precision batches: 128 or 256)
     int64_t k_base;                     // first inner index (split-k slices)
     // fault tolerance (ignored by the plain kernels)
     DevCounters *counters;

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -63,13 +64,112 @@ struct DeviceWs {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uint64_t> graph_key;
-    std::unordered_map<uint64_t, int> tuned;  // batch signature -> schedule
     int cus = 0;
 };
 
 constexpr int kAuxWords = 16;
 
 std::unordered_map<int, DeviceWs> g_ws;
+
+// The tuning table.  Its text form, one entry per line ('#' starts a
+// comment):
+//   tile <dtype> <abft> <rows>       single low-precision calls of that
+//                                    dtype (1 BF16, 2 FP8) and mode take
+//                                    tiles of 128 or 256 rows
+//   batch_mstar <m>                  in low-precision batches, problems with
+//                                    at least m rows take 256-row tiles (the
+//                                    threshold is then not tuned; -1: tuned)
+//   batch <signature> <schedule> <m> a batch tuned before: its signature
+//                                    (hex), work order and threshold
+// It is read from the file FTGEMM_TUNE_TABLE names (when set) at the first
+// call that needs it, or from the file ftgemm_load_tune_table names; batches
+// tuned afterwards are appended to that file.
+constexpr int64_t kNoBigTiles = INT64_MAX;
+struct TuneTable {
+    bool loaded = false;
+    std::string path;             // where tuned batches are appended ("": nowhere)
+    int single_rows[3][3] = {};   // [dtype][abft], 0: the default choice
+    int64_t batch_mstar = -1;     // forced threshold, -1: tuned
+    std::unordered_map<uint64_t, std::pair<int, int64_t>> batches;
+};
+std::mutex g_tune_mu;
+TuneTable g_tune;
+
+// Parse a table file into t; false when the file cannot be read or a line
+// is malformed.
+bool parse_table(const char *path, TuneTable &t)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool ok = true;
+    while (std::fgets(line, sizeof line, f)) {
+        if (char *c = std::strchr(line, '#')) *c = 0;
+        char key[32];
+        if (std::sscanf(line, "%31s", key) != 1) continue;
+        if (!std::strcmp(key, "tile")) {
+            int dt, ab, rows;
+            if (std::sscanf(line, "%*s %d %d %d", &dt, &ab, &rows) != 3 || dt < 1 || dt > 2 ||
+                ab < 0 || ab > 2 || (rows != 128 && rows != 256)) {
+                ok = false;
+                break;
+            }
+            t.single_rows[dt][ab] = rows;
+        } else if (!std::strcmp(key, "batch_mstar")) {
+            long long v;
+            if (std::sscanf(line, "%*s %lld", &v) != 1) { ok = false; break; }
+            t.batch_mstar = v < 0 ? -1 : (int64_t)v;
+        } else if (!std::strcmp(key, "batch")) {
+            unsigned long long sig;
+            int sched;
+            long long mstar;
+            if (std::sscanf(line, "%*s %llx %d %lld", &sig, &sched, &mstar) != 3 || sched < 0 ||
+                sched > 2) {
+                ok = false;
+                break;
+            }
+            t.batches[(uint64_t)sig] = {sched, mstar < 0 ? kNoBigTiles : (int64_t)mstar};
+        } else {
+            ok = false;
+            break;
+        }
+    }
+    std::fclose(f);
+    return ok;
+}
+
+// The table, read from FTGEMM_TUNE_TABLE on first use.  Called with
+// g_tune_mu held.
+TuneTable &tune_table()
+{
+    if (!g_tune.loaded) {
+        g_tune.loaded = true;
+        if (const char *e = std::getenv("FTGEMM_TUNE_TABLE")) {
+            g_tune.path = e;
+            TuneTable t;
+            if (parse_table(e, t)) {
+                t.loaded = true;
+                t.path = e;
+                g_tune = t;
+            }
+        }
+    }
+    return g_tune;
+}
+
+// Record a tuned batch in the table and append it to the table's file.
+void remember_batch(uint64_t sig, int sched, int64_t mstar)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    TuneTable &t = tune_table();
+    t.batches[sig] = {sched, mstar};
+    if (t.path.empty()) return;
+    if (FILE *f = std::fopen(t.path.c_str(), "a")) {
+        std::fprintf(f, "batch %016llx %d %lld\n", (unsigned long long)sig, sched,
+                     mstar == kNoBigTiles ? -1LL : (long long)mstar);
+        std::fclose(f);
+    }
+}
 
 ftgemm_status invalid(int pos)
 {
@@ -295,6 +395,15 @@ int check_windows(const ftgemm_gemm_desc &d)
     return 0;
 }
 
+// Tile of a single low-precision call: the default choice, or the table's.
+void lp_tiling(const ftgemm_gemm_desc &d, int *tm, int *tn, int *bk)
+{
+    ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, tm, tn, bk);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const int rows = tune_table().single_rows[d.dtype][d.abft < 3 ? d.abft : 0];
+    if (rows) *tm = rows;
+}
+
 // Argument checks in BLAS order; returns 0 or the 1-based position.
 int check_args(const ftgemm_gemm_desc &d)
 {
@@ -341,6 +450,7 @@ GemmArgs base_args(const ftgemm_gemm_desc &d, int tm, int tn)
     g.problem = 0;
     g.tiles_m = (int32_t)((d.m + tm - 1) / tm);
     g.tiles_n = (int32_t)((d.n + tn - 1) / tn);
+    g.tile_rows = tm;
     g.k_base = 0;
     return g;
 }
@@ -564,7 +674,7 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
     if (d.dtype == FTGEMM_F64)
         ftg::tiling_f64(&tm, &tn, &bk);
     else
-        ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, &tm, &tn, &bk);
+        lp_tiling(d, &tm, &tn, &bk);
     GemmArgs g = base_args(d, tm, tn);
     const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
     // Low precision: the threshold norms in one pass before the product for
@@ -683,6 +793,7 @@ uint64_t fnv1a(uint64_t h, uint64_t v)
 
 struct BatchPlan {
     std::vector<ftg::WorkItem> items;
+    int rows = 128;  // tile rows of every item's problem, 0 when mixed
     int nqueues = 1;
     int32_t qbegin[ftg::kMaxQueues + 1] = {};
 };
@@ -703,6 +814,9 @@ void plan_items(const std::vector<ftg::GemmArgs> &probs, const std::vector<int> 
                 plan->items.push_back(ftg::WorkItem{p, tm, tn, 0});
     };
     plan->items.clear();
+    plan->rows = live.empty() ? 128 : probs[live[0]].tile_rows;
+    for (int p : live)
+        if (probs[p].tile_rows != plan->rows) plan->rows = 0;
     if (sched != kLptPerXcd) {
         for (int p : order) emit(p);
         plan->nqueues = 1;
@@ -777,6 +891,7 @@ ftgemm_status upload_batch(DeviceWs &ws, const std::vector<ftg::GemmArgs> &probs
 ftg::BatchArgs batch_args(const DeviceWs &ws, const BatchPlan &plan)
 {
     ftg::BatchArgs b{};
+    b.rows = plan.rows;
     b.probs = ws.d_probs;
     b.items = ws.d_items;
     b.queue = ws.aux + 1;
@@ -800,6 +915,47 @@ ftgemm_status launch_batch(DeviceWs &ws, const ftgemm_gemm_desc &d0, int count,
         HIP_TRY(ftg::launch_lp_batched(b, d0.dtype == FTGEMM_FP8_E4M3, ta, tb, d0.abft != 0,
                                        ws.cus, stream));
     return FTGEMM_OK;
+}
+
+// Signature of a batch: its size, dtype, mode, transposes and every shape.
+uint64_t batch_signature(int32_t count, const ftgemm_gemm_desc *descs)
+{
+    const ftgemm_gemm_desc &d0 = descs[0];
+    uint64_t sig = 0xcbf29ce484222325ull;
+    sig = fnv1a(sig, (uint64_t)count);
+    sig = fnv1a(sig, (uint64_t)d0.dtype * 16 + (d0.abft ? 8 : 0) + d0.transA * 2 + d0.transB);
+    for (int32_t p = 0; p < count; ++p)
+        sig = fnv1a(fnv1a(fnv1a(sig, (uint64_t)descs[p].m), (uint64_t)descs[p].n),
+                    (uint64_t)descs[p].k);
+    return sig;
+}
+
+// Tile rows of each problem of a batch: low-precision problems with at least
+// mstar rows take 256-row tiles, the others (and every FP64 problem) 128.
+void set_tile_rows(std::vector<ftg::GemmArgs> &probs, const ftgemm_gemm_desc *descs, bool lp,
+                   int64_t mstar)
+{
+    for (size_t p = 0; p < probs.size(); ++p) {
+        const int rows = lp && descs[p].m >= mstar ? 256 : 128;
+        probs[p].tile_rows = rows;
+        probs[p].tiles_m = (int32_t)((descs[p].m + rows - 1) / rows);
+    }
+}
+
+// The tile rows each problem of a batch takes now: the threshold the table
+// fixes, else the one remembered for the batch, else 128 everywhere.
+void batch_rows(int32_t count, const ftgemm_gemm_desc *descs, int32_t *rows)
+{
+    const bool lp = descs[0].dtype != FTGEMM_F64;
+    int64_t mstar = kNoBigTiles;
+    {
+        std::lock_guard<std::mutex> tl(g_tune_mu);
+        TuneTable &t = tune_table();
+        auto it = t.batches.find(batch_signature(count, descs));
+        if (it != t.batches.end()) mstar = it->second.second;
+        if (t.batch_mstar >= 0) mstar = t.batch_mstar;
+    }
+    for (int32_t p = 0; p < count; ++p) rows[p] = lp && descs[p].m >= mstar ? 256 : 128;
 }
 
 ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_report *reps,
@@ -835,15 +991,15 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
         ftg::tiling_f64(&tm, &tn, &bk);
     else
         ftg::tiling_lp(d0.dtype == FTGEMM_FP8_E4M3, d0.abft, 0, 0, true, &tm, &tn, &bk);
+    const bool lp = d0.dtype != FTGEMM_F64;
     std::vector<ftg::GemmArgs> probs(count);
     std::vector<int> live;
-    uint64_t sig = 0xcbf29ce484222325ull;
-    sig = fnv1a(sig, (uint64_t)count);
-    sig = fnv1a(sig, (uint64_t)d0.dtype * 16 + (d0.abft ? 8 : 0) + d0.transA * 2 + d0.transB);
+    const uint64_t sig = batch_signature(count, descs);
     bool write_only = true;
     for (int32_t p = 0; p < count; ++p) {
         const ftgemm_gemm_desc &d = descs[p];
         ftg::GemmArgs g = base_args(d, tm, tn);
+        g.tile_rows = tm;
         g.problem = p;
         g.counters = ws->counters + p;
         g.records = ws->records;
@@ -853,7 +1009,6 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
         g.plan = ws->plan;
         g.echo = ws->echo;
         probs[p] = g;
-        sig = fnv1a(fnv1a(fnv1a(sig, (uint64_t)d.m), (uint64_t)d.n), (uint64_t)d.k);
         if (d.m == 0 || d.n == 0) continue;
         if (d.alpha == 0.0 || d.k == 0) {
             // no product: C <- beta C, outside the persistent launch
@@ -866,19 +1021,37 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
         live.push_back(p);
     }
 
-    // schedule: remembered, tuned now, or the default
+    // tile rows and work order: remembered (or in the table), tuned now, or
+    // the defaults (128-row tiles, cost-ordered single queue)
     int sched = kLptOneQueue;
-    auto known = ws->tuned.find(sig);
+    int64_t mstar = kNoBigTiles;
+    bool known = false;
+    int64_t forced = -1;
+    {
+        std::lock_guard<std::mutex> tl(g_tune_mu);
+        TuneTable &t = tune_table();
+        auto it = t.batches.find(sig);
+        if (it != t.batches.end()) {
+            sched = it->second.first;
+            mstar = it->second.second;
+            known = true;
+        }
+        forced = t.batch_mstar;
+    }
+    if (!lp) mstar = kNoBigTiles;
+    else if (forced >= 0) mstar = forced;
     static const bool no_tune = std::getenv("FTGEMM_NO_TUNE") != nullptr;
     BatchPlan plan;
-    if (known != ws->tuned.end()) {
-        sched = known->second;
-    } else if (write_only && !no_tune && !live.empty()) {
+    if (!known && write_only && !no_tune && !live.empty()) {
+        // Trials on the batch itself (C is write-only): one untimed launch,
+        // then two timed ones.  First the threshold from which a
+        // low-precision problem takes 256-row tiles (unless the table fixes
+        // it), with the default order; then the order.
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
-        float best = 0.0f;
-        for (int c = 0; c < kNumSchedules; ++c) {
+        auto trial = [&](int c, int64_t ms_rows, float *out) -> ftgemm_status {
+            set_tile_rows(probs, descs, lp, ms_rows);
             plan_items(probs, live, c, &plan);
             if (ftgemm_status st = upload_batch(*ws, probs, plan, stream)) return st;
             if (ftgemm_status st = launch_batch(*ws, d0, count, plan, stream)) return st;
@@ -887,8 +1060,25 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
                 if (ftgemm_status st = launch_batch(*ws, d0, count, plan, stream)) return st;
             HIP_TRY(hipEventRecord(e1, stream));
             HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipEventElapsedTime(out, e0, e1));
+            return FTGEMM_OK;
+        };
+        if (lp && forced < 0) {
+            const int64_t cand[4] = {kNoBigTiles, 1024, 512, 256};
+            float best = 0.0f;
+            for (int c = 0; c < 4; ++c) {
+                float ms = 0.0f;
+                if (ftgemm_status st = trial(kLptOneQueue, cand[c], &ms)) return st;
+                if (c == 0 || ms < best) {
+                    best = ms;
+                    mstar = cand[c];
+                }
+            }
+        }
+        float best = 0.0f;
+        for (int c = 0; c < kNumSchedules; ++c) {
             float ms = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ftgemm_status st = trial(c, mstar, &ms)) return st;
             if (c == 0 || ms < best) {
                 best = ms;
                 sched = c;
@@ -896,8 +1086,9 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
         }
         HIP_TRY(hipEventDestroy(e0));
         HIP_TRY(hipEventDestroy(e1));
-        ws->tuned[sig] = sched;
+        remember_batch(sig, sched, mstar);
     }
+    set_tile_rows(probs, descs, lp, mstar);
     plan_items(probs, live, sched, &plan);
     if (ftgemm_status st = upload_batch(*ws, probs, plan, stream)) return st;
 
@@ -907,6 +1098,7 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
         (uint64_t)count, (uint64_t)(d0.abft ? ws->nplan : 0), (uint64_t)(uintptr_t)ws->d_probs,
         (uint64_t)(uintptr_t)ws->d_items, (uint64_t)(uintptr_t)ws->counters,
         (uint64_t)(uintptr_t)ws->echo, (uint64_t)(uintptr_t)ws->aux, (uint64_t)plan.nqueues,
+        (uint64_t)plan.rows,
         (uint64_t)ws->cus, (uint64_t)plan.items.size()};
     for (int q = 0; q <= plan.nqueues; ++q) key.push_back((uint64_t)plan.qbegin[q]);
     if (!ws->exec || key != ws->graph_key) {
@@ -1013,7 +1205,7 @@ ftgemm_status run_noalloc(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStre
     if (d.dtype == FTGEMM_F64)
         ftg::tiling_f64(&tm, &tn, &bk);
     else
-        ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, &tm, &tn, &bk);
+        lp_tiling(d, &tm, &tn, &bk);
     GemmArgs g = base_args(d, tm, tn);
     const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
     g.counters = counters;
@@ -1143,7 +1335,13 @@ ftgemm_status ftgemm_query_tiling(ftgemm_dtype dtype, int64_t m, int64_t n, int6
         ftg::tiling_f64(&a, &b, &c);
         s = choose_split(m, n, k, a, b, c, &slice_k);
     } else {
-        ftg::tiling_lp(dtype == FTGEMM_FP8_E4M3, 1, m, n, false, &a, &b, &c);
+        ftgemm_gemm_desc d{};
+        d.dtype = dtype;
+        d.abft = 1;
+        d.m = m;
+        d.n = n;
+        d.k = k;
+        lp_tiling(d, &a, &b, &c);
     }
     *tm = a;
     *tn = b;
@@ -1172,12 +1370,38 @@ ftgemm_status ftgemm_query_tiling_ex(const ftgemm_gemm_desc *desc, int32_t *tm, 
         ftg::tiling_f64(&a, &b, &c);
         s = choose_split(d.m, d.n, d.k, a, b, c, &slice_k);
     } else {
-        ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, &a, &b, &c);
+        lp_tiling(d, &a, &b, &c);
     }
     *tm = a;
     *tn = b;
     *bk = c;
     *split_k = s;
+    return FTGEMM_OK;
+}
+
+ftgemm_status ftgemm_load_tune_table(const char *path)
+{
+    t_last_invalid = 0;
+    TuneTable t;
+    t.loaded = true;
+    if (path) {
+        if (!parse_table(path, t)) return invalid(1);
+        t.path = path;
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune = t;
+    return FTGEMM_OK;
+}
+
+ftgemm_status ftgemm_batch_tiling(int32_t count, const ftgemm_gemm_desc *problems,
+                                  int32_t *tile_rows)
+{
+    t_last_invalid = 0;
+    if (count < 0) return invalid(1);
+    if (count > 0 && !problems) return invalid(2);
+    if (count > 0 && !tile_rows) return invalid(3);
+    if (count == 0) return FTGEMM_OK;
+    batch_rows(count, problems, tile_rows);
     return FTGEMM_OK;
 }
 

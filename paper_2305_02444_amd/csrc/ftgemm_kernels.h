@@ -108,6 +108,8 @@ struct BatchArgs {
     unsigned int *queue;     // per queue: next item to hand out; zero at launch
     int32_t nqueues;         // 1, or one per XCD
     int32_t qbegin[kMaxQueues + 1];  // queue q hands out items [qbegin[q], qbegin[q + 1])
+    int32_t rows;            // low precision: 128 or 256 when every problem's tiles
+                             // have that many rows, 0 when mixed
 };
 hipError_t launch_f64_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int grid,
                               hipStream_t stream);

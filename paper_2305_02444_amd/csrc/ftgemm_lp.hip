@@ -1380,16 +1380,27 @@ __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
     tile<FP8, TA, TB, ABFT, BM, ONE, PRE>(g, tm_, tn_, sm);
 }
 
-// Tile rows of the batched kernel (problems of mixed, often small, shapes).
+// Default tile rows of the batched kernel (problems of mixed, often small,
+// shapes); each problem may take 256-row tiles instead (GemmArgs::tile_rows,
+// chosen per problem by the batch's tuning).
 constexpr int kBatchBM = 128;
 
 // Persistent batched kernel: workgroup w starts on queue w mod nqueues (with
 // one queue per XCD, the XCD it runs on) and moves on to the others when it
-// runs dry; every workgroup leaves once all queues are drained.
-template <bool FP8, bool TA, bool TB, bool ABFT>
+// runs dry; every workgroup leaves once all queues are drained.  A work
+// item runs the 128- or the 256-row tile as its problem says; the two share
+// one LDS area.
+// ROWS: 128 or 256 when every problem of the batch takes tiles of that
+// many rows, 0 when they are mixed (the kernel then holds both tile codes,
+// and the registers of the larger).
+template <bool FP8, bool TA, bool TB, bool ABFT, int ROWS>
 __global__ __launch_bounds__(NT, 2) void batched_kernel(BatchArgs b)
 {
-    __shared__ Smem<kBatchBM> sm;
+    constexpr size_t kBytes = ROWS == 128 ? sizeof(Smem<128>)
+                              : ROWS == 256 ? sizeof(Smem<256>)
+                              : sizeof(Smem<256>) > sizeof(Smem<128>) ? sizeof(Smem<256>)
+                                                                      : sizeof(Smem<128>);
+    __shared__ __align__(16) unsigned char smem[kBytes];
     __shared__ int next;
     const int first = (int)(blockIdx.x % (unsigned)b.nqueues);
     for (int qi = 0; qi < b.nqueues; ++qi) {
@@ -1403,18 +1414,23 @@ __global__ __launch_bounds__(NT, 2) void batched_kernel(BatchArgs b)
             if (it >= end) break;
             const WorkItem w = b.items[it];
             const GemmArgs g = b.probs[w.problem];
-            tile<FP8, TA, TB, ABFT, kBatchBM>(g, w.tile_m, w.tile_n, sm);
+            if (ROWS == 256 || (ROWS == 0 && g.tile_rows == 256))
+                tile<FP8, TA, TB, ABFT, 256>(g, w.tile_m, w.tile_n,
+                                             *reinterpret_cast<Smem<256> *>(smem));
+            else
+                tile<FP8, TA, TB, ABFT, kBatchBM>(g, w.tile_m, w.tile_n,
+                                                  *reinterpret_cast<Smem<kBatchBM> *>(smem));
             __syncthreads();
         }
     }
 }
 
-template <bool FP8>
-hipError_t launch_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int grid,
-                          hipStream_t stream)
+template <bool FP8, int ROWS>
+hipError_t launch_batched_rows(const BatchArgs &b, bool ta, bool tb, bool abft, int grid,
+                               hipStream_t stream)
 {
 #define FTG_LP_BCASE(x, y, z) \
-    hipLaunchKernelGGL((batched_kernel<FP8, x, y, z>), dim3(grid), dim3(NT), 0, stream, b)
+    hipLaunchKernelGGL((batched_kernel<FP8, x, y, z, ROWS>), dim3(grid), dim3(NT), 0, stream, b)
     if (abft) {
         if (!ta && !tb) FTG_LP_BCASE(false, false, true);
         else if (!ta && tb) FTG_LP_BCASE(false, true, true);
@@ -1428,6 +1444,15 @@ hipError_t launch_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int g
     }
 #undef FTG_LP_BCASE
     return hipGetLastError();
+}
+
+template <bool FP8>
+hipError_t launch_batched(const BatchArgs &b, bool ta, bool tb, bool abft, int grid,
+                          hipStream_t stream)
+{
+    if (b.rows == 128) return launch_batched_rows<FP8, 128>(b, ta, tb, abft, grid, stream);
+    if (b.rows == 256) return launch_batched_rows<FP8, 256>(b, ta, tb, abft, grid, stream);
+    return launch_batched_rows<FP8, 0>(b, ta, tb, abft, grid, stream);
 }
 
 template <bool FP8, int BM>

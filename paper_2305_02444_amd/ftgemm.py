@@ -90,6 +90,10 @@ def lib():
                                   vp, i64, C.POINTER(Report), vp]
         L.ftgemm_gemm_ex.restype = C.c_int
         L.ftgemm_gemm_ex.argtypes = [C.POINTER(GemmDesc), C.POINTER(Report), vp]
+        L.ftgemm_batch_tiling.restype = C.c_int
+        L.ftgemm_batch_tiling.argtypes = [C.c_int32, C.POINTER(GemmDesc), C.POINTER(C.c_int32)]
+        L.ftgemm_load_tune_table.restype = C.c_int
+        L.ftgemm_load_tune_table.argtypes = [C.c_char_p]
         L.ftgemm_gemm_ex_noalloc.restype = C.c_int
         L.ftgemm_gemm_ex_noalloc.argtypes = [C.POINTER(GemmDesc), C.POINTER(Report), vp]
         for name in ("ftgemm_gemm_batched", "ftgemm_gemm_batched_loop"):
@@ -259,6 +263,20 @@ def gemm(A, B, Cm, alpha=1.0, beta=0.0, transA=False, transB=False, report=None,
 def gemm_ex(desc: GemmDesc, report=None, stream=None):
     rp = C.byref(report.rep) if report is not None else None
     _check(lib().ftgemm_gemm_ex(C.byref(desc), rp, _stream(stream)), "ftgemm_gemm_ex")
+
+
+def batch_tiling(descs):
+    """Rows of the tiles each problem takes in gemm_batched now."""
+    arr = (GemmDesc * len(descs))(*descs)
+    rows = (C.c_int32 * max(len(descs), 1))()
+    _check(lib().ftgemm_batch_tiling(len(descs), arr, rows), "ftgemm_batch_tiling")
+    return [int(r) for r in rows[:len(descs)]]
+
+
+def load_tune_table(path=None):
+    """Replace the tuning table with the file at path (None: empty)."""
+    _check(lib().ftgemm_load_tune_table(path.encode() if path else None),
+           "ftgemm_load_tune_table")
 
 
 def gemm_ex_noalloc(desc: GemmDesc, report=None, stream=None):

@@ -217,3 +217,41 @@ def test_operand_windows_wider_than_the_loaders_reach_are_refused():
               desc(F.BF16, 1, 0, 512, 512, 512, ok_bf, 512)):
         d.alpha, d.beta = 0.0, 1.0
         assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.OK
+
+
+def test_tuning_table(tmp_path):
+    """The tuning table on the host: a file with a malformed line is refused
+    (position 1) and leaves the table as it was; 'tile' lines force the
+    tiles of single low-precision calls; 'batch_mstar' fixes which batched
+    low-precision problems take 256-row tiles; FP64 keeps 128 x 128; an
+    empty table restores the defaults."""
+    bad = tmp_path / "bad.tune"
+    bad.write_text("tile 1 1 200\n")
+    with pytest.raises(F.FTGemmError):
+        F.load_tune_table(str(bad))
+    assert F.lib().ftgemm_last_invalid_arg() == 1
+    with pytest.raises(F.FTGemmError):
+        F.load_tune_table(str(tmp_path / "missing.tune"))
+    assert F.query_tiling_ex(F.BF16, 8192, 8192, 8192)[:2] == (256, 128)
+    good = tmp_path / "good.tune"
+    good.write_text("# comment\ntile 1 1 128\ntile 2 0 128   # plain FP8 on 128 rows\n"
+                    "batch_mstar 512\n")
+    F.load_tune_table(str(good))
+    try:
+        assert F.query_tiling_ex(F.BF16, 8192, 8192, 8192)[:2] == (128, 128)
+        assert F.query_tiling(F.BF16, 8192, 8192, 8192)[:2] == (128, 128)
+        assert F.query_tiling_ex(F.FP8_E4M3, 8192, 8192, 8192, abft=0)[:2] == (128, 128)
+        assert F.query_tiling_ex(F.BF16, 8192, 8192, 8192, abft=2)[:2] == (256, 128)
+        descs = []
+        for m in (100, 511, 512, 2000):
+            d = F.GemmDesc()
+            d.dtype, d.m, d.n, d.k = F.BF16, m, 64, 64
+            descs.append(d)
+        assert F.batch_tiling(descs) == [128, 128, 256, 256]
+        for d in descs:
+            d.dtype = F.F64
+        assert F.batch_tiling(descs) == [128] * 4
+    finally:
+        F.load_tune_table(None)
+    assert F.query_tiling_ex(F.BF16, 8192, 8192, 8192)[:2] == (256, 128)
+    assert F.query_tiling_ex(F.FP8_E4M3, 8192, 8192, 8192, abft=0)[:2] == (256, 128)

@@ -1,11 +1,19 @@
 """Batched fault-tolerant GEMM (one persistent launch replayed from a HIP
-graph, schedule picked by the library's autotuner) against the CPU oracle,
-problem by problem, and against the loop of per-problem launches.
+graph, work order and low-precision tile rows picked by the library's
+autotuner) against the CPU oracle, problem by problem, and against the loop
+of per-problem launches.
 
 Each problem has its own checksums, report and faults (the plan's `problem`
 field is the index in the batch).  Tolerances as for single calls: 1e-12
 normwise for FP64, 1e-5 for BF16.  The batched and the per-problem paths run
-the same tile code, so their outputs must be bitwise equal."""
+the same tile code, so their outputs must be bitwise equal.  The oracle
+takes each problem's tile rows from ftgemm_batch_tiling; tests that compare
+with single launches (whose tiles follow the single-call rule) keep every
+problem on 128-row tiles through the tuning table."""
+import contextlib
+import os
+import tempfile
+
 import numpy as np
 import pytest
 
@@ -49,16 +57,34 @@ def _batch(shapes, dtype, wid, alpha=1.0, beta=0.0):
     return host, dev, descs
 
 
-def _plan(shapes, wid, dtype, lo_exp):
-    """Truncated Poisson(1) faults per problem (at most 3, one per tile),
-    additive, 10^U(lo, 6) times the typical |C|."""
+@contextlib.contextmanager
+def _table(text):
+    """A tuning table with these lines for the duration (then an empty one)."""
+    fd, path = tempfile.mkstemp(suffix=".tune")
+    with os.fdopen(fd, "w") as fh:
+        fh.write(text)
+    try:
+        F.load_tune_table(path)
+        yield path
+    finally:
+        F.load_tune_table(None)
+        os.unlink(path)
+
+
+NO_BIG_TILES = "batch_mstar 1000000000\n"
+
+
+def _plan(shapes, wid, dtype, lo_exp, rows=None):
+    """Truncated Poisson(1) faults per problem (at most 3, one per tile of
+    rows[p] x 128), additive, 10^U(lo, 6) times the typical |C|."""
     g = synth.rng(wid, 0, synth.STREAM_PLAN)
     plan = []
     for p, (m, n, k) in enumerate(shapes):
-        tiles = (-(-m // 128)) * (-(-n // 128))
+        tm = rows[p] if rows else 128
+        tiles = (-(-m // tm)) * (-(-n // 128))
         cnt = min(synth.truncated_poisson(g, 1.0, 3), tiles if k > 0 else 0)
         sigma = np.sqrt(k / 9.0)
-        for f in synth.additive_plan(g, m, n, k, 128, 128, cnt,
+        for f in synth.additive_plan(g, m, n, k, tm, 128, cnt,
                                      synth.log_magnitude(sigma, lo_exp, 6.0)):
             f.problem = p
             plan.append(f)
@@ -71,11 +97,11 @@ def _outputs(dev, dtype):
     return [np.asfortranarray(t[2].cpu().numpy().astype(np.float64)) for t in dev]
 
 
-def _check_problem(p, got, host, shapes, plan, rep, dtype, alpha, beta, tiles=None):
+def _check_problem(p, got, host, shapes, plan, rep, dtype, alpha, beta, tiles=None, tm=128):
     dA, dB, Cin = host[p]
     m, n, k = shapes[p]
     pp = [f for f in plan if f.problem == p]
-    ref = O.default().ftgemm(dA, dB, Cin, alpha, beta, tm=128, tn=128,
+    ref = O.default().ftgemm(dA, dB, Cin, alpha, beta, tm=tm, tn=128,
                              bk=F.query_tiling(dtype, m, n, k)[2],
                              acc_bits=64 if dtype == F.F64 else 32, injections=to_oracle(pp),
                              tiles=tiles, mma=lp_mma(dtype))
@@ -85,14 +111,14 @@ def _check_problem(p, got, host, shapes, plan, rep, dtype, alpha, beta, tiles=No
         corrected = {(r["tile_m"], r["tile_n"]) for r in rep.records
                      if r["kind"] == F.KIND_CORRECTED}
         for i, j in np.argwhere(mask & (ref.raw != ref.C)):
-            if (i // 128, j // 128) in corrected:
+            if (i // tm, j // 128) in corrected:
                 assert abs(got[i, j] - ref.C[i, j]) <= \
-                    rebuild_bound(dA, dB, False, False, alpha, 128, 128, got, ref.C, i, j)
+                    rebuild_bound(dA, dB, False, False, alpha, tm, 128, got, ref.C, i, j)
                 mask[i, j] = False
     assert normwise(got[mask], ref.C[mask]) <= TOL[dtype], p
     recs = rep.records
     if tiles is not None:
-        tm_ = -(-m // 128)
+        tm_ = -(-m // tm)
         keep = set(int(t) for t in tiles)
         recs = [r for r in recs if r["tile_m"] + r["tile_n"] * tm_ in keep]
     assert flagged(recs) == flagged(ref.records), p
@@ -110,7 +136,9 @@ def test_small_batch_matches_oracle_and_loop(dtype):
     host, dev, descs = _batch(shapes, dtype, 60)
     F.set_fault_plan(plan)
     reps = [F.ReportBuffer() for _ in shapes]
-    F.gemm_batched(descs, reps)
+    with _table(NO_BIG_TILES):
+        assert F.batch_tiling(descs) == [128] * len(shapes)
+        F.gemm_batched(descs, reps)
     got = _outputs(dev, dtype)
     views = [r.view() for r in reps]
     for p in range(len(shapes)):
@@ -148,7 +176,8 @@ def test_batch_several_errors_per_tile(dtype):
     host, dev, descs = _batch(shapes, dtype, 65, alpha=1.0, beta=0.0)
     F.set_fault_plan(plan)
     reps = [F.ReportBuffer() for _ in shapes]
-    F.gemm_batched(descs, reps)
+    with _table(NO_BIG_TILES):
+        F.gemm_batched(descs, reps)
     got = _outputs(dev, dtype)
     host2, dev2, descs2 = _batch(shapes, dtype, 65, alpha=1.0, beta=0.0)
     F.gemm_batched(descs2, [F.ReportBuffer() for _ in shapes], loop=True)
@@ -221,8 +250,15 @@ def test_c5_512_problems(dtype):
     and rebuilt in its own problem; the oracle checks every faulty tile and
     a sample of whole problems."""
     shapes = synth.batched_shapes(70, dtype, 512)
-    plan = _plan(shapes, 70 + dtype, dtype, 1.0)
     host, dev, descs = _batch(shapes, dtype, 70)
+    # the first call tunes the work order and (BF16) the tile rows; the
+    # faults are then placed one per tile of each problem's chosen tiles
+    F.clear_fault_plan()
+    F.gemm_batched(descs)
+    rows = F.batch_tiling(descs)
+    assert set(rows) <= {128, 256} and (dtype != F.F64 or set(rows) == {128})
+    say("tile rows chosen: %d of 512 problems on 256-row tiles" % rows.count(256))
+    plan = _plan(shapes, 70 + dtype, dtype, 1.0, rows)
     F.set_fault_plan(plan)
     reps = [F.ReportBuffer() for _ in shapes]
     F.gemm_batched(descs, reps)
@@ -235,10 +271,48 @@ def test_c5_512_problems(dtype):
         assert v.corrected == len(want) and v.detected == len(want), p
     small = sorted(range(512), key=lambda p: shapes[p][0] * shapes[p][1] * shapes[p][2])[:6]
     for p in small:
-        _check_problem(p, got[p], host, shapes, plan, views[p], dtype, 1.0, 0.0)
-    faulty = sorted({f.problem for f in plan})[:12]
+        _check_problem(p, got[p], host, shapes, plan, views[p], dtype, 1.0, 0.0, tm=rows[p])
+    faulty = sorted({f.problem for f in plan})
+    # every faulty problem on 256-row tiles (up to 6), then others, up to 12
+    faulty = ([p for p in faulty if rows[p] == 256][:6] +
+              [p for p in faulty if rows[p] == 128])[:12]
     for p in faulty:
         m, n, k = shapes[p]
-        tm_ = -(-m // 128)
-        tiles = sorted({(f.row // 128) + (f.col // 128) * tm_ for f in plan if f.problem == p})
-        _check_problem(p, got[p], host, shapes, plan, views[p], dtype, 1.0, 0.0, tiles=tiles)
+        tm_ = -(-m // rows[p])
+        tiles = sorted({(f.row // rows[p]) + (f.col // 128) * tm_ for f in plan
+                        if f.problem == p})
+        _check_problem(p, got[p], host, shapes, plan, views[p], dtype, 1.0, 0.0, tiles=tiles,
+                       tm=rows[p])
+
+
+def test_batch_tile_rows_per_problem():
+    """BF16 problems of at least 256 rows on 256-row tiles and the others on
+    128-row tiles, in one persistent launch (the table fixes the threshold):
+    ragged shapes, faults one per tile of each problem's tiles, every
+    problem checked against the oracle on its own tiles; the checksum-free
+    batch writes the same bits."""
+    dtype = F.BF16
+    shapes = [(300, 200, 150), (255, 130, 64), (256, 128, 64), (600, 300, 333), (100, 500, 70),
+              (513, 129, 257)]
+    host, dev, descs = _batch(shapes, dtype, 66)
+    with _table("batch_mstar 256\n"):
+        rows = F.batch_tiling(descs)
+        assert rows == [256, 128, 256, 256, 128, 256]
+        plan = _plan(shapes, 66, dtype, 1.0, rows)
+        F.set_fault_plan(plan)
+        reps = [F.ReportBuffer() for _ in shapes]
+        F.gemm_batched(descs, reps)
+        got = _outputs(dev, dtype)
+        F.clear_fault_plan()
+        views = [r.view() for r in reps]
+        for p in range(len(shapes)):
+            _check_problem(p, got[p], host, shapes, plan, views[p], dtype, 1.0, 0.0, tm=rows[p])
+        assert sum(v.corrected for v in views) == len(plan) > 0
+        plain = [F.make_desc(t[0], t[1], t[2], 1.0, 0.0, abft=False, dtype=dtype) for t in dev]
+        F.gemm_batched(plain)
+        got2 = _outputs(dev, dtype)
+    for p in range(len(shapes)):
+        clean = np.ones(got[p].shape, dtype=bool)
+        for r in views[p].records:
+            clean[r["row"], r["col"]] = False
+        assert np.array_equal(got[p][clean], got2[p][clean]), p
