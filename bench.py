@@ -6,7 +6,7 @@ kernel with every checksum operation compiled out, at 8192^3 in FP64 (the
 headline) and BF16 / FP8 (extra legs), with and without injected faults.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
-    python bench.py --profile {f64,f64-unfused,bf16,fp8,copy}   (for rocprofv3 passes)
+    python bench.py --profile KIND   (a short workload for rocprofv3 passes; see profile_run)
 
 A step is one full fault-tolerant GEMM call C = alpha*A*B + beta*C
 (alpha = beta = 1, inputs uniform on [-1, 1], column-major N/N) on inputs
@@ -262,7 +262,8 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[name],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK[name], 4),
                      "traffic": read_traffic("ftgemm_%s_8192_counters.txt" % name,
-                                             ["ftgemm_lp.hip", "ftgemm_device.h"])
+                                             ["ftgemm_lp.hip", "ftgemm_norms.hip",
+                                              "ftgemm_device.h"])
                      if size == 8192 else None},
         "injected": {"faults_per_call": len(plan), "kind": "FP32 exponent bit flip",
                      "tflops": round(flops / (t_inj * 1e-3) / 1e12, 3),
@@ -395,11 +396,20 @@ def batched_leg(torch, F, synth, np, dtype, steps, warmup):
     return out
 
 
+PROFILE_KINDS = ["f64", "f64-plain", "f64-unfused", "bf16", "bf16-plain", "bf16-fused",
+                 "fp8", "fp8-plain", "fp8-plain-128", "fp8-fused", "copy"]
+
+
 def profile_run(kind, size, calls=3):
-    """A short fixed workload for counter passes: `calls` fault-tolerant
-    GEMMs of one format at size^3 (alpha = beta = 1, no report), or, for
-    `copy`, device copies of a 512 MiB buffer (the scale of the traffic
-    counters)."""
+    """A short fixed workload for counter passes: `calls` GEMMs of one format
+    at size^3 (alpha = beta = 1, no report), or, for `copy`, device copies of
+    a 512 MiB buffer (the scale of the traffic counters).  Kinds: the
+    fault-tolerant call (f64, bf16, fp8), the same kernel with checksums
+    compiled out on its default tile (-plain) and, for FP8, on the
+    fault-tolerant call's 128-row tile (fp8-plain-128), the unfused FP64
+    mode, and the low-precision fault tolerance with every operand checksum
+    formed in the tiles from the staged operands (-fused: the entry point
+    that allocates nothing, which takes no pass before the product)."""
     import torch
     from paper_2305_02444_amd import ftgemm as F
     torch.cuda.set_device(0)
@@ -413,30 +423,39 @@ def profile_run(kind, size, calls=3):
         return
     m = n = k = size
     g = torch.Generator(device="cuda").manual_seed(5)
-    if kind in ("f64", "f64-unfused"):
+    base = kind.split("-")[0]
+    abft = {"plain": 0, "unfused": 3}.get(kind.split("-")[1], 1) if "-" in kind else 1
+    call = F.gemm_ex_noalloc if kind.endswith("-fused") else F.gemm_ex
+    if base == "f64":
         A = F.colmajor_empty(m, k, torch.float64)
         B = F.colmajor_empty(k, n, torch.float64)
         A.uniform_(-1, 1, generator=g)
         B.uniform_(-1, 1, generator=g)
         Cm = F.colmajor_empty(m, n, torch.float64).uniform_(-1, 1, generator=g)
-        d = F.make_desc(A, B, Cm, 1.0, 1.0, abft=3 if kind == "f64-unfused" else True)
+        d = F.make_desc(A, B, Cm, 1.0, 1.0, abft=abft)
     else:
-        dt = torch.bfloat16 if kind == "bf16" else torch.float8_e4m3fn
+        dt = torch.bfloat16 if base == "bf16" else torch.float8_e4m3fn
         A = F.colmajor_empty(m, k, torch.float32).normal_(generator=g)
         B = F.colmajor_empty(k, n, torch.float32).normal_(generator=g)
         scale = 1.0 if kind == "bf16" else 1.0 / 64.0
         A8, B8 = (A / scale).to(dt), (B / scale).to(dt)
         del A, B
         Cm = F.colmajor_empty(m, n, torch.float32).normal_(generator=g)
-        code = F.BF16 if kind == "bf16" else F.FP8_E4M3
-        if kind == "fp8":
+        code = F.BF16 if base == "bf16" else F.FP8_E4M3
+        if base == "fp8":
             A8, B8 = A8.view(torch.uint8), B8.view(torch.uint8)
-        d = F.make_desc(A8, B8, Cm, 1.0, 1.0, scaleA=scale, scaleB=scale, dtype=code)
+        d = F.make_desc(A8, B8, Cm, 1.0, 1.0, abft=abft, scaleA=scale, scaleB=scale, dtype=code)
     F.clear_fault_plan()
-    for _ in range(calls):
-        F.gemm_ex(d)
-    torch.cuda.synchronize()
-    print("%s fault-tolerant GEMM %d^3 x %d" % (kind, size, calls), flush=True)
+
+    def run():
+        for _ in range(calls):
+            call(d)
+        torch.cuda.synchronize()
+    if kind == "fp8-plain-128":
+        with_table(F, "tile %d 0 128\n" % F.FP8_E4M3, run)
+    else:
+        run()
+    print("%s GEMM %d^3 x %d" % (kind, size, calls), flush=True)
 
 
 def main():
@@ -449,7 +468,7 @@ def main():
     ap.add_argument("--no-low-precision", action="store_true")
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--profile", choices=["f64", "f64-unfused", "bf16", "fp8", "copy"])
+    ap.add_argument("--profile", choices=PROFILE_KINDS)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
