@@ -226,6 +226,16 @@ struct LpLoader {
     {
         if (kInner) {
             const __amdgpu_buffer_rsrc_t rs = rsrc(k0, o0);
+            if (k - k0 >= E::BK) {
+                // a full step (uniform): no chunk crosses the end of the
+                // inner dimension, so no per-chunk checks (whose masks
+                // would otherwise be held across the loop)
+#pragma unroll
+                for (int r = 0; r < kOuter; ++r)
+                    w[r] = __builtin_amdgcn_raw_buffer_load_b128(
+                        rs, (int)(uint32_t)((p0() + (int64_t)outer(r) * ld) * E::EB), 0, 0);
+                return;
+            }
             const int valid = (int)((k - k0) < E::BK ? (k - k0) : E::BK) - p0();
 #pragma unroll
             for (int r = 0; r < kOuter; ++r) {
