@@ -279,23 +279,35 @@ struct LpLoader {
                         set_col_dw(g, b, 1, (int)v[1]);
                     }
                 }
-                const int live = (int)(nouter - o0) - outer(8 * g);  // outer indices inside
-                if (live < 8) {
-                    // the tile's last rows: element by element (a chunk that
-                    // crosses the end of the matrix), zero past it
+            }
+            // Only the last tile along the outer index (a uniform test) can
+            // hold chunks that cross the end of the matrix; its other tiles
+            // skip the per-group checks, whose masks would otherwise be held
+            // across the loop.
+            if (nouter - o0 < OUTER) {
 #pragma unroll
-                    for (int b = 0; b < PG; ++b)
+                for (int g = 0; g < kGroups; ++g) {
+                    const uint32_t base =
+                        (uint32_t)((outer(8 * g) + (int64_t)p0() * ld) * E::EB);
+                    const int live = (int)(nouter - o0) - outer(8 * g);  // outer indices inside
+                    if (live < 8) {
+                        // the tile's last rows: element by element (a chunk
+                        // that crosses the end of the matrix), zero past it
 #pragma unroll
-                        for (int d = 0; d < 8 / PG; ++d) {
-                            unsigned v = 0;
+                        for (int b = 0; b < PG; ++b)
 #pragma unroll
-                            for (int e = 0; e < PG; ++e) {
-                                const int idx = d * PG + e;
-                                if (idx < live)
-                                    v |= load_elem(rs, base + b * col + idx * E::EB) << (8 * E::EB * e);
+                            for (int d = 0; d < 8 / PG; ++d) {
+                                unsigned v = 0;
+#pragma unroll
+                                for (int e = 0; e < PG; ++e) {
+                                    const int idx = d * PG + e;
+                                    if (idx < live)
+                                        v |= load_elem(rs, base + b * col + idx * E::EB)
+                                             << (8 * E::EB * e);
+                                }
+                                set_col_dw(g, b, d, (int)v);
                             }
-                            set_col_dw(g, b, d, (int)v);
-                        }
+                    }
                 }
             }
         }
