@@ -218,6 +218,58 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
             missed.append(change)
         elif kind == F.KIND_CHECKSUM_ONLY:
             one_side.append(change)
+    # Guard-banded flips (the acceptance test of the fault-tolerance claim):
+    # candidate flips of exponent and high fraction bits in distinct tiles;
+    # their output change comes from the echoes of one run, the thresholds
+    # of their entry's row and column from a probe run that plants unequal
+    # faults on both checksum entries (the tile then recomputes, and its
+    # record carries both thresholds); a flip is kept when its change is at
+    # least 4 times the larger threshold, or not finite.
+    need = -(-tiles // 64)
+    cand = synth.bitflip_plan(synth.rng(wid, size, synth.STREAM_PLAN + 7), m, n, k, tm, tn,
+                              min(4 * need, tiles))
+    F.set_fault_plan(cand)
+    rbc = F.ReportBuffer(record_capacity=len(cand) + 8, echo_capacity=len(cand))
+    dC.copy_(dC0)
+    F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype), report=rbc)
+    echoes = rbc.view().echoes
+    probe = []
+    for f in cand:
+        probe.append(synth.Fault(f.row, f.col, 0, synth.ADD, 1.0e6,
+                                 target=synth.TGT_ROW_CHECKSUM))
+        probe.append(synth.Fault(f.row, f.col, 0, synth.ADD, 3.0e6,
+                                 target=synth.TGT_COL_CHECKSUM))
+    F.set_fault_plan(probe)
+    rbp = F.ReportBuffer(record_capacity=len(cand) + 8, echo_capacity=len(probe))
+    dC.copy_(dC0)
+    F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype), report=rbp)
+    tau_of = {(r["tile_m"], r["tile_n"]): max(r["tau_row"], r["tau_col"])
+              for r in rbp.view().records}
+    accepted, band = [], 0
+    for f, e in zip(cand, echoes):
+        tau = tau_of.get((f.row // tm, f.col // tn))
+        change = abs(alpha_p * (e["after"] - e["before"]))
+        if tau is None or not e["applied"]:
+            continue
+        if not np.isfinite(e["after"]) or change >= 4.0 * tau:
+            if len(accepted) < need:
+                accepted.append(f)
+        else:
+            band += 1
+    F.set_fault_plan(accepted)
+    t_gb, _ = timed(torch, call(True), steps, warmup, reset)
+    rbg = F.ReportBuffer()
+    dC.copy_(dC0)
+    F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype), report=rbg)
+    gb = rbg.view()
+    F.clear_fault_plan()
+    guarded = {"faults_per_call": len(accepted), "candidates": len(cand),
+               "rejected_by_guard_band": band,
+               "kind": "FP32 bit flip (bits 19..30), guard-banded",
+               "tflops": round(flops / (t_gb * 1e-3) / 1e12, 3),
+               "overhead_pct": round(100.0 * (t_gb / t_plain - 1.0), 2),
+               "detected": int(gb.detected), "corrected": int(gb.corrected),
+               "recomputed": int(gb.recomputed), "checksum_only": int(gb.checksum_only)}
     # one-sided mode (column checksum only, tile recomputed on detection,
     # threshold norms from one pass over A and B)
     dC.copy_(dC0)
@@ -273,6 +325,7 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
                      "undetected_output_change": [float("%.4g" % d) for d in missed],
                      "one_side_output_change": [float("%.4g" % d) for d in one_side],
                      "median_threshold": float("%.4g" % taus[len(taus) // 2]) if taus else None},
+        "injected_guard_banded": guarded,
         "error_free_check": {"detected": int(clean.detected), "max_ratio": clean.max_ratio,
                              "tiles_verified": int(clean.tiles_verified)},
         "max_rel_err_vs_fp64": max(errs),
