@@ -34,6 +34,13 @@
  * neither place the faulty column nor tell a data fault from a checksum
  * fault.  Faults aimed at the row checksum have no entry to land on.
  *
+ * Weighted mode (weighted = 1; the ranked extension "weighted checksum
+ * vectors locate two errors"): each tile also carries a weighted row
+ * checksum per column, weights w_i = i + 1 over the tile's local rows.  A
+ * single error at local row r of column j shows as (r + 1) times the plain
+ * residual of column j on it, which locates the error without pairing
+ * residuals by size and confirms every correction (see ft_tile).
+ *
  * Pins (tests/test_oracle_*.py): the checksum identities e^T(AB) = (e^T A)B
  * and (AB)e = A(Be) bit-exactly on small-integer data; brute-force location
  * of single injected errors; bit-exact recovery of integer data; GEMM against
@@ -160,7 +167,7 @@ void oracle_gemm_entries(int ta, int tb, int64_t k, double alpha,
 /* ------------------------------------------------------------------------- */
 
 enum { INJ_ADD = 0, INJ_BITFLIP = 1 };
-enum { TGT_ACC = 0, TGT_ROW_CHECKSUM = 1, TGT_COL_CHECKSUM = 2 };
+enum { TGT_ACC = 0, TGT_ROW_CHECKSUM = 1, TGT_COL_CHECKSUM = 2, TGT_WEIGHTED_CHECKSUM = 3 };
 enum { KIND_CORRECTED = 1, KIND_CHECKSUM_ONLY = 2, KIND_RECOMPUTED = 3,
        KIND_UNCORRECTABLE = 4 };
 /* Largest number of elements rebuilt along one line of a tile. */
@@ -205,7 +212,8 @@ typedef struct {
     int32_t mma_group;         /* instruction's group sums (see threshold)  */
     int32_t one_sided;         /* 1: only the column checksum (one entry    */
                                /* per row), recompute on any disagreement   */
-    int32_t pad;
+    int32_t weighted;          /* 1: also a weighted row checksum per column */
+                               /* (weights i + 1), see ft_tile              */
     int64_t slice_k;           /* 0, or the inner length of each slice of a */
                                /* split inner dimension (see ft_tile_split) */
 } oracle_params;
@@ -226,6 +234,12 @@ static double flip_bit(double v, int bit, int acc_bits)
     u ^= (uint64_t)1u << bit;
     memcpy(&v, &u, 8);
     return v;
+}
+
+/* Unit roundoff of the accumulation: FP32 or FP64. */
+static double unit_roundoff(const oracle_params *P)
+{
+    return (P->acc_bits == 32) ? ldexp(1.0, -24) : ldexp(1.0, -53);
 }
 
 /* Rounding-error threshold of one checksum entry.
@@ -313,7 +327,7 @@ static void tile_encode(const oracle_params *P, const double *A, const double *B
                         int64_t w, double *Pr, double *Pc, double *tr, double *tc)
 {
     const int64_t k = P->k;
-    const double u = (P->acc_bits == 32) ? ldexp(1.0, -24) : ldexp(1.0, -53);
+    const double u = unit_roundoff(P);
     const double alpha = P->alpha, beta = P->beta;
     double *x = malloc(sizeof(double) * (k > 0 ? k : 1));
     double *y = malloc(sizeof(double) * (k > 0 ? k : 1));
@@ -413,6 +427,56 @@ static void tile_encode(const oracle_params *P, const double *A, const double *B
     free(x); free(y); free(nb); free(na); free(gc); free(gr);
 }
 
+/* Weighted row checksums of one tile (the weighted mode): with local row
+ * weights w_i = i + 1 (i = 0 .. h-1 within the tile),
+ *   Pw_j = alpha sum_p x'_p B(p, j) + beta sum_i w_i Cin(i, j),  x'_p = sum_i w_i A(i, p),
+ * and their thresholds: the row-checksum bound with A_I replaced by W A_I
+ * (W = diag(w)), x by x' and Cin(I, j) by W Cin(I, j). */
+static void tile_encode_weighted(const oracle_params *P, const double *A, const double *B,
+                                 const double *Cin, int64_t i0, int64_t j0, int64_t h,
+                                 int64_t w, double *Pw, double *tw)
+{
+    const int64_t k = P->k;
+    const double u = unit_roundoff(P);
+    const double alpha = P->alpha, beta = P->beta;
+    double *xw = malloc(sizeof(double) * (k > 0 ? k : 1));
+    for (int64_t p = 0; p < k; ++p) {
+        double s = 0.0;
+        for (int64_t ii = 0; ii < h; ++ii)
+            s += (double)(ii + 1) * opA(A, P->lda, P->ta, i0 + ii, p);
+        xw[p] = s;
+    }
+    double fwa = 0.0, nxw = 0.0, ma = 0.0;
+    for (int64_t ii = 0; ii < h; ++ii)
+        for (int64_t p = 0; p < k; ++p) {
+            const double a = (double)(ii + 1) * opA(A, P->lda, P->ta, i0 + ii, p);
+            fwa += a * a;
+            ma = fmax(ma, fabs(a));
+        }
+    for (int64_t p = 0; p < k; ++p) nxw += xw[p] * xw[p];
+    fwa = sqrt(fwa);
+    nxw = sqrt(nxw);
+    const double trunc = P->mma_grid * sqrt((double)(P->mma_group > 0 ? P->mma_group : 1));
+    for (int64_t jj = 0; jj < w; ++jj) {
+        double s = 0.0, c = 0.0, c2 = 0.0, nb = 0.0;
+        for (int64_t p = 0; p < k; ++p) {
+            const double b = opB(B, P->ldb, P->tb, p, j0 + jj);
+            s += xw[p] * b;
+            nb += b * b;
+        }
+        if (beta != 0.0)
+            for (int64_t ii = 0; ii < h; ++ii) {
+                const double cw = (double)(ii + 1) * Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+                c += cw;
+                c2 += cw * cw;
+            }
+        Pw[jj] = alpha * s + beta * c;
+        tw[jj] = threshold(P->lambda, u, k, h, alpha, sqrt(nb), fwa, nxw, beta, sqrt(c2)) +
+                 P->lambda * fabs(alpha) * trunc * sqrt((double)h) * ma * sqrt(nb);
+    }
+    free(xw);
+}
+
 /* Thresholds of one tile, exported for the fault planner's guard band. */
 void oracle_tile_thresholds(const oracle_params *P, const double *A, const double *B,
                             const double *Cin, int64_t tile_m, int64_t tile_n,
@@ -452,6 +516,9 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
     double *Pr = malloc(sizeof(double) * w), *Pc = malloc(sizeof(double) * h);
     double *Rr = malloc(sizeof(double) * w), *Rc = malloc(sizeof(double) * h);
     double *tr = malloc(sizeof(double) * w), *tc = malloc(sizeof(double) * h);
+    const int wt = P->weighted && !P->one_sided;
+    double *Pw = malloc(sizeof(double) * w), *tw = malloc(sizeof(double) * w);
+    double *dw = malloc(sizeof(double) * w);
 
     int recomputed = 0, produced = 0;
     int attempt_faults = 1;
@@ -459,6 +526,7 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
         /* Encoding (Section 2.2), then the planned faults on the encoded
          * checksums -- on the first attempt only. */
         tile_encode(P, A, B, Cin, i0, j0, h, w, Pr, Pc, tr, tc);
+        if (wt) tile_encode_weighted(P, A, B, Cin, i0, j0, h, w, Pw, tw);
 
         /* Faults aimed at the encoded checksums. */
         for (int64_t q = 0; attempt_faults && inj && q < ninj; ++q) {
@@ -475,6 +543,11 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
                 Pc[f->row - i0] = (f->mode == INJ_ADD) ? before + f->delta
                                                        : flip_bit(before, f->bit, 64);
                 if (echo) { echo[q].applied = 1; echo[q].before = before; echo[q].after = Pc[f->row - i0]; }
+            } else if (f->target == TGT_WEIGHTED_CHECKSUM && wt && f->row >= i0 &&
+                       f->row < i0 + h && f->col >= j0 && f->col < j0 + w) {
+                double before = Pw[f->col - j0];
+                Pw[f->col - j0] = before + f->delta;
+                if (echo) { echo[q].applied = 1; echo[q].before = before; echo[q].after = Pw[f->col - j0]; }
             }
         }
 
@@ -505,6 +578,13 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
             for (int64_t jj = 0; jj < w; ++jj)
                 s += out[ii + jj * h];
             Rc[ii] = s;
+        }
+        /* Weighted reference sums and their residuals. */
+        for (int64_t jj = 0; wt && jj < w; ++jj) {
+            double s = 0.0;
+            for (int64_t ii = 0; ii < h; ++ii)
+                s += (double)(ii + 1) * out[ii + jj * h];
+            dw[jj] = s - Pw[jj];
         }
 
         /* Verify.  The comparison is written so that NaN residuals flag. */
@@ -571,7 +651,13 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
             for (int64_t jj = 0; jj < w; ++jj)
                 if (jj != jbad) sc += out[ibad + jj * h];
             double fixed = Pr[jbad] - sr;
-            if (fabs(sc + fixed - Pc[ibad]) <= tc[ibad]) {
+            /* Weighted mode: a finite error at (ibad, jbad) shows as
+             * (ibad + 1) times its column residual on the weighted checksum. */
+            const double dcol = Rr[jbad] - Pr[jbad];
+            const int wok = !wt || !isfinite(dcol) || !isfinite(dw[jbad]) ||
+                fabs(dw[jbad] - (double)(ibad + 1) * dcol) <=
+                    tw[jbad] + (double)(ibad + 1) * tr[jbad];
+            if (wok && fabs(sc + fixed - Pc[ibad]) <= tc[ibad]) {
                 out[ibad + jbad * h] = fixed;
                 if (rec) { rec->kind = KIND_CORRECTED; rec->after = fixed; }
                 break;
@@ -595,7 +681,28 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
                 if (!(fabs(d) <= (by_row ? tr[x] : tc[x]))) sumd += d;
             }
             const double dl = by_row ? Rc[line] - Pc[line] : Rr[line] - Pr[line];
-            if (fabs(dl - sumd) <= (by_row ? tc[line] : tr[line])) {
+            /* Weighted mode: along a row, each crossing column x shows
+             * (line + 1) d_x on its weighted checksum; along a column, the
+             * column's weighted residual is the weighted sum of the rows'. */
+            int wok = 1;
+            if (wt && by_row) {
+                for (int64_t x = 0; x < len; ++x) {
+                    const double d = Rr[x] - Pr[x];
+                    if (fabs(d) <= tr[x]) continue;
+                    if (!(fabs(dw[x] - (double)(line + 1) * d) <=
+                          tw[x] + (double)(line + 1) * tr[x])) wok = 0;
+                }
+            } else if (wt) {
+                double sw = 0.0, tsum = tw[line];
+                for (int64_t x = 0; x < len; ++x) {
+                    const double d = Rc[x] - Pc[x];
+                    if (fabs(d) <= tc[x]) continue;
+                    sw += (double)(x + 1) * d;
+                    tsum += (double)(x + 1) * tc[x];
+                }
+                if (!(fabs(dw[line] - sw) <= tsum)) wok = 0;
+            }
+            if (wok && fabs(dl - sumd) <= (by_row ? tc[line] : tr[line])) {
                 for (int64_t x = 0; x < len; ++x) {
                     const double d = by_row ? Rr[x] - Pr[x] : Rc[x] - Pc[x];
                     if (fabs(d) <= (by_row ? tr[x] : tc[x])) continue;
@@ -628,6 +735,30 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
                 if (!(fabs(Rr[jj] - Pr[jj]) <= tr[jj])) cols[nc++] = jj;
             int paired = 1;
             unsigned taken = 0;
+            if (wt) {
+                /* Weighted mode: each flagged column locates its error's
+                 * row from the ratio of its weighted to its plain residual
+                 * (row + 1); the row must be flagged, taken once, and carry
+                 * the same residual.  Equal errors need no pairing by size;
+                 * two errors in one column give a ratio that does not fit. */
+                for (int64_t a = 0; a < nr; ++a) mate[a] = -1;
+                for (int64_t b = 0; b < nc && paired; ++b) {
+                    const double dc = Rr[cols[b]] - Pr[cols[b]];
+                    const double ratio = dw[cols[b]] / dc;
+                    if (!isfinite(ratio) || !isfinite(dc)) { paired = 0; break; }
+                    const int64_t r = (int64_t)llround(ratio) - 1;
+                    int64_t a = -1;
+                    for (int64_t q = 0; q < nr; ++q) if (rows[q] == r) a = q;
+                    if (a < 0 || mate[a] >= 0) { paired = 0; break; }
+                    if (!(fabs(dw[cols[b]] - (double)(r + 1) * dc) <=
+                          tw[cols[b]] + (double)(r + 1) * tr[cols[b]]) ||
+                        !(fabs((Rc[r] - Pc[r]) - dc) <= tc[r] + tr[cols[b]])) {
+                        paired = 0;
+                        break;
+                    }
+                    mate[a] = b;
+                }
+            } else
             for (int64_t a = 0; a < nr && paired; ++a) {
                 const double dr = Rc[rows[a]] - Pc[rows[a]];
                 int64_t found = 0;
@@ -695,6 +826,7 @@ static int ft_tile(const oracle_params *P, const double *A, const double *B,
         }
 
     free(acc); free(out); free(Pr); free(Pc); free(Rr); free(Rc); free(tr); free(tc);
+    free(Pw); free(tw); free(dw);
     return produced;
 }
 
@@ -897,6 +1029,30 @@ static int ft_tile_split(const oracle_params *P, const double *A, const double *
     free(W); free(Wraw); free(Ws); free(Wr); free(pub); free(ptau); free(Psum); free(Tsum);
     free(li); free(le); free(map); free(out); free(Pe); free(Re); free(Te); free(De);
     return nrec;
+}
+
+/* Weighted encoded checksums, their thresholds and the weighted reference
+ * sums of one fault-free tile (pins of the weighted mode). */
+void oracle_tile_weighted(const oracle_params *P, const double *A, const double *B,
+                          const double *Cin, int64_t tile_m, int64_t tile_n,
+                          double *Pw, double *tw, double *Rw)
+{
+    const int64_t i0 = tile_m * P->tm, j0 = tile_n * P->tn;
+    const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 : P->tm;
+    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;
+    double *acc = malloc(sizeof(double) * h * w);
+    tile_encode_weighted(P, A, B, Cin, i0, j0, h, w, Pw, tw);
+    tile_accumulate(P, A, B, i0, j0, h, w, acc, NULL, 0, NULL);
+    for (int64_t jj = 0; jj < w; ++jj) {
+        double s = 0.0;
+        for (int64_t ii = 0; ii < h; ++ii) {
+            double a = P->alpha * acc[ii + jj * h];
+            if (P->beta != 0.0) a = a + P->beta * Cin[(i0 + ii) + (j0 + jj) * P->ldc];
+            s += (double)(ii + 1) * a;
+        }
+        Rw[jj] = s;
+    }
+    free(acc);
 }
 
 /* Fault-tolerant GEMM over the tile grid.  tiles: list of tile indices

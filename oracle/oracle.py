@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libftgemm_oracle.so")
 
 # Fault modes / targets / record kinds, as defined in ftgemm_oracle.c.
 ADD, BITFLIP = 0, 1
-TGT_ACC, TGT_ROW_CHECKSUM, TGT_COL_CHECKSUM = 0, 1, 2
+TGT_ACC, TGT_ROW_CHECKSUM, TGT_COL_CHECKSUM, TGT_WEIGHTED_CHECKSUM = 0, 1, 2, 3
 CORRECTED, CHECKSUM_ONLY, RECOMPUTED, UNCORRECTABLE = 1, 2, 3, 4
 
 DEFAULT_LAMBDA = 8.0
@@ -82,7 +82,7 @@ class _Params(C.Structure):
                 ("alpha", C.c_double), ("beta", C.c_double), ("tm", C.c_int64),
                 ("tn", C.c_int64), ("bk", C.c_int64), ("acc_bits", C.c_int32),
                 ("correct", C.c_int32), ("lam", C.c_double), ("mma_grid", C.c_double),
-                ("mma_group", C.c_int32), ("one_sided", C.c_int32), ("pad", C.c_int32),
+                ("mma_group", C.c_int32), ("one_sided", C.c_int32), ("weighted", C.c_int32),
                 ("slice_k", C.c_int64)]
 
 
@@ -152,6 +152,8 @@ class Oracle:
                                             C.c_int64, dp, dp, dp, dp]
         L.oracle_set_threads.restype = C.c_int32
         L.oracle_set_threads.argtypes = [C.c_int32]
+        L.oracle_tile_weighted.argtypes = [C.POINTER(_Params), dp, dp, dp, C.c_int64,
+                                           C.c_int64, dp, dp, dp]
         L.oracle_sizeof.restype = C.c_int64
         L.oracle_sizeof.argtypes = [C.c_int]
         for idx, cls in enumerate((_Inj, _Rec, _Echo, _Params)):
@@ -207,16 +209,16 @@ class Oracle:
 
     # -- fault-tolerant GEMM ----------------------------------------------
     def _params(self, A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, correct, lam,
-                mma=(0.0, 1), one_sided=False, slice_k=0):
+                mma=(0.0, 1), one_sided=False, slice_k=0, weighted=False):
         m, n, k = _dims(A, B, ta, tb)
         return _Params(int(ta), int(tb), m, n, k, max(1, A.shape[0]), max(1, B.shape[0]),
                        max(1, Cin.shape[0]), alpha, beta, tm, tn, bk, acc_bits,
-                       int(correct), lam, float(mma[0]), int(mma[1]), int(bool(one_sided)), 0,
-                       int(slice_k))
+                       int(correct), lam, float(mma[0]), int(mma[1]), int(bool(one_sided)),
+                       int(bool(weighted)), int(slice_k))
 
     def ftgemm(self, A, B, Cin=None, alpha=1.0, beta=0.0, ta=False, tb=False, tm=128,
                tn=128, bk=16, acc_bits=64, injections=(), tiles=None, correct=True,
-               lam=DEFAULT_LAMBDA, mma=(0.0, 1), one_sided=False, slice_k=0):
+               lam=DEFAULT_LAMBDA, mma=(0.0, 1), one_sided=False, slice_k=0, weighted=False):
         """Fault-tolerant GEMM, tile by tile (Sections 2.2 and 2.3).  mma:
         (grid, group) of a multiplier that truncates its in-instruction
         sums, which widens the thresholds; (0, 1) for exact sums.
@@ -225,12 +227,15 @@ class Oracle:
         slice_k: 0, or the length of the slices of a split inner dimension;
         each slice is verified as a tile of its own and the reduction of the
         slices is verified against their summed checksums (records: one per
-        slice that found something, then one for the reduction)."""
+        slice that found something, then one for the reduction).
+        weighted: each tile also keeps a weighted row checksum per column
+        (weights i + 1 over its rows), which locates and confirms
+        corrections of several errors."""
         A, B = _f64(A), _f64(B)
         m, n, k = _dims(A, B, ta, tb)
         Cin = np.zeros((max(m, 1), max(n, 1)), order="F") if Cin is None else _f64(Cin)
         P = self._params(A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, correct, lam,
-                         mma, one_sided, slice_k)
+                         mma, one_sided, slice_k, weighted)
         out = np.full((m, n), np.nan, order="F")
         raw = np.full((m, n), np.nan, order="F")
         inj = list(injections)
@@ -290,6 +295,22 @@ class Oracle:
         self.L.oracle_tile_checksums(C.byref(P), _dptr(A), _dptr(B), _dptr(Cin), tile_m,
                                      tile_n, _dptr(Pr), _dptr(Pc), _dptr(Rr), _dptr(Rc))
         return Pr, Pc, Rr, Rc
+
+
+    def tile_weighted(self, A, B, tile_m, tile_n, Cin=None, alpha=1.0, beta=0.0, ta=False,
+                      tb=False, tm=128, tn=128, bk=16, acc_bits=64, lam=DEFAULT_LAMBDA):
+        """Weighted encoded checksums, thresholds and reference sums (Pw, tw,
+        Rw) of one fault-free tile."""
+        A, B = _f64(A), _f64(B)
+        m, n, k = _dims(A, B, ta, tb)
+        Cin = np.zeros((max(m, 1), max(n, 1)), order="F") if Cin is None else _f64(Cin)
+        P = self._params(A, B, Cin, alpha, beta, ta, tb, tm, tn, bk, acc_bits, True, lam,
+                         weighted=True)
+        w = min(tn, n - tile_n * tn)
+        Pw, tw, Rw = np.empty(w), np.empty(w), np.empty(w)
+        self.L.oracle_tile_weighted(C.byref(P), _dptr(A), _dptr(B), _dptr(Cin), tile_m, tile_n,
+                                    _dptr(Pw), _dptr(tw), _dptr(Rw))
+        return Pw, tw, Rw
 
 
 _default = None

@@ -413,6 +413,111 @@ def pin_split_inner_dimension(orc):
     assert [e["applied"] for e in r.echo] == [True, False, True]
 
 
+def pin_weighted_checksums(orc):
+    """The weighted row checksums of the hand-worked tile
+    (tests/golden/threshold_example.txt): encoded values and thresholds from
+    norms worked out by hand; and on integer data the weighted identity
+    e_w^T (A B) = (e_w^T A) B holds bit for bit in every tile, ragged and
+    transposed ones included, its reference side being the weighted column
+    sums of the product (numpy)."""
+    d = read_threshold_example()
+    kw = dict(Cin=d["Cin"], alpha=d["alpha"], beta=d["beta"], tm=4, tn=4, bk=2,
+              lam=d["lambda"])
+    Pw, tw, Rw = orc.tile_weighted(d["A"], d["B"], 0, 0, **kw)
+    assert np.array_equal(Pw, d["weighted_checksums"]) and np.array_equal(Rw, Pw)
+    nb = np.array([1.0, 5.0, 7.0, 5.0])
+    for acc_bits, u in ((64, 2.0 ** -53), (32, 2.0 ** -24)):
+        Pw, tw, Rw = orc.tile_weighted(d["A"], d["B"], 0, 0, acc_bits=acc_bits, **kw)
+        want = 8.0 * u * (2.0 * nb * (5.0 * np.sqrt(d["weighted_frob2"]) +
+                                      2.0 * np.sqrt(d["weighted_x2"])) +
+                          np.sqrt(d["weighted_cin2"]))
+        assert np.allclose(tw, want, rtol=1e-14, atol=0), (acc_bits, tw / u, want / u)
+    for ta in (False, True):
+        for tb in (False, True):
+            g = synth.rng(98, int(ta) * 2 + int(tb), 0)
+            m, n, k = 21, 18, 40
+            A = np.asfortranarray(g.integers(-8, 9, (k, m) if ta else (m, k)).astype(float))
+            B = np.asfortranarray(g.integers(-8, 9, (n, k) if tb else (k, n)).astype(float))
+            Cin = np.asfortranarray(g.integers(-8, 9, (m, n)).astype(float))
+            oa, ob = _ops(A, B, ta, tb)
+            Cf = 2.0 * (oa @ ob) - 1.0 * Cin
+            for ti in range(-(-m // 8)):
+                for tj in range(-(-n // 8)):
+                    Pw, tw, Rw = orc.tile_weighted(A, B, ti, tj, Cin, 2.0, -1.0, ta, tb, tm=8,
+                                                   tn=8, bk=5)
+                    blk = Cf[ti * 8:ti * 8 + 8, tj * 8:tj * 8 + 8]
+                    wts = np.arange(1, blk.shape[0] + 1, dtype=float)
+                    assert np.array_equal(Rw, wts @ blk), (ta, tb, ti, tj)
+                    assert np.array_equal(Pw, Rw), (ta, tb, ti, tj)
+
+
+def pin_weighted_location(orc):
+    """The weighted mode on integer data (residuals exact): every error
+    pattern below is set against brute force (where the faulty output
+    differs from the fault-free product).  Two equal errors in distinct rows
+    and columns, which residual pairing cannot tell apart, are located by the
+    ratio of weighted to plain residual and corrected; three errors on the
+    corners of a rectangle with the two off-corner ones equal, which pairing
+    misreads, and a row whose two errors cancel beside a row with two
+    errors, which a line correction misreads, are computed again; errors
+    along a column and along a row are corrected and confirmed; a fault on
+    the weighted checksum alone changes nothing; a data error plus a fault on
+    its column's weighted checksum is computed again; a lone non-finite
+    error is still rebuilt."""
+    g = synth.rng(99, 0, 0)
+    m, n, k = 32, 32, 24
+    A = np.asfortranarray(g.integers(-8, 9, (m, k)).astype(float))
+    B = np.asfortranarray(g.integers(-8, 9, (k, n)).astype(float))
+    Cin = np.asfortranarray(g.integers(-8, 9, (m, n)).astype(float))
+    Cff = 3.0 * (A @ B) + 2.0 * Cin
+    Inj = O.Injection
+    run = lambda plan, wt=True: orc.ftgemm(A, B, Cin, 3.0, 2.0, tm=16, tn=16, bk=8,
+                                           injections=plan, weighted=wt)
+    # equal errors: pairing recomputes, the weighted mode corrects
+    two = [Inj(2, 3, 1, O.ADD, 25.0), Inj(7, 12, 9, O.ADD, 25.0)]
+    r = run(two, False)
+    assert [d["kind"] for d in r.records] == [O.RECOMPUTED]
+    r = run(two)
+    assert np.argwhere(r.raw != Cff).tolist() == [[2, 3], [7, 12]]
+    assert [(d["kind"], d["row"], d["col"], d["nbad_rows"]) for d in r.records] == \
+        [(O.CORRECTED, 2, 3, 2)]
+    assert np.array_equal(r.C, Cff)
+    # four equal errors in distinct rows and columns of tile (1, 1)
+    four = [Inj(16 + 3 * q, 16 + 5 * q, 2 * q, O.ADD, 40.0) for q in range(4)]
+    r = run(four)
+    assert [(d["kind"], d["nbad_rows"], d["nbad_cols"]) for d in r.records] == \
+        [(O.CORRECTED, 4, 4)]
+    assert np.array_equal(r.C, Cff)
+    # the rectangle: pairing corrects it wrongly, the weighted mode recomputes
+    rect = [Inj(2, 3, 1, O.ADD, 25.0), Inj(2, 12, 9, O.ADD, 40.0), Inj(7, 3, 9, O.ADD, 40.0)]
+    assert not np.array_equal(run(rect, False).C, Cff)
+    r = run(rect)
+    assert [d["kind"] for d in r.records] == [O.RECOMPUTED] and np.array_equal(r.C, Cff)
+    # a row with two errors and a row whose two errors cancel: rows 2 and 5
+    # of tile (0, 0); only row 2 and columns 3, 9 disagree on the plain sums
+    canc = [Inj(2, 3, 1, O.ADD, 10.0), Inj(5, 3, 1, O.ADD, 6.0), Inj(5, 9, 1, O.ADD, -6.0),
+            Inj(2, 9, 4, O.ADD, 7.0)]
+    r = run(canc, False)
+    assert [d["kind"] for d in r.records] == [O.CORRECTED] and not np.array_equal(r.C, Cff)
+    r = run(canc)
+    assert [d["kind"] for d in r.records] == [O.RECOMPUTED] and np.array_equal(r.C, Cff)
+    # lines: three errors in column 9 (tile (0, 0)), two in row 20 (tile (1, 0))
+    lines = [Inj(1, 9, 5, O.ADD, 50.0), Inj(7, 9, 9, O.ADD, 60.0), Inj(14, 9, 20, O.ADD, -70.0),
+             Inj(20, 2, 3, O.ADD, 100.0), Inj(20, 11, 17, O.ADD, -40.0)]
+    r = run(lines)
+    assert sorted((d["kind"], d["row"], d["col"]) for d in r.records) == \
+        [(O.CORRECTED, 1, 9), (O.CORRECTED, 20, 2)]
+    assert np.array_equal(r.C, Cff)
+    # checksum faults on the weighted entries
+    r = run([Inj(4, 6, 0, O.ADD, 500.0, target=O.TGT_WEIGHTED_CHECKSUM)])
+    assert not r.records and r.echo[0]["applied"] and np.array_equal(r.C, Cff)
+    r = run([Inj(4, 6, 3, O.ADD, 30.0), Inj(0, 6, 0, O.ADD, 90.0, target=O.TGT_WEIGHTED_CHECKSUM)])
+    assert [d["kind"] for d in r.records] == [O.RECOMPUTED] and np.array_equal(r.C, Cff)
+    # a lone infinite error is rebuilt as in the plain mode
+    r = run([Inj(9, 10, 4, O.ADD, np.inf)])
+    assert [d["kind"] for d in r.records] == [O.CORRECTED] and np.array_equal(r.C, Cff)
+
+
 def pin_one_sided(orc):
     """One-sided mode (only the column checksum, one entry per row;
     recompute on any disagreement).  On integer data: each accumulator fault
@@ -624,4 +729,5 @@ ALL_PINS = [pin_gemm_vs_numpy, pin_gemm_integer_exact, pin_blas_special_cases,
             pin_crossing_pairs, pin_one_sided,
             pin_no_false_positives, pin_ragged_and_subset, pin_threshold_sound_and_tight,
             pin_threshold_worked_example, pin_gemm_entries_vs_numpy,
-            pin_single_flag_rule, pin_split_inner_dimension]
+            pin_single_flag_rule, pin_split_inner_dimension, pin_weighted_checksums,
+            pin_weighted_location]

@@ -18,7 +18,7 @@ MUTANTS = {
     "line_residual_added_not_subtracted": (
         "out[ii + jj * h] -= d;", "out[ii + jj * h] += d;"),
     "line_confirmed_without_its_own_residual": (
-        "if (fabs(dl - sumd) <= (by_row ? tc[line] : tr[line])) {",
+        "if (wok && fabs(dl - sumd) <= (by_row ? tc[line] : tr[line])) {",
         "if (fabs(sumd) <= (by_row ? tc[line] : tr[line]) || 1) {"),
     "pair_residual_added_not_subtracted": (
         "out[rows[a] + jj * h] -= Rr[jj] - Pr[jj];", "out[rows[a] + jj * h] += Rr[jj] - Pr[jj];"),
@@ -36,8 +36,8 @@ MUTANTS = {
     "threshold_drops_sqrt_h": (
         "double sh = sqrt((double)h);", "double sh = 1.0;"),
     "threshold_unit_roundoffs_swapped": (
-        "const double u = (P->acc_bits == 32) ? ldexp(1.0, -24) : ldexp(1.0, -53);",
-        "const double u = (P->acc_bits == 32) ? ldexp(1.0, -53) : ldexp(1.0, -24);"),
+        "return (P->acc_bits == 32) ? ldexp(1.0, -24) : ldexp(1.0, -53);",
+        "return (P->acc_bits == 32) ? ldexp(1.0, -53) : ldexp(1.0, -24);"),
     "threshold_drops_beta_term": (
         " + 2.0 * u * fabs(beta) * nrm_cin);", ");"),
     "threshold_lambda_a_tenth": (
@@ -59,6 +59,15 @@ MUTANTS = {
         "const int in = f->k_index >= kb &&", "const int in = f->k_index >= kb + 8 &&"),
     "split_reduction_drops_beta": (
         "if (beta != 0.0) { v = v + beta * c; vr = vr + beta * c; }", ""),
+    "weighted_encode_weights_off_by_one": (
+        "s += (double)(ii + 1) * opA(A, P->lda, P->ta, i0 + ii, p);",
+        "s += (double)(ii) * opA(A, P->lda, P->ta, i0 + ii, p);"),
+    "weighted_line_confirm_skipped": (
+        "if (!(fabs(dw[x] - (double)(line + 1) * d) <=", "if (0 && !(fabs(dw[x] - (double)(line + 1) * d) <="),
+    "weighted_single_confirm_skipped": (
+        "const int wok = !wt || !isfinite(dcol)", "const int wok = 1 || !isfinite(dcol)"),
+    "weighted_location_off_by_one": (
+        "const int64_t r = (int64_t)llround(ratio) - 1;", "const int64_t r = (int64_t)llround(ratio);"),
     "threshold_zero": (
         "return lambda * (fabs(alpha)", "return 0.0 * (fabs(alpha)"),
     "fault_one_step_late": (
@@ -68,7 +77,7 @@ MUTANTS = {
         "const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 : P->tm;\n    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;\n    const double alpha",
         "const int64_t h = (P->m - i0 < P->tm) ? P->m - i0 - 1 : P->tm;\n    const int64_t w = (P->n - j0 < P->tn) ? P->n - j0 : P->tn;\n    const double alpha"),
     "correction_not_confirmed": (
-        "if (fabs(sc + fixed - Pc[ibad]) <= tc[ibad]) {", "if (1) {"),
+        "if (wok && fabs(sc + fixed - Pc[ibad]) <= tc[ibad]) {", "if (1) {"),
     "bf16_exponent_bias_off_by_one": (
         "v = ldexp((double)(128 + f), e - 127 - 7);", "v = ldexp((double)(128 + f), e - 126 - 7);"),
     "e4m3_nan_code_wrong": (
