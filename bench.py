@@ -449,8 +449,8 @@ def batched_leg(torch, F, synth, np, dtype, steps, warmup):
     return out
 
 
-PROFILE_KINDS = ["f64", "f64-plain", "f64-unfused", "bf16", "bf16-plain", "bf16-fused",
-                 "fp8", "fp8-plain", "fp8-plain-128", "fp8-fused", "copy"]
+PROFILE_KINDS = ["f64", "f64-plain", "f64-unfused", "f64-weighted", "bf16", "bf16-plain",
+                 "bf16-fused", "fp8", "fp8-plain", "fp8-plain-128", "fp8-fused", "copy"]
 
 
 def profile_run(kind, size, calls=3):
@@ -459,8 +459,8 @@ def profile_run(kind, size, calls=3):
     a 512 MiB buffer (the scale of the traffic counters).  Kinds: the
     fault-tolerant call (f64, bf16, fp8), the same kernel with checksums
     compiled out on its default tile (-plain) and, for FP8, on the
-    fault-tolerant call's 128-row tile (fp8-plain-128), the unfused FP64
-    mode, and the low-precision fault tolerance with every operand checksum
+    fault-tolerant call's 128-row tile (fp8-plain-128), the unfused and
+    weighted FP64 modes, and the low-precision fault tolerance with every operand checksum
     formed in the tiles from the staged operands (-fused: the entry point
     that allocates nothing, which takes no pass before the product)."""
     import torch
@@ -477,7 +477,8 @@ def profile_run(kind, size, calls=3):
     m = n = k = size
     g = torch.Generator(device="cuda").manual_seed(5)
     base = kind.split("-")[0]
-    abft = {"plain": 0, "unfused": 3}.get(kind.split("-")[1], 1) if "-" in kind else 1
+    abft = ({"plain": 0, "unfused": 3, "weighted": 4}.get(kind.split("-")[1], 1)
+            if "-" in kind else 1)
     call = F.gemm_ex_noalloc if kind.endswith("-fused") else F.gemm_ex
     if base == "f64":
         A = F.colmajor_empty(m, k, torch.float64)
@@ -602,6 +603,28 @@ def main():
     F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=3), report=rb)
     clean_uf = rb.view()
     t_uf, _ = timed(torch, call(3), args.steps, args.warmup, reset)
+    # the weighted mode (also a weighted row checksum per column): error-free,
+    # then two equal faults in each of 64 other tiles, in different rows and
+    # columns (paired by the weighted checksums; the plain mode recomputes)
+    dC.copy_(dC0)
+    rb = F.ReportBuffer()
+    F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=4), report=rb)
+    clean_w = rb.view()
+    t_w, _ = timed(torch, call(4), args.steps, args.warmup, reset)
+    plan3 = synth.crossing_pairs_plan(synth.rng(20, m + 2, synth.STREAM_PLAN), m, n, k, 128, 128,
+                                      -(-tiles // 64), synth.log_magnitude(sigma, 0.0, 2.0),
+                                      equal=True)
+    F.set_fault_plan(plan3)
+    t_w_inj, _ = timed(torch, call(4), args.steps, args.warmup, reset)
+    rb = F.ReportBuffer()
+    reset()
+    F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=4), report=rb)
+    inj_w = rb.view()
+    rb = F.ReportBuffer()
+    reset()
+    F.gemm(dA, dB, dC, 1.0, 1.0, report=rb)
+    inj_w1 = rb.view()
+    F.clear_fault_plan()
 
     value = flops / (t_ft * 1e-3) / 1e12
     achieved = value
@@ -650,6 +673,18 @@ def main():
                     "injected": {"faults_per_call": len(plan),
                                  "overhead_pct": round(100.0 * (t_uf_inj / t_plain - 1.0), 2),
                                  "detected": int(inj_uf.detected)}},
+        "weighted": {"tflops": round(flops / (t_w * 1e-3) / 1e12, 3),
+                     "abft_overhead_pct": round(100.0 * (t_w / t_plain - 1.0), 2),
+                     "error_free_check": {"detected": int(clean_w.detected),
+                                          "max_ratio": clean_w.max_ratio},
+                     "injected_equal_pairs": {
+                         "faults_per_call": len(plan3),
+                         "tflops": round(flops / (t_w_inj * 1e-3) / 1e12, 3),
+                         "overhead_pct": round(100.0 * (t_w_inj / t_plain - 1.0), 2),
+                         "corrected": int(inj_w.corrected),
+                         "recomputed": int(inj_w.recomputed),
+                         "mode_1_corrected": int(inj_w1.corrected),
+                         "mode_1_recomputed": int(inj_w1.recomputed)}},
     }
     if not args.no_low_precision:
         del dA, dB, dC, dC0

@@ -81,7 +81,12 @@ enum {
 
 /* Fault injection (test hook): mode and target. */
 enum { FTGEMM_INJ_ADD = 0, FTGEMM_INJ_BITFLIP = 1 };
-enum { FTGEMM_TGT_ACC = 0, FTGEMM_TGT_ROW_CHECKSUM = 1, FTGEMM_TGT_COL_CHECKSUM = 2 };
+enum {
+    FTGEMM_TGT_ACC = 0,
+    FTGEMM_TGT_ROW_CHECKSUM = 1,
+    FTGEMM_TGT_COL_CHECKSUM = 2,
+    FTGEMM_TGT_WEIGHTED_CHECKSUM = 3  /* weighted mode (abft 4) only */
+};
 
 /* One detection.  row / col are global indices into C (-1 where the kind
  * has none: a checksum-only record names the row of a disagreeing column
@@ -130,7 +135,9 @@ typedef struct {
 /* One planned soft error (test hook).  It lands after the inner-dimension
  * step containing k_index has been accumulated (ACC target), or on the
  * encoded checksum entry of column `col` (ROW_CHECKSUM) / row `row`
- * (COL_CHECKSUM) of the tile holding C(row, col).  BITFLIP flips bit `bit`
+ * (COL_CHECKSUM) of the tile holding C(row, col), or on the weighted row
+ * checksum entry of column `col` (WEIGHTED_CHECKSUM; applied in the
+ * weighted mode only, elsewhere it has no entry to land on).  BITFLIP flips bit `bit`
  * of the accumulator in its own precision (FP64 for F64, FP32 otherwise);
  * checksum targets take ADD only.  `problem` selects the problem of a
  * batched call (0 otherwise). */
@@ -170,6 +177,18 @@ typedef struct {
  *      are not applied.  Its workspace ((m + n) k / 128 + 8 m n / 128
  *      doubles, plus the thin GEMMs' split slices) is grown on demand and
  *      kept.
+ *   4  weighted (F64 single calls only; FTGEMM_ERR_UNSUPPORTED for BF16 /
+ *      FP8, in batches and without allocation): mode 1 plus a weighted
+ *      row checksum per column of each tile, sum_i (i + 1) C(i, j) over
+ *      the tile's local rows i, encoded the same way (from the weighted
+ *      column sums of the staged A tile, and C_in in the beta pass) and
+ *      held to the column's threshold with A, the operand checksum and
+ *      C_in weighted alike.  A single error at local row r of column j
+ *      shows as r + 1 times the column's residual on it: every correction
+ *      of mode 1 is confirmed by it, and errors in distinct rows and
+ *      columns are paired by it (each flagged column names its row) rather
+ *      than by their sizes, so equal errors are corrected too.  The inner
+ *      dimension is never split.
  * BF16 / FP8 single calls with abft 2, and with abft 1 when the output
  * holds at least 256 tiles, take the threshold norms of the rows of op(A)
  * and columns of op(B), and the FP32 operand checksums of every tile
@@ -236,7 +255,7 @@ ftgemm_status ftgemm_gemm_batched(int32_t count, const ftgemm_gemm_desc *problem
  * checksums themselves, with no pass over A and B before the product (C is
  * the same; a rebuilt element may differ from ftgemm_gemm_ex's in its last
  * FP32 bits).  Refused with FTGEMM_ERR_UNSUPPORTED: abft 2 and 3 (their
- * workspace grows with the problem) and an armed fault plan longer than
+ * workspace grows with the problem), abft 4 and an armed fault plan longer than
  * 256 entries.  Records beyond 1024 are dropped (still counted).  Every
  * call on a GPU shares that GPU's array and keeps the last call's contents
  * in it: calls that overlap on one GPU (on different streams, or from
@@ -297,9 +316,10 @@ ftgemm_status ftgemm_query_tiling(ftgemm_dtype dtype, int64_t m, int64_t n, int6
  * the other fields are not read): in the one-sided mode FP8 also takes
  * 256 x 128 tiles from 256 tiles on.  Errors: desc NULL or its fields out of
  * range (position 1), an output pointer NULL (position 2); one-sided F64
- * and unfused BF16 / FP8 return FTGEMM_ERR_UNSUPPORTED.  The unfused mode
- * reports the tiling of its checksum-free product (its verification tiles
- * are 128 x 128, as the F64 kernel's). */
+ * and unfused or weighted BF16 / FP8 return FTGEMM_ERR_UNSUPPORTED.  The
+ * unfused mode reports the tiling of its checksum-free product (its
+ * verification tiles are 128 x 128, as the F64 kernel's); the weighted mode
+ * reports split_k 1. */
 ftgemm_status ftgemm_query_tiling_ex(const ftgemm_gemm_desc *desc, int32_t *tm, int32_t *tn,
                                      int32_t *bk, int32_t *split_k);
 

@@ -64,6 +64,10 @@ struct Epi {
     double fin_row[TM], fin_col[TN];            // full encoded checksums
     double tau_row[TM], tau_col[TN];
     double d_row[TM], d_col[TN];
+    // weighted mode: weighted row checksums of the columns (weights i + 1)
+    double enc_colw[NW][TN];                    // product part, partials
+    double ref_colw[WM][TN], cin_colw[WM][TN], cin2_colw[WM][TN];
+    double fin_colw[TN], tau_colw[TN], d_colw[TN];
 };
 
 struct Smem {
@@ -73,9 +77,11 @@ struct Smem {
     } u;
     double xs[2][BK][NW];  // [buffer][p][partial]: column sums of the A tile
     double ys[2][BK][NW];  // [buffer][p][partial]: row sums of the B tile
+    double xws[2][BK][NW]; // weighted mode: weighted column sums of the A tile
     double red[NW][2];
     double vnrm[2][BK];    // x_p^2, y_p^2 summed over the steps (slot per p)
-    double scal[4];        // |x|^2, |y|^2, |A_I|_F^2, |B_J|_F^2
+    double vnrmw[BK];      // weighted mode: x'_p^2 summed over the steps
+    double scal[6];        // |x|^2, |y|^2, |A_I|_F^2, |B_J|_F^2, |W A_I|_F^2, |x'|^2
     TileFault faults[kMaxTileFaults];
     int nfaults;
     double wratio[4];      // largest |d| / tau of the waves that verify
@@ -165,6 +171,21 @@ struct OpLoader {
             if ((t & 63) < 32) dst[t & 31][t >> 6] = s;
         }
     }
+    // The same with every element weighted by its outer index + 1 (the
+    // weighted mode's x'_p = sum_i (i + 1) A(i, p)).
+    __device__ __forceinline__ void wsum_to(const double v[EPT], double (*dst)[NW]) const
+    {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) s = fma((double)(o(r) + 1), v[r], s);
+        if (kContig) {
+            s = sum16(s);
+            if ((t & 15) == 0) dst[t >> 4][0] = s;
+        } else {
+            s = pair_sum32(s);
+            if ((t & 63) < 32) dst[t & 31][t >> 6] = s;
+        }
+    }
     // Per-outer-index partials accumulated by this thread over the steps,
     // completed across the threads that hold the same outer indices (the
     // other p), into dst[slot][outer]: 8 slots (one per wave) for kContig,
@@ -209,7 +230,9 @@ __device__ __forceinline__ int owner_reg(int row, int col)
     return ((row & 63) >> 4) * 8 + ((col & 31) >> 4) * 4 + ((row & 15) >> 2);
 }
 
-template <bool TA, bool TB, bool ABFT>
+// WGT (with ABFT): the weighted mode -- a weighted row checksum per column
+// (weights i + 1 over the tile's rows) locates and confirms corrections.
+template <bool TA, bool TB, bool ABFT, bool WGT = false>
 __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem &sm)
 {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -246,6 +269,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
     };
     auto sums = [&](int buf) {
         la.sum_to(ra, sm.xs[buf]);
+        if (WGT) la.wsum_to(ra, sm.xws[buf]);
         lb.sum_to(rb, sm.ys[buf]);
     };
 
@@ -278,8 +302,10 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         // The norms only scale the rounding-error threshold, so FP32 is ample
         // for them (and halves their registers).
         double enc_a[EPT] = {}, enc_b[EPT] = {};
+        double enc_bw[WGT ? EPT : 1] = {};  // weighted mode: x' . B partials
         float nrm_a[EPT] = {}, nrm_b[EPT] = {};
         float vx = 0.0f, vy = 0.0f;  // x_p^2, y_p^2 over the steps, for this thread's p
+        float vxw = 0.0f;            // weighted mode: x'_p^2
 
         load(0);
         if (ABFT) sums(0);
@@ -302,11 +328,12 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                 __syncthreads();
                 // x_p, y_p of step s are complete; their gather is issued
                 // here and used after the step's first products
-                double yv = 0.0, xv = 0.0;
+                double yv = 0.0, xv = 0.0, xwv = 0.0;
                 if (ABFT) {
                     yv = gather<OpLoader<TB>::kParts>(sm.ys[buf], la.p());
                     xv = gather<OpLoader<!TA>::kParts>(sm.xs[buf], lb.p());
                 }
+                if (WGT) xwv = gather<OpLoader<!TA>::kParts>(sm.xws[buf], lb.p());
 #pragma unroll
                 for (int kk = 0; kk < BK / 4; ++kk) {
                     if (kk == (ABFT ? 1 : 0)) {
@@ -317,6 +344,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                             for (int r = 0; r < EPT; ++r) {
                                 enc_a[r] += ra[r] * yv;
                                 enc_b[r] += xv * rb[r];
+                                if (WGT) enc_bw[r] += xwv * rb[r];
                                 // squares of the FP32-rounded values: two
                                 // instructions (convert, FP32 fma)
                                 const float fa = (float)ra[r], fb = (float)rb[r];
@@ -326,6 +354,10 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                             const float fy = (float)yv, fx = (float)xv;
                             vy = fmaf(fy, fy, vy);
                             vx = fmaf(fx, fx, vx);
+                            if (WGT) {
+                                const float fxw = (float)xwv;
+                                vxw = fmaf(fxw, fxw, vxw);
+                            }
                         }
                         if (s + 1 < nsteps) load(s + 1);
                     }
@@ -417,10 +449,16 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         lb.partials_to(nrm_b, sm.u.epi.nrm_col);
         if (la.first_of_p()) sm.vnrm[1][la.p()] = (double)vy;
         if (lb.first_of_p()) sm.vnrm[0][lb.p()] = (double)vx;
+        if (WGT) {
+            lb.partials_to(enc_bw, sm.u.epi.enc_colw);
+            if (lb.first_of_p()) sm.vnrmw[lb.p()] = (double)vxw;
+        }
 
         // Beta pass fused with the C_in part of the encoding (Section 2.2)
         // and the reference sums of the output.
         double col_o[2] = {0, 0}, col_c[2] = {0, 0}, col_c2[2] = {0, 0};
+        // weighted mode: the same column sums with row weights i + 1
+        double col_ow[WGT ? 2 : 1] = {}, col_cw[WGT ? 2 : 1] = {}, col_cw2[WGT ? 2 : 1] = {};
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -438,6 +476,10 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                     acc[mi][ni][r] = o;
                     row_o += o; row_c += cin; row_c2 += cin * cin;
                     col_o[ni] += o; col_c[ni] += cin; col_c2[ni] += cin * cin;
+                    if (WGT) {
+                        const double wr = (double)(row + 1), cw = wr * cin;
+                        col_ow[ni] += wr * o; col_cw[ni] += cw; col_cw2[ni] += cw * cw;
+                    }
                 }
                 row_o = sum16(row_o);
                 if (use_c) { row_c = sum16(row_c); row_c2 = sum16(row_c2); }
@@ -456,6 +498,19 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                 sm.u.epi.ref_col[wm][col] = col_o[ni];
                 sm.u.epi.cin_col[wm][col] = col_c[ni];
                 sm.u.epi.cin2_col[wm][col] = col_c2[ni];
+            }
+            if (WGT) {
+                col_ow[ni] = sum_rows(col_ow[ni]);
+                if (use_c) {
+                    col_cw[ni] = sum_rows(col_cw[ni]);
+                    col_cw2[ni] = sum_rows(col_cw2[ni]);
+                }
+                if (q == 0) {
+                    const int col = wn * 32 + 16 * ni + c16;
+                    sm.u.epi.ref_colw[wm][col] = col_ow[ni];
+                    sm.u.epi.cin_colw[wm][col] = col_cw[ni];
+                    sm.u.epi.cin2_colw[wm][col] = col_cw2[ni];
+                }
             }
         }
         if (t == 0) { sm.nbad_r = 0; sm.nbad_c = 0; sm.ibad = TM; sm.jbad = TN; }
@@ -476,23 +531,34 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
             nrm2 = nr;
             sm.u.epi.fin_row[x] = e;
         } else if (is_col) {
-            double e = 0, nr = 0;
+            double e = 0, nr = 0, ew = 0;
 #pragma unroll
             for (int v = 0; v < OpLoader<TB>::kOuterParts; ++v) {
                 e += sm.u.epi.enc_col[v][x];
                 nr += sm.u.epi.nrm_col[v][x];
+                if (WGT) ew += sm.u.epi.enc_colw[v][x];
             }
             nrm2 = nr;
             sm.u.epi.fin_col[x] = e;
+            if (WGT) sm.u.epi.fin_colw[x] = ew;
         }
-        // Frobenius norms of the A and B tiles (waves 0-1 and 2-3), |x|, |y|
+        // Frobenius norms of the A and B tiles (waves 0-1 and 2-3), |x|, |y|;
+        // weighted mode: |W A_I|_F (rows weighted by i + 1) and |x'|
         if (w < 4) {
             const double f = sum64(nrm2);
             if (lane == 0) sm.red[w][0] = f;
+            if (WGT && w < 2) {
+                const double wx = (double)(x + 1), fw = sum64(wx * wx * nrm2);
+                if (lane == 0) sm.red[w][1] = fw;
+            }
         }
         if (w == 4) {
             const double v2 = pair_sum16(sum16(sm.vnrm[lane >> 5][lane & 31]));
             if ((lane & 31) == 0) sm.red[4 + (lane >> 5)][0] = v2;
+        }
+        if (WGT && w == 5) {
+            const double v2 = sum64(lane < BK ? sm.vnrmw[lane] : 0.0);
+            if (lane == 0) sm.red[6][0] = v2;
         }
         __syncthreads();
         if (t == 0) {
@@ -500,6 +566,10 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
             sm.scal[3] = sm.red[2][0] + sm.red[3][0];  // |B_J|_F^2
             sm.scal[0] = sm.red[4][0];                 // |x|^2
             sm.scal[1] = sm.red[5][0];                 // |y|^2
+            if (WGT) {
+                sm.scal[4] = sm.red[0][1] + sm.red[1][1];  // |W A_I|_F^2
+                sm.scal[5] = sm.red[6][0];                 // |x'|^2
+            }
         }
         __syncthreads();
 
@@ -549,6 +619,29 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                     sm.u.epi.fin_row[x] = P; sm.u.epi.tau_row[x] = tau; sm.u.epi.d_row[x] = d;
                 } else {
                     sm.u.epi.fin_col[x] = P; sm.u.epi.tau_col[x] = tau; sm.u.epi.d_col[x] = d;
+                }
+                if (WGT && is_col) {
+                    // weighted row checksum of column x and its threshold:
+                    // the column's bound with A_I, x and C_in(:, x) weighted
+                    double Pw = g.alpha * sm.u.epi.fin_colw[x];
+                    const double Rw = sm.u.epi.ref_colw[0][x] + sm.u.epi.ref_colw[1][x];
+                    const double cw2 = sm.u.epi.cin2_colw[0][x] + sm.u.epi.cin2_colw[1][x];
+                    if (use_c) Pw += g.beta * (sm.u.epi.cin_colw[0][x] + sm.u.epi.cin_colw[1][x]);
+                    if (faults_on)
+                        for (int f = 0; f < nf; ++f) {
+                            const TileFault tf = sm.faults[f];
+                            if (tf.target != FTGEMM_TGT_WEIGHTED_CHECKSUM || tf.col != x) continue;
+                            ftgemm_injection_echo e;
+                            e.problem = g.problem; e.applied = 1; e.row = i0 + tf.row;
+                            e.col = j0 + tf.col; e.k_index = g.plan[tf.idx].k_index;
+                            e.before = Pw; Pw += tf.delta; e.after = Pw;
+                            g.echo[tf.idx] = e;
+                        }
+                    sm.u.epi.fin_colw[x] = Pw;
+                    sm.u.epi.tau_colw[x] =
+                        ft_threshold(kLambda, U, sqk, sqrt((double)hrows), g.alpha, sqrt(nrm2),
+                                     sqrt(sm.scal[4]), sqrt(sm.scal[5]), g.beta, sqrt(cw2));
+                    sm.u.epi.d_colw[x] = Rw - Pw;
                 }
                 if (x < (is_row ? hrows : wcols)) {
                     if (!(fabs(d) <= tau)) {
@@ -613,7 +706,16 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
 #pragma unroll
             for (int v = 0; v < NW; ++v) { sc += sm.red[v][0]; sr += sm.red[v][1]; }
             const double fixed = sm.u.epi.fin_col[js] - sc;
-            if (fabs(sr + fixed - sm.u.epi.fin_row[is]) <= sm.u.epi.tau_row[is]) {
+            // weighted mode: a finite error at (is, js) shows as is + 1 times
+            // the column's residual on its weighted checksum
+            bool wok = true;
+            if (WGT) {
+                const double dc = sm.u.epi.d_col[js], dw = sm.u.epi.d_colw[js];
+                wok = !isfinite(dc) || !isfinite(dw) ||
+                      fabs(dw - (double)(is + 1) * dc) <=
+                          sm.u.epi.tau_colw[js] + (double)(is + 1) * sm.u.epi.tau_col[js];
+            }
+            if (wok && fabs(sr + fixed - sm.u.epi.fin_row[is]) <= sm.u.epi.tau_row[is]) {
                 if (w == owner_wave(is, js)) {
                     const int ol = owner_lane(is, js), sel = owner_reg(is, js);
 #pragma unroll
@@ -645,7 +747,36 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                 if (f < nfix)
                     sumd += by_row ? sm.u.epi.d_col[sm.bad_c[f]] : sm.u.epi.d_row[sm.bad_r[f]];
             const double dl = by_row ? sm.u.epi.d_row[line] : sm.u.epi.d_col[line];
-            if (fabs(dl - sumd) <= (by_row ? sm.u.epi.tau_row[line] : sm.u.epi.tau_col[line])) {
+            // weighted mode: along a row, each flagged column shows line + 1
+            // times its residual on its weighted checksum; along a column,
+            // the column's weighted residual is the weighted sum of the
+            // flagged rows' residuals
+            bool wok = true;
+            if (WGT) {
+                if (by_row) {
+                    const double wl = (double)(line + 1);
+#pragma unroll
+                    for (int f = 0; f < kMaxLineFixes; ++f)
+                        if (f < nfix) {
+                            const int xc = sm.bad_c[f];
+                            if (!(fabs(sm.u.epi.d_colw[xc] - wl * sm.u.epi.d_col[xc]) <=
+                                  sm.u.epi.tau_colw[xc] + wl * sm.u.epi.tau_col[xc]))
+                                wok = false;
+                        }
+                } else {
+                    double sw = 0.0, tsum = sm.u.epi.tau_colw[line];
+#pragma unroll
+                    for (int f = 0; f < kMaxLineFixes; ++f)
+                        if (f < nfix) {
+                            const int xr = sm.bad_r[f];
+                            sw += (double)(xr + 1) * sm.u.epi.d_row[xr];
+                            tsum += (double)(xr + 1) * sm.u.epi.tau_row[xr];
+                        }
+                    wok = fabs(sm.u.epi.d_colw[line] - sw) <= tsum;
+                }
+            }
+            if (wok &&
+                fabs(dl - sumd) <= (by_row ? sm.u.epi.tau_row[line] : sm.u.epi.tau_col[line])) {
                 // each crossing's residual at its position along the line
                 // (the encoded-sum partials are no longer needed)
                 double *lfix = sm.u.epi.enc_row[0];
@@ -687,7 +818,39 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
             // which keeps this rare path off the registers of the others.
             int *pcol = reinterpret_cast<int *>(sm.u.epi.enc_row[1]);
             double *pd = sm.u.epi.enc_row[0];
-            if (t == 0) {
+            if (WGT && t == 0) {
+                // Weighted mode: each flagged column finds its error's row
+                // from the ratio of its weighted to its plain residual
+                // (row + 1); that row must be flagged, found once, carry the
+                // same residual, and the weighted residual must fit.  Equal
+                // errors need no pairing by size; two errors in one column
+                // give a ratio that fits no row.
+                bool ok = true;
+                unsigned taken = 0;
+                for (int b = 0; b < nc && ok; ++b) {
+                    const int j = sm.bad_c[b];
+                    const double dc = sm.u.epi.d_col[j], dw = sm.u.epi.d_colw[j];
+                    const double ratio = dw / dc;
+                    int a = -1, r = -1;
+                    if (isfinite(dc) && isfinite(ratio)) {
+                        const double rr = round(ratio);
+                        if (rr >= 1.0 && rr <= (double)TM) r = (int)rr - 1;
+                    }
+                    for (int q2 = 0; q2 < nr; ++q2)
+                        if (r >= 0 && sm.bad_r[q2] == r) a = q2;
+                    if (a < 0 || ((taken >> a) & 1u)) { ok = false; break; }
+                    const double wr = (double)(r + 1);
+                    if (!(fabs(dw - wr * dc) <= sm.u.epi.tau_colw[j] + wr * sm.u.epi.tau_col[j]) ||
+                        !(fabs(sm.u.epi.d_row[r] - dc) <= sm.u.epi.tau_row[r] + sm.u.epi.tau_col[j])) {
+                        ok = false;
+                        break;
+                    }
+                    taken |= 1u << a;
+                    pcol[r] = j;
+                    pd[r] = dc;
+                }
+                sm.red[3][0] = (double)(ok ? pcol[first_i] : -1);
+            } else if (t == 0) {
                 unsigned taken = 0;
                 int named = -1;
                 for (int a = 0; a < nr; ++a) {
@@ -877,14 +1040,14 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
     }
 }
 
-template <bool TA, bool TB, bool ABFT>
+template <bool TA, bool TB, bool ABFT, bool WGT = false>
 __global__ __launch_bounds__(NT, 2) void kernel(GemmArgs g)
 {
     __shared__ Smem sm;
     int tm_, tn_;
-    if (g.nslices <= 1) {
+    if (WGT || g.nslices <= 1) {
         map_tile(blockIdx.x, g.tiles_m, g.tiles_n, tm_, tn_);
-        tile<TA, TB, ABFT>(g, tm_, tn_, sm);
+        tile<TA, TB, ABFT, WGT>(g, tm_, tn_, sm);
         return;
     }
     // Slice s of a split inner dimension: the partial product of the
@@ -938,13 +1101,21 @@ __global__ __launch_bounds__(NT, 2) void batched_kernel(BatchArgs b)
 
 #define FTG_F64_CASE(ta, tb, ab) \
     hipLaunchKernelGGL((f64::kernel<ta, tb, ab>), dim3(grid), dim3(f64::NT), 0, stream, g)
+#define FTG_F64_WCASE(ta, tb) \
+    hipLaunchKernelGGL((f64::kernel<ta, tb, true, true>), dim3(grid), dim3(f64::NT), 0, stream, g)
 
-hipError_t launch_f64(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream)
+hipError_t launch_f64(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream,
+                      bool weighted)
 {
     const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n *
-                          (unsigned)(g.nslices > 1 ? g.nslices : 1);
+                          (unsigned)(g.nslices > 1 && !weighted ? g.nslices : 1);
     if (grid == 0) return hipSuccess;
-    if (abft) {
+    if (weighted) {
+        if (!ta && !tb) FTG_F64_WCASE(false, false);
+        else if (!ta && tb) FTG_F64_WCASE(false, true);
+        else if (ta && !tb) FTG_F64_WCASE(true, false);
+        else FTG_F64_WCASE(true, true);
+    } else if (abft) {
         if (!ta && !tb) FTG_F64_CASE(false, false, true);
         else if (!ta && tb) FTG_F64_CASE(false, true, true);
         else if (ta && !tb) FTG_F64_CASE(true, false, true);

@@ -428,7 +428,7 @@ int check_args(const ftgemm_gemm_desc &d)
     if (d.dtype == FTGEMM_FP8_E4M3 &&
         !(std::isfinite(d.scaleA) && std::isfinite(d.scaleB) && d.scaleA > 0 && d.scaleB > 0))
         return 14;
-    if (d.abft < 0 || d.abft > 3) return 14;
+    if (d.abft < 0 || d.abft > 4) return 14;
     if (d.m > INT32_MAX / 2 || d.n > INT32_MAX / 2) return d.m > INT32_MAX / 2 ? 3 : 4;
     return check_windows(d);
 }
@@ -658,7 +658,7 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
         return FTGEMM_OK;
     }
     if (d.abft == 2 && d.dtype == FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
-    if (d.abft == 3 && d.dtype != FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
+    if (d.abft >= 3 && d.dtype != FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
     if (d.dtype != FTGEMM_F64 && d.abft)
         for (const ftgemm_injection &f : g_plan)  // FP32 accumulators have 32 bits
@@ -714,9 +714,11 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
                                        nb + 2 * d.m, nb + 2 * d.m + d.n, pw, part, xs + nx, tn,
                                        d.k, stream));
     }
+    // (the weighted mode never splits the inner dimension)
     int64_t slice_k = d.k;
-    const int nslices =
-        d.dtype == FTGEMM_F64 ? choose_split(d.m, d.n, d.k, tm, tn, bk, &slice_k) : 1;
+    const int nslices = d.dtype == FTGEMM_F64 && d.abft != 4
+                            ? choose_split(d.m, d.n, d.k, tm, tn, bk, &slice_k)
+                            : 1;
     if (nslices > 1) {
         const int64_t ntiles = (int64_t)g.tiles_m * g.tiles_n;
         const size_t wbytes = sizeof(double) * (size_t)nslices * d.m * d.n;
@@ -739,7 +741,7 @@ ftgemm_status run_one(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStream_t
         HIP_TRY(ftg::launch_clear_report(ws->counters, 1, ws->echo, ws->nplan, ws->aux, 1,
                                          stream));
     if (d.dtype == FTGEMM_F64) {
-        HIP_TRY(ftg::launch_f64(g, ta, tb, d.abft != 0, stream));
+        HIP_TRY(ftg::launch_f64(g, ta, tb, d.abft != 0, stream, d.abft == 4));
         if (nslices > 1) {
             ftg::ReduceArgs r{};
             r.C = (double *)d.C;
@@ -1173,8 +1175,8 @@ ftgemm_status run_noalloc(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStre
         return FTGEMM_OK;
     }
     // the one-sided and unfused modes need workspace that grows with the
-    // problem
-    if (d.abft == 2 || d.abft == 3) return FTGEMM_ERR_UNSUPPORTED;
+    // problem; the weighted mode is for single calls
+    if (d.abft >= 2) return FTGEMM_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
     const int nplan = d.abft ? (int)g_plan.size() : 0;
     if (nplan > kNoAllocPlan) {
@@ -1305,7 +1307,8 @@ ftgemm_status ftgemm_set_fault_plan(const ftgemm_injection *plan, int32_t n)
         const ftgemm_injection &f = plan[q];
         const bool ok_mode = f.mode == FTGEMM_INJ_ADD || f.mode == FTGEMM_INJ_BITFLIP;
         const bool ok_tgt = f.target == FTGEMM_TGT_ACC || f.target == FTGEMM_TGT_ROW_CHECKSUM ||
-                            f.target == FTGEMM_TGT_COL_CHECKSUM;
+                            f.target == FTGEMM_TGT_COL_CHECKSUM ||
+                            f.target == FTGEMM_TGT_WEIGHTED_CHECKSUM;
         const bool ok_bit = f.mode != FTGEMM_INJ_BITFLIP || (f.bit >= 0 && f.bit < 64);
         const bool ok_ck = f.target == FTGEMM_TGT_ACC || f.mode == FTGEMM_INJ_ADD;
         if (!ok_mode || !ok_tgt || !ok_bit || !ok_ck || f.row < 0 || f.col < 0 ||
@@ -1358,17 +1361,17 @@ ftgemm_status ftgemm_query_tiling_ex(const ftgemm_gemm_desc *desc, int32_t *tm, 
     const ftgemm_gemm_desc &d = *desc;
     if (d.dtype != FTGEMM_F64 && d.dtype != FTGEMM_BF16 && d.dtype != FTGEMM_FP8_E4M3)
         return invalid(1);
-    if (d.abft < 0 || d.abft > 3) return invalid(1);
+    if (d.abft < 0 || d.abft > 4) return invalid(1);
     if (d.m < 0 || d.n < 0 || d.k < 0) return invalid(1);
     if (!tm || !tn || !bk || !split_k) return invalid(2);
     if (d.abft == 2 && d.dtype == FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
-    if (d.abft == 3 && d.dtype != FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
+    if (d.abft >= 3 && d.dtype != FTGEMM_F64) return FTGEMM_ERR_UNSUPPORTED;
     int a = 0, b = 0, c = 0;
     int64_t slice_k = d.k;
     int s = 1;
     if (d.dtype == FTGEMM_F64) {
         ftg::tiling_f64(&a, &b, &c);
-        s = choose_split(d.m, d.n, d.k, a, b, c, &slice_k);
+        if (d.abft != 4) s = choose_split(d.m, d.n, d.k, a, b, c, &slice_k);
     } else {
         lp_tiling(d, &a, &b, &c);
     }

@@ -8,7 +8,10 @@
 namespace ftg {
 
 // FP64 tile kernel (one 128 x 128 output tile per workgroup).
-hipError_t launch_f64(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream);
+// weighted: the weighted mode (also a weighted row checksum per column;
+// never splits the inner dimension)
+hipError_t launch_f64(const GemmArgs &g, bool ta, bool tb, bool abft, hipStream_t stream,
+                      bool weighted = false);
 void tiling_f64(int *tm, int *tn, int *bk);
 
 // BF16 / FP8 E4M3 tile kernel (FP32 accumulation and output, one tm x 128

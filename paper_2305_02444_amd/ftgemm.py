@@ -23,7 +23,7 @@ F64, BF16, FP8_E4M3 = 0, 1, 2
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NO_MEMORY = 0, 1, 2, 3, 4
 KIND_CORRECTED, KIND_CHECKSUM_ONLY, KIND_RECOMPUTED, KIND_UNCORRECTABLE = 1, 2, 3, 4
 INJ_ADD, INJ_BITFLIP = 0, 1
-TGT_ACC, TGT_ROW_CHECKSUM, TGT_COL_CHECKSUM = 0, 1, 2
+TGT_ACC, TGT_ROW_CHECKSUM, TGT_COL_CHECKSUM, TGT_WEIGHTED_CHECKSUM = 0, 1, 2, 3
 
 
 class FaultRecord(C.Structure):
@@ -237,7 +237,8 @@ def make_desc(A, B, Cm, alpha=1.0, beta=0.0, transA=False, transB=False, abft=Tr
     d.dtype = _dtype_code(A) if dtype is None else dtype
     d.transA = OP_T if transA else OP_N
     d.transB = OP_T if transB else OP_N
-    # abft: False / True, or the mode number (0, 1, 2 = one-sided, 3 = unfused)
+    # abft: False / True, or the mode number (0, 1, 2 = one-sided, 3 = unfused,
+    # 4 = weighted)
     d.abft = int(abft) if not isinstance(abft, bool) else (1 if abft else 0)
     d.m, d.n, d.k = m, n, k
     d.lda, d.ldb, d.ldc = _ld(A), _ld(B), _ld(Cm)

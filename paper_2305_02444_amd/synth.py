@@ -28,7 +28,7 @@ STREAM_A, STREAM_B, STREAM_C, STREAM_PLAN, STREAM_SHAPES = 0, 1, 2, 3, 4
 # Fault modes / targets (the library and the oracle each define the same
 # numbering for their own structures).
 ADD, BITFLIP = 0, 1
-TGT_ACC, TGT_ROW_CHECKSUM, TGT_COL_CHECKSUM = 0, 1, 2
+TGT_ACC, TGT_ROW_CHECKSUM, TGT_COL_CHECKSUM, TGT_WEIGHTED_CHECKSUM = 0, 1, 2, 3
 
 E4M3_MAX = 448.0
 
@@ -128,11 +128,11 @@ def additive_plan(g, m, n, k, tm, tn, count, magnitude):
     return plan
 
 
-def crossing_pairs_plan(g, m, n, k, tm, tn, count, magnitude):
+def crossing_pairs_plan(g, m, n, k, tm, tn, count, magnitude, equal=False):
     """Two faults in each of count distinct tiles, in different rows and
     different columns of the tile (tiles with a single row or column are
     skipped); magnitude(g) draws each delta, redrawn until the two differ
-    by more than 1 in 1000."""
+    by more than 1 in 1000 -- or, with equal, one delta for both."""
     tm_ = -(-m // tm)
     tn_ = -(-n // tn)
     plan = []
@@ -143,8 +143,8 @@ def crossing_pairs_plan(g, m, n, k, tm, tn, count, magnitude):
         rows = g.choice(h, size=2, replace=False)
         cols = g.choice(w, size=2, replace=False)
         d1 = float(magnitude(g))
-        d2 = float(magnitude(g))
-        while abs(d1 - d2) <= 1e-3 * max(abs(d1), abs(d2)):
+        d2 = d1 if equal else float(magnitude(g))
+        while not equal and abs(d1 - d2) <= 1e-3 * max(abs(d1), abs(d2)):
             d2 = float(magnitude(g))
         for r, c, d in ((rows[0], cols[0], d1), (rows[1], cols[1], d2)):
             plan.append(Fault(ti * tm + int(r), tj * tn + int(c), int(g.integers(0, max(k, 1))),

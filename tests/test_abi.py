@@ -60,14 +60,14 @@ def test_gemm_ex_descriptor_checks():
 
 
 def test_abft_modes_checked_on_the_host():
-    """abft outside 0..3 is an argument error; the one-sided mode (2) is
-    refused for FP64, the unfused mode (3) for BF16 and FP8, and both in
-    batches, before anything runs."""
+    """abft outside 0..4 is an argument error; the one-sided mode (2) is
+    refused for FP64, the unfused (3) and weighted (4) modes for BF16 and
+    FP8, and all three in batches, before anything runs."""
     L = F.lib()
     d = F.GemmDesc()
     d.dtype, d.m, d.n, d.k, d.lda, d.ldb, d.ldc = F.BF16, 4, 4, 4, 4, 4, 4
     d.alpha, d.scaleA, d.scaleB, d.A, d.B, d.C = 1.0, 1.0, 1.0, 1, 1, 1
-    for bad in (-1, 4, 7):
+    for bad in (-1, 5, 7):
         d.abft = bad
         assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
         assert L.ftgemm_last_invalid_arg() == 14
@@ -79,6 +79,12 @@ def test_abft_modes_checked_on_the_host():
     assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_UNSUPPORTED
     d.dtype = F.F64
     assert L.ftgemm_gemm_batched(1, C.byref(d), None, None) == F.ERR_UNSUPPORTED
+    d.abft = 4
+    assert L.ftgemm_gemm_batched(1, C.byref(d), None, None) == F.ERR_UNSUPPORTED
+    d.dtype = F.BF16
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_UNSUPPORTED
+    d.dtype = F.FP8_E4M3
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_UNSUPPORTED
 
 
 def test_query_tiling_ex():
@@ -103,7 +109,12 @@ def test_query_tiling_ex():
     d.dtype, d.abft = F.F64, 3
     assert L.ftgemm_query_tiling_ex(C.byref(d), *[C.byref(x) for x in v]) == F.OK
     assert [x.value for x in v] == list(F.query_tiling(F.F64, 64, 64, 64))
-    d.abft = 5
+    # the weighted mode never splits the inner dimension
+    assert F.query_tiling(F.F64, 1024, 1024, 32768)[3] > 1
+    assert F.query_tiling_ex(F.F64, 1024, 1024, 32768, abft=4) == (128, 128, 32, 1)
+    d.dtype, d.abft = F.BF16, 4
+    assert L.ftgemm_query_tiling_ex(C.byref(d), *[C.byref(x) for x in v]) == F.ERR_UNSUPPORTED
+    d.dtype, d.abft = F.F64, 5
     assert L.ftgemm_query_tiling_ex(C.byref(d), *[C.byref(x) for x in v]) == F.ERR_INVALID_ARG
     d.abft = 1
     assert L.ftgemm_query_tiling_ex(C.byref(d), None, None, None, None) == F.ERR_INVALID_ARG
@@ -116,6 +127,12 @@ def test_fault_plan_validation():
     assert L.ftgemm_set_fault_plan(C.byref(bad), 1) == F.ERR_INVALID_ARG
     bad = F.Injection(0, F.INJ_BITFLIP, F.TGT_ROW_CHECKSUM, 3, 1, 1, 1, 0.0)
     assert L.ftgemm_set_fault_plan(C.byref(bad), 1) == F.ERR_INVALID_ARG
+    bad = F.Injection(0, F.INJ_BITFLIP, F.TGT_WEIGHTED_CHECKSUM, 3, 1, 1, 1, 0.0)
+    assert L.ftgemm_set_fault_plan(C.byref(bad), 1) == F.ERR_INVALID_ARG
+    bad = F.Injection(0, F.INJ_ADD, 4, 0, 1, 1, 1, 1.0)
+    assert L.ftgemm_set_fault_plan(C.byref(bad), 1) == F.ERR_INVALID_ARG
+    ok = F.Injection(0, F.INJ_ADD, F.TGT_WEIGHTED_CHECKSUM, 0, 1, 1, 1, 2.0)
+    assert L.ftgemm_set_fault_plan(C.byref(ok), 1) == F.OK
     bad = F.Injection(0, F.INJ_BITFLIP, F.TGT_ACC, 64, 1, 1, 1, 0.0)
     assert L.ftgemm_set_fault_plan(C.byref(bad), 1) == F.ERR_INVALID_ARG
     assert L.ftgemm_set_fault_plan(None, -1) == F.ERR_INVALID_ARG
