@@ -65,7 +65,7 @@ struct Epi {
     double tau_row[TM], tau_col[TN];
     double d_row[TM], d_col[TN];
     // weighted mode: weighted row checksums of the columns (weights i + 1)
-    double enc_colw[NW][TN];                    // product part, partials
+    double enc_colw[NT / TN][TN];               // product part, partials
     double ref_colw[WM][TN], cin_colw[WM][TN], cin2_colw[WM][TN];
     double fin_colw[TN], tau_colw[TN], d_colw[TN];
 };
@@ -75,12 +75,15 @@ struct Smem {
         Stage st[2];
         Epi epi;
     } u;
-    double xs[2][BK][NW];  // [buffer][p][partial]: column sums of the A tile
+    // [buffer][p][partial]: column sums of the A tile (weighted mode, A not
+    // transposed: the weighted sum in slot 1)
+    alignas(16) double xs[2][BK][NW];
     double ys[2][BK][NW];  // [buffer][p][partial]: row sums of the B tile
     double xws[2][BK][NW]; // weighted mode: weighted column sums of the A tile
     double red[NW][2];
     double vnrm[2][BK];    // x_p^2, y_p^2 summed over the steps (slot per p)
     double vnrmw[BK];      // weighted mode: x'_p^2 summed over the steps
+    alignas(16) double xfin[BK][2];  // weighted mode, A transposed: x_p, x'_p of the step
     double scal[6];        // |x|^2, |y|^2, |A_I|_F^2, |B_J|_F^2, |W A_I|_F^2, |x'|^2
     TileFault faults[kMaxTileFaults];
     int nfaults;
@@ -160,7 +163,9 @@ struct OpLoader {
     // its p: the full tile sum for kContig (the 16 lanes of one DPP row), a
     // per-wave partial otherwise (lanes l and l^32).  The result goes to
     // dst[p][slot]: slot 0 for kContig, the wave index otherwise.
-    __device__ __forceinline__ void sum_to(const double v[EPT], double (*dst)[NW]) const
+    // Returns what this thread summed (for kContig, every thread of the p
+    // has the full sum).
+    __device__ __forceinline__ double sum_to(const double v[EPT], double (*dst)[NW]) const
     {
         double s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
         if (kContig) {
@@ -170,21 +175,25 @@ struct OpLoader {
             s = pair_sum32(s);
             if ((t & 63) < 32) dst[t & 31][t >> 6] = s;
         }
+        return s;
     }
     // The same with every element weighted by its outer index + 1 (the
-    // weighted mode's x'_p = sum_i (i + 1) A(i, p)).
-    __device__ __forceinline__ void wsum_to(const double v[EPT], double (*dst)[NW]) const
+    // weighted mode's x'_p = sum_i (i + 1) A(i, p)), into slot `slot` for
+    // kContig (slot 1 sits beside x_p, so one read fetches both).
+    __device__ __forceinline__ double wsum_to(const double v[EPT], double (*dst)[NW],
+                                              int slot) const
     {
         double s = 0.0;
 #pragma unroll
         for (int r = 0; r < EPT; ++r) s = fma((double)(o(r) + 1), v[r], s);
         if (kContig) {
             s = sum16(s);
-            if ((t & 15) == 0) dst[t >> 4][0] = s;
+            if ((t & 15) == 0) dst[t >> 4][slot] = s;
         } else {
             s = pair_sum32(s);
             if ((t & 63) < 32) dst[t & 31][t >> 6] = s;
         }
+        return s;
     }
     // Per-outer-index partials accumulated by this thread over the steps,
     // completed across the threads that hold the same outer indices (the
@@ -250,6 +259,9 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
     // B transposed: its columns (j) do.
     OpLoader<!TA> la;
     OpLoader<TB> lb;
+    // weighted mode with A's partial sums spread over the waves: finished
+    // once per step behind a second barrier
+    constexpr bool kFinish = WGT && OpLoader<!TA>::kParts > 1;
     la.init((const double *)g.A, g.lda, TA ? k : m, TA ? m : k, t);
     lb.init((const double *)g.B, g.ldb, TB ? n : k, TB ? k : n, t);
     // Staged operand registers of one step.
@@ -267,9 +279,19 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
             sm.u.st[buf].B[b_p][phys(lb.o(r))] = rb[r];
         }
     };
-    auto sums = [&](int buf) {
-        la.sum_to(ra, sm.xs[buf]);
-        if (WGT) la.wsum_to(ra, sm.xws[buf]);
+    // (weighted mode, A not transposed: the squares of the step's x_p and
+    // x'_p of this thread's p go into vx, vxw)
+    auto sums = [&](int buf, float &vx, float &vxw) {
+        const double x = la.sum_to(ra, sm.xs[buf]);
+        if (WGT) {
+            const double xw = kFinish ? la.wsum_to(ra, sm.xws[buf], 0)
+                                      : la.wsum_to(ra, sm.xs[buf], 1);
+            if (!kFinish) {
+                const float fx = (float)x, fw = (float)xw;
+                vx = fmaf(fx, fx, vx);
+                vxw = fmaf(fw, fw, vxw);
+            }
+        }
         lb.sum_to(rb, sm.ys[buf]);
     };
 
@@ -301,14 +323,19 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         // outer indices (rows of A in the A loader, columns of B in the B one).
         // The norms only scale the rounding-error threshold, so FP32 is ample
         // for them (and halves their registers).
-        double enc_a[EPT] = {}, enc_b[EPT] = {};
-        double enc_bw[WGT ? EPT : 1] = {};  // weighted mode: x' . B partials
-        float nrm_a[EPT] = {}, nrm_b[EPT] = {};
+        double enc_a[EPT] = {}, enc_b[WGT ? 1 : EPT] = {};
+        // The weighted mode takes the B side from the staged B tile in LDS
+        // instead (one register per sum instead of one per staged element,
+        // which leaves room for the weighted sums): thread t covers column
+        // j = t mod 128 and a quarter of each step's p, and sums x_p B(p, j),
+        // x'_p B(p, j), B(p, j)^2, x_p^2 and x'_p^2 there.
+        double enc_w = 0.0;
+        float vxw = 0.0f;
+        float nrm_a[EPT] = {}, nrm_b[WGT ? 1 : EPT] = {};
         float vx = 0.0f, vy = 0.0f;  // x_p^2, y_p^2 over the steps, for this thread's p
-        float vxw = 0.0f;            // weighted mode: x'_p^2
 
         load(0);
-        if (ABFT) sums(0);
+        if (ABFT) sums(0, vx, vxw);
         // The steps run in segments that end where a planned fault lands, so
         // the fault hook sits outside the hot loop.
         int s = 0;
@@ -326,14 +353,25 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                 const int buf = s & 1;
                 store(buf);
                 __syncthreads();
+                if constexpr (kFinish) {
+                    // x_p and x'_p of the step summed once from their wave
+                    // partials (each thread reads eight p per step)
+                    if (t < BK) {
+                        const double x = gather<NW>(sm.xs[buf], t);
+                        const double xw = gather<NW>(sm.xws[buf], t);
+                        sm.xfin[t][0] = x;
+                        sm.xfin[t][1] = xw;
+                        const float fx = (float)x, fw = (float)xw;
+                        vx = fmaf(fx, fx, vx);
+                        vxw = fmaf(fw, fw, vxw);
+                    }
+                    __syncthreads();
+                }
                 // x_p, y_p of step s are complete; their gather is issued
                 // here and used after the step's first products
-                double yv = 0.0, xv = 0.0, xwv = 0.0;
-                if (ABFT) {
-                    yv = gather<OpLoader<TB>::kParts>(sm.ys[buf], la.p());
-                    xv = gather<OpLoader<!TA>::kParts>(sm.xs[buf], lb.p());
-                }
-                if (WGT) xwv = gather<OpLoader<!TA>::kParts>(sm.xws[buf], lb.p());
+                double yv = 0.0, xv = 0.0;
+                if (ABFT) yv = gather<OpLoader<TB>::kParts>(sm.ys[buf], la.p());
+                if (ABFT && !WGT) xv = gather<OpLoader<!TA>::kParts>(sm.xs[buf], lb.p());
 #pragma unroll
                 for (int kk = 0; kk < BK / 4; ++kk) {
                     if (kk == (ABFT ? 1 : 0)) {
@@ -343,23 +381,35 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
 #pragma unroll
                             for (int r = 0; r < EPT; ++r) {
                                 enc_a[r] += ra[r] * yv;
-                                enc_b[r] += xv * rb[r];
-                                if (WGT) enc_bw[r] += xwv * rb[r];
                                 // squares of the FP32-rounded values: two
                                 // instructions (convert, FP32 fma)
-                                const float fa = (float)ra[r], fb = (float)rb[r];
+                                const float fa = (float)ra[r];
                                 nrm_a[r] = fmaf(fa, fa, nrm_a[r]);
-                                nrm_b[r] = fmaf(fb, fb, nrm_b[r]);
+                                if constexpr (!WGT) {
+                                    enc_b[r] += xv * rb[r];
+                                    const float fb = (float)rb[r];
+                                    nrm_b[r] = fmaf(fb, fb, nrm_b[r]);
+                                }
                             }
-                            const float fy = (float)yv, fx = (float)xv;
+                            const float fy = (float)yv;
                             vy = fmaf(fy, fy, vy);
-                            vx = fmaf(fx, fx, vx);
-                            if (WGT) {
-                                const float fxw = (float)xwv;
-                                vxw = fmaf(fxw, fxw, vxw);
+                            if (!WGT) {
+                                const float fx = (float)xv;
+                                vx = fmaf(fx, fx, vx);
                             }
                         }
                         if (s + 1 < nsteps) load(s + 1);
+                    }
+                    if (WGT) {
+                        // one p of this thread's quarter per sub-step
+                        const int pw = (t / TN) * (BK / 4) + kk;
+                        const double bv = sm.u.st[buf].B[pw][phys(t & (TN - 1))];
+                        const double2 xq = *reinterpret_cast<const double2 *>(
+                            kFinish ? &sm.xfin[pw][0] : &sm.xs[buf][pw][0]);
+                        enc_b[0] = fma(xq.x, bv, enc_b[0]);
+                        enc_w = fma(xq.y, bv, enc_w);
+                        const float fb = (float)bv;
+                        nrm_b[0] = fmaf(fb, fb, nrm_b[0]);
                     }
                     double fa[4], fb[2];
 #pragma unroll
@@ -377,7 +427,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                     if (ABFT && kk == BK / 4 - 1 && s + 1 < nsteps) {
                         // operand checksums of step s + 1, published before
                         // its barrier
-                        sums(buf ^ 1);
+                        sums(buf ^ 1, vx, vxw);
                     }
                 }
             }
@@ -445,13 +495,24 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         // accounts for it.  The A loader's p gathers y, the B loader's x.
         la.partials_to(enc_a, sm.u.epi.enc_row);
         la.partials_to(nrm_a, sm.u.epi.nrm_row);
-        lb.partials_to(enc_b, sm.u.epi.enc_col);
-        lb.partials_to(nrm_b, sm.u.epi.nrm_col);
         if (la.first_of_p()) sm.vnrm[1][la.p()] = (double)vy;
-        if (lb.first_of_p()) sm.vnrm[0][lb.p()] = (double)vx;
-        if (WGT) {
-            lb.partials_to(enc_bw, sm.u.epi.enc_colw);
-            if (lb.first_of_p()) sm.vnrmw[lb.p()] = (double)vxw;
+        if constexpr (!WGT) {
+            lb.partials_to(enc_b, sm.u.epi.enc_col);
+            lb.partials_to(nrm_b, sm.u.epi.nrm_col);
+            if (lb.first_of_p()) sm.vnrm[0][lb.p()] = (double)vx;
+        } else {
+            // one partial per quarter of p; the squares of x_p and x'_p from
+            // the threads that summed them (one per p)
+            const int jw = t & (TN - 1), qw = t / TN;
+            sm.u.epi.enc_col[qw][jw] = enc_b[0];
+            sm.u.epi.nrm_col[qw][jw] = (double)nrm_b[0];
+            sm.u.epi.enc_colw[qw][jw] = enc_w;
+            const bool own = kFinish ? t < BK : la.first_of_p();
+            const int pv = kFinish ? t : la.p();
+            if (own) {
+                sm.vnrm[0][pv] = (double)vx;
+                sm.vnrmw[pv] = (double)vxw;
+            }
         }
 
         // Beta pass fused with the C_in part of the encoding (Section 2.2)
@@ -532,8 +593,9 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
             sm.u.epi.fin_row[x] = e;
         } else if (is_col) {
             double e = 0, nr = 0, ew = 0;
+            constexpr int parts = WGT ? NT / TN : OpLoader<TB>::kOuterParts;
 #pragma unroll
-            for (int v = 0; v < OpLoader<TB>::kOuterParts; ++v) {
+            for (int v = 0; v < parts; ++v) {
                 e += sm.u.epi.enc_col[v][x];
                 nr += sm.u.epi.nrm_col[v][x];
                 if (WGT) ew += sm.u.epi.enc_colw[v][x];
