@@ -22,7 +22,12 @@
  *   - Matrices are column-major (BLAS).  op(X) = X for FTGEMM_OP_N and X^T
  *     for FTGEMM_OP_T.  op(A) is m x k, op(B) is k x n, C is m x n.
  *     lda >= max(1, transA == N ? m : k), ldb >= max(1, transB == N ? k : n),
- *     ldc >= max(1, m).
+ *     ldc >= max(1, m).  The kernels address what one tile reads in one
+ *     inner-dimension step of an operand (and, for F64, the tile's part of
+ *     C) with 32-bit offsets, so a leading dimension that makes it span
+ *     2 GiB or more is refused as invalid (for F64 about 2.1 million
+ *     elements for the operand whose tile spans 128 stored columns, and
+ *     for ldc; see the library's argument check).
  *   - A, B and C are device pointers owned by the caller; C is read (unless
  *     beta == 0) and written.  Nothing is retained after the call returns.
  *   - Calls are asynchronous on `stream` (a hipStream_t; NULL is the

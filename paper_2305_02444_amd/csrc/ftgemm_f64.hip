@@ -26,6 +26,8 @@
 #include "ftgemm_device.h"
 #include "ftgemm_kernels.h"
 
+#include <type_traits>
+
 namespace ftg {
 namespace f64 {
 
@@ -231,6 +233,38 @@ __device__ __forceinline__ double gather(const double (*src)[NW], int p)
            ((src[p][4] + src[p][5]) + (src[p][6] + src[p][7]));
 }
 
+// C_in for the beta pass, read through a buffer resource that starts at the
+// tile and ends with C, so what lies past C's last element reads as 0; rows
+// and columns past the tile's own inside C are read and must be dropped by
+// the caller.  Offsets are 32-bit: the host limits ldc so that a tile spans
+// less than 2 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t cin_rsrc(const double *C, int64_t ldc,
+                                                           int64_t m, int64_t n, int64_t i0,
+                                                           int64_t j0)
+{
+    const int64_t first = i0 + j0 * ldc;
+    int64_t ext = (ldc * (n - 1) + m - first) * 8;
+    if (ext < 0) ext = 0;
+    if (ext > 0x7FFFFFFF) ext = 0x7FFFFFFF;
+    return make_rsrc(C + first, (uint64_t)ext);
+}
+
+// The C_in elements under this thread's accumulators of row group mi (acc
+// layout).  The beta passes fetch group mi + 1 before they work on group mi,
+// so one group's wait overlaps the previous group's work.
+__device__ __forceinline__ void load_cin(__amdgpu_buffer_rsrc_t rs, int64_t ldc, int mi, int wm,
+                                         int wn, int q, int c16, double cv[2][4])
+{
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = wm * 64 + 16 * mi + 4 * r + q;
+            const int col = wn * 32 + 16 * ni + c16;
+            cv[ni][r] = buf_load_f64(rs, (uint32_t)((row + (int64_t)col * ldc) * 8));
+        }
+}
+
 // owner of tile element (row, col): wave, lane and flat register index
 __device__ __forceinline__ int owner_wave(int row, int col) { return (row >> 6) + 2 * (col >> 5); }
 __device__ __forceinline__ int owner_lane(int row, int col) { return 16 * (row & 3) + (col & 15); }
@@ -336,80 +370,29 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
 
         load(0);
         if (ABFT) sums(0, vx, vxw);
-        // The steps run in segments that end where a planned fault lands, so
-        // the fault hook sits outside the hot loop.
-        int s = 0;
-#pragma unroll 1
-        while (s < nsteps) {
-            int stop = nsteps - 1;
-            if (faults_on)
-                for (int f = 0; f < nf; ++f) {
-                    const int fs = sm.faults[f].kstep;
-                    if (sm.faults[f].target == FTGEMM_TGT_ACC && fs >= s && fs < stop)
-                        stop = fs;
-                }
-#pragma unroll 1
-            for (; s <= stop; ++s) {
+        if constexpr (!ABFT) {
+            // Checksum-free steps: those with a next step, then the last one,
+            // which fetches the beta pass's first two row groups of C_in into
+            // the free operand registers instead (measured faster for this
+            // kernel; the fault-tolerant loop below measured slower with the
+            // same split).
+            auto pstep = [&](const int s, auto last) {
+                constexpr bool kLast = decltype(last)::value;
                 const int buf = s & 1;
                 store(buf);
                 __syncthreads();
-                if constexpr (kFinish) {
-                    // x_p and x'_p of the step summed once from their wave
-                    // partials (each thread reads eight p per step)
-                    if (t < BK) {
-                        const double x = gather<NW>(sm.xs[buf], t);
-                        const double xw = gather<NW>(sm.xws[buf], t);
-                        sm.xfin[t][0] = x;
-                        sm.xfin[t][1] = xw;
-                        const float fx = (float)x, fw = (float)xw;
-                        vx = fmaf(fx, fx, vx);
-                        vxw = fmaf(fw, fw, vxw);
-                    }
-                    __syncthreads();
-                }
-                // x_p, y_p of step s are complete; their gather is issued
-                // here and used after the step's first products
-                double yv = 0.0, xv = 0.0;
-                if (ABFT) yv = gather<OpLoader<TB>::kParts>(sm.ys[buf], la.p());
-                if (ABFT && !WGT) xv = gather<OpLoader<!TA>::kParts>(sm.xs[buf], lb.p());
 #pragma unroll
                 for (int kk = 0; kk < BK / 4; ++kk) {
-                    if (kk == (ABFT ? 1 : 0)) {
-                        if (ABFT) {
-                            // the encoded checksums and norms of step s,
-                            // before ra/rb take step s + 1
-#pragma unroll
-                            for (int r = 0; r < EPT; ++r) {
-                                enc_a[r] += ra[r] * yv;
-                                // squares of the FP32-rounded values: two
-                                // instructions (convert, FP32 fma)
-                                const float fa = (float)ra[r];
-                                nrm_a[r] = fmaf(fa, fa, nrm_a[r]);
-                                if constexpr (!WGT) {
-                                    enc_b[r] += xv * rb[r];
-                                    const float fb = (float)rb[r];
-                                    nrm_b[r] = fmaf(fb, fb, nrm_b[r]);
-                                }
-                            }
-                            const float fy = (float)yv;
-                            vy = fmaf(fy, fy, vy);
-                            if (!WGT) {
-                                const float fx = (float)xv;
-                                vx = fmaf(fx, fx, vx);
-                            }
+                    if (kk == 0) {
+                        if constexpr (!kLast) {
+                            load(s + 1);
+                        } else if (use_c) {
+                            const __amdgpu_buffer_rsrc_t crs = cin_rsrc(C, ldc, m, n, i0, j0);
+                            load_cin(crs, ldc, 0, wm, wn, q, c16,
+                                     reinterpret_cast<double (*)[4]>(ra));
+                            load_cin(crs, ldc, 1, wm, wn, q, c16,
+                                     reinterpret_cast<double (*)[4]>(rb));
                         }
-                        if (s + 1 < nsteps) load(s + 1);
-                    }
-                    if (WGT) {
-                        // one p of this thread's quarter per sub-step
-                        const int pw = (t / TN) * (BK / 4) + kk;
-                        const double bv = sm.u.st[buf].B[pw][phys(t & (TN - 1))];
-                        const double2 xq = *reinterpret_cast<const double2 *>(
-                            kFinish ? &sm.xfin[pw][0] : &sm.xs[buf][pw][0]);
-                        enc_b[0] = fma(xq.x, bv, enc_b[0]);
-                        enc_w = fma(xq.y, bv, enc_w);
-                        const float fb = (float)bv;
-                        nrm_b[0] = fmaf(fb, fb, nrm_b[0]);
                     }
                     double fa[4], fb[2];
 #pragma unroll
@@ -424,39 +407,142 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                         for (int ni = 0; ni < 2; ++ni)
                             acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(
                                 fa[mi], fb[ni], acc[mi][ni], 0, 0, 0);
-                    if (ABFT && kk == BK / 4 - 1 && s + 1 < nsteps) {
-                        // operand checksums of step s + 1, published before
-                        // its barrier
-                        sums(buf ^ 1, vx, vxw);
+                }
+            };
+#pragma unroll 1
+            for (int s = 0; s < nsteps - 1; ++s) pstep(s, std::false_type{});
+            if (nsteps > 0) pstep(nsteps - 1, std::true_type{});
+        } else {
+            // The steps run in segments that end where a planned fault lands, so
+            // the fault hook sits outside the hot loop.
+            int s = 0;
+    #pragma unroll 1
+            while (s < nsteps) {
+                int stop = nsteps - 1;
+                if (faults_on)
+                    for (int f = 0; f < nf; ++f) {
+                        const int fs = sm.faults[f].kstep;
+                        if (sm.faults[f].target == FTGEMM_TGT_ACC && fs >= s && fs < stop)
+                            stop = fs;
+                    }
+    #pragma unroll 1
+                for (; s <= stop; ++s) {
+                    const int buf = s & 1;
+                    store(buf);
+                    __syncthreads();
+                    if constexpr (kFinish) {
+                        // x_p and x'_p of the step summed once from their wave
+                        // partials (each thread reads eight p per step)
+                        if (t < BK) {
+                            const double x = gather<NW>(sm.xs[buf], t);
+                            const double xw = gather<NW>(sm.xws[buf], t);
+                            sm.xfin[t][0] = x;
+                            sm.xfin[t][1] = xw;
+                            const float fx = (float)x, fw = (float)xw;
+                            vx = fmaf(fx, fx, vx);
+                            vxw = fmaf(fw, fw, vxw);
+                        }
+                        __syncthreads();
+                    }
+                    // x_p, y_p of step s are complete; their gather is issued
+                    // here and used after the step's first products.  In the
+                    // weighted mode, waves 4-7 encode, and fetch the next
+                    // step, three sub-steps after waves 0-3, so that the
+                    // vector work of the two waves a SIMD holds (waves dealt
+                    // round-robin) does not coincide (measured: 14% faster
+                    // there; the plain two-sided mode measured 1% slower
+                    // with it at 8192^3).
+                    const int enc_kk =
+                        WGT && __builtin_amdgcn_readfirstlane(threadIdx.x >> 8) ? 4 : 1;
+                    double yv = 0.0, xv = 0.0;
+                    if (ABFT) yv = gather<OpLoader<TB>::kParts>(sm.ys[buf], la.p());
+                    if (ABFT && !WGT) xv = gather<OpLoader<!TA>::kParts>(sm.xs[buf], lb.p());
+    #pragma unroll
+                    for (int kk = 0; kk < BK / 4; ++kk) {
+                        if (kk == (ABFT ? enc_kk : 0)) {
+                            if (ABFT) {
+                                // the encoded checksums and norms of step s,
+                                // before ra/rb take step s + 1
+    #pragma unroll
+                                for (int r = 0; r < EPT; ++r) {
+                                    enc_a[r] += ra[r] * yv;
+                                    // squares of the FP32-rounded values: two
+                                    // instructions (convert, FP32 fma)
+                                    const float fa = (float)ra[r];
+                                    nrm_a[r] = fmaf(fa, fa, nrm_a[r]);
+                                    if constexpr (!WGT) {
+                                        enc_b[r] += xv * rb[r];
+                                        const float fb = (float)rb[r];
+                                        nrm_b[r] = fmaf(fb, fb, nrm_b[r]);
+                                    }
+                                }
+                                const float fy = (float)yv;
+                                vy = fmaf(fy, fy, vy);
+                                if (!WGT) {
+                                    const float fx = (float)xv;
+                                    vx = fmaf(fx, fx, vx);
+                                }
+                            }
+                            if (s + 1 < nsteps) load(s + 1);
+                        }
+                        if (WGT) {
+                            // one p of this thread's quarter per sub-step
+                            const int pw = (t / TN) * (BK / 4) + kk;
+                            const double bv = sm.u.st[buf].B[pw][phys(t & (TN - 1))];
+                            const double2 xq = *reinterpret_cast<const double2 *>(
+                                kFinish ? &sm.xfin[pw][0] : &sm.xs[buf][pw][0]);
+                            enc_b[0] = fma(xq.x, bv, enc_b[0]);
+                            enc_w = fma(xq.y, bv, enc_w);
+                            const float fb = (float)bv;
+                            nrm_b[0] = fmaf(fb, fb, nrm_b[0]);
+                        }
+                        double fa[4], fb[2];
+    #pragma unroll
+                        for (int mi = 0; mi < 4; ++mi)
+                            fa[mi] = sm.u.st[buf].A[4 * kk + q][phys(wm * 64 + 16 * mi + c16)];
+    #pragma unroll
+                        for (int ni = 0; ni < 2; ++ni)
+                            fb[ni] = sm.u.st[buf].B[4 * kk + q][phys(wn * 32 + 16 * ni + c16)];
+    #pragma unroll
+                        for (int mi = 0; mi < 4; ++mi)
+    #pragma unroll
+                            for (int ni = 0; ni < 2; ++ni)
+                                acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                    fa[mi], fb[ni], acc[mi][ni], 0, 0, 0);
+                        if (ABFT && kk == BK / 4 - 1 && s + 1 < nsteps) {
+                            // operand checksums of step s + 1, published before
+                            // its barrier
+                            sums(buf ^ 1, vx, vxw);
+                        }
                     }
                 }
-            }
-            if (ABFT && faults_on) {
-                // Fault hook: accumulator faults land after step `stop`.
-                for (int f = 0; f < nf; ++f) {
-                    const TileFault tf = sm.faults[f];
-                    if (tf.target != FTGEMM_TGT_ACC || tf.kstep != stop) continue;
-                    if (w != owner_wave(tf.row, tf.col)) continue;
-                    const int ol = owner_lane(tf.row, tf.col), sel = owner_reg(tf.row, tf.col);
-                    double before = 0.0;
-#pragma unroll
-                    for (int e = 0; e < 32; ++e)
-                        if (sel == e) before = acc[e >> 3][(e >> 2) & 1][e & 3];
-                    const double after = tf.mode == FTGEMM_INJ_ADD ? before + tf.delta
-                                                                   : flip_bit_f64(before, tf.bit);
-#pragma unroll
-                    for (int e = 0; e < 32; ++e)
-                        if (sel == e && lane == ol) acc[e >> 3][(e >> 2) & 1][e & 3] = after;
-                    if (lane == ol) {
-                        ftgemm_injection_echo ech;
-                        ech.problem = g.problem;
-                        ech.applied = 1;
-                        ech.row = i0 + tf.row;
-                        ech.col = j0 + tf.col;
-                        ech.k_index = g.plan[tf.idx].k_index;
-                        ech.before = before;
-                        ech.after = after;
-                        g.echo[tf.idx] = ech;
+                if (ABFT && faults_on) {
+                    // Fault hook: accumulator faults land after step `stop`.
+                    for (int f = 0; f < nf; ++f) {
+                        const TileFault tf = sm.faults[f];
+                        if (tf.target != FTGEMM_TGT_ACC || tf.kstep != stop) continue;
+                        if (w != owner_wave(tf.row, tf.col)) continue;
+                        const int ol = owner_lane(tf.row, tf.col), sel = owner_reg(tf.row, tf.col);
+                        double before = 0.0;
+    #pragma unroll
+                        for (int e = 0; e < 32; ++e)
+                            if (sel == e) before = acc[e >> 3][(e >> 2) & 1][e & 3];
+                        const double after = tf.mode == FTGEMM_INJ_ADD ? before + tf.delta
+                                                                       : flip_bit_f64(before, tf.bit);
+    #pragma unroll
+                        for (int e = 0; e < 32; ++e)
+                            if (sel == e && lane == ol) acc[e >> 3][(e >> 2) & 1][e & 3] = after;
+                        if (lane == ol) {
+                            ftgemm_injection_echo ech;
+                            ech.problem = g.problem;
+                            ech.applied = 1;
+                            ech.row = i0 + tf.row;
+                            ech.col = j0 + tf.col;
+                            ech.k_index = g.plan[tf.idx].k_index;
+                            ech.before = before;
+                            ech.after = after;
+                            g.echo[tf.idx] = ech;
+                        }
                     }
                 }
             }
@@ -471,8 +557,17 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
 
         if (!ABFT) {
             // Plain GEMM epilogue: the beta pass and the store.
+            // row groups 0 and 1 of C_in arrived in the operand registers;
+            // 2 and 3 are fetched while the first two are written
+            const __amdgpu_buffer_rsrc_t crs = cin_rsrc(C, ldc, m, n, i0, j0);
+            double c2[2][4] = {}, c3[2][4] = {};
 #pragma unroll
-            for (int mi = 0; mi < 4; ++mi)
+            for (int mi = 0; mi < 4; ++mi) {
+                if (use_c && mi < 2) load_cin(crs, ldc, mi + 2, wm, wn, q, c16, mi ? c3 : c2);
+                const double (*cn)[4] = mi == 0   ? reinterpret_cast<const double (*)[4]>(ra)
+                                        : mi == 1 ? reinterpret_cast<const double (*)[4]>(rb)
+                                        : mi == 2 ? c2
+                                                  : c3;
 #pragma unroll
                 for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
@@ -480,11 +575,12 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                         const int row = wm * 64 + 16 * mi + 4 * r + q;
                         const int col = wn * 32 + 16 * ni + c16;
                         if (row < hrows && col < wcols) {
-                            double *pc = C + (i0 + row) + (j0 + col) * ldc;
                             const double o = g.alpha * acc[mi][ni][r];
-                            *pc = use_c ? o + g.beta * *pc : o;
+                            C[(i0 + row) + (j0 + col) * ldc] =
+                                use_c ? o + g.beta * cn[ni][r] : o;
                         }
                     }
+            }
             return;
         }
 
@@ -517,11 +613,19 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
 
         // Beta pass fused with the C_in part of the encoding (Section 2.2)
         // and the reference sums of the output.
+        // (row group mi + 1 of C_in is fetched while group mi is summed)
+        const __amdgpu_buffer_rsrc_t crs = cin_rsrc(C, ldc, m, n, i0, j0);
+        double cn[2][4] = {}, cx[2][4] = {};
+        if (use_c) load_cin(crs, ldc, 0, wm, wn, q, c16, cn);
+        // the report's largest ratio so far, read while the tile is verified
+        unsigned long long seen = 0;
+        if (t == 0) seen = atomic_peek(&g.counters->max_ratio_bits);
         double col_o[2] = {0, 0}, col_c[2] = {0, 0}, col_c2[2] = {0, 0};
         // weighted mode: the same column sums with row weights i + 1
         double col_ow[WGT ? 2 : 1] = {}, col_cw[WGT ? 2 : 1] = {}, col_cw2[WGT ? 2 : 1] = {};
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
+        for (int mi = 0; mi < 4; ++mi) {
+            if (use_c && mi + 1 < 4) load_cin(crs, ldc, mi + 1, wm, wn, q, c16, cx);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 double row_o = 0, row_c = 0, row_c2 = 0;
@@ -530,7 +634,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                 for (int ni = 0; ni < 2; ++ni) {
                     const int col = wn * 32 + 16 * ni + c16;
                     const bool ok = row < hrows && col < wcols;
-                    const double cin = (use_c && ok) ? C[(i0 + row) + (j0 + col) * ldc] : 0.0;
+                    const double cin = (use_c && ok) ? cn[ni][r] : 0.0;
                     double o = g.alpha * acc[mi][ni][r];
                     if (use_c) o = o + g.beta * cin;
                     o = ok ? o : 0.0;
@@ -550,6 +654,11 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                     sm.u.epi.cin2_row[wn][row] = row_c2;
                 }
             }
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cn[ni][r] = cx[ni][r];
+        }
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni) {
             col_o[ni] = sum_rows(col_o[ni]);
@@ -722,9 +831,10 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         }
         __syncthreads();
         if (t == 0)
-            atomic_max_nonneg(&g.counters->max_ratio_bits,
-                              fmax(fmax(sm.wratio[0], sm.wratio[1]),
-                                   fmax(sm.wratio[2], sm.wratio[3])));
+            atomic_max_seen(&g.counters->max_ratio_bits,
+                            fmax(fmax(sm.wratio[0], sm.wratio[1]),
+                                 fmax(sm.wratio[2], sm.wratio[3])),
+                            seen);
 
         const int nr = sm.nbad_r, nc = sm.nbad_c;
         if (nr == 0 && nc == 0) {

@@ -180,8 +180,8 @@ def test_status_strings():
 
 
 def test_operand_windows_wider_than_the_loaders_reach_are_refused():
-    """A step of an operand is read through one buffer window of at most
-    2^31 - 1 bytes with 32-bit offsets.  A leading dimension that makes the
+    """A step of an operand (and, for FP64, a tile of C_in) is read through
+    one buffer window of at most 2^31 - 1 bytes with 32-bit offsets.  A leading dimension that makes the
     window wider would read zeros or wrapped addresses with no sign (the
     checksums are summed from the same staged values), so it is refused on
     the host with the operand's position; the largest leading dimension
@@ -228,10 +228,19 @@ def test_operand_windows_wider_than_the_loaders_reach_are_refused():
     d = desc(F.F64, 1, 0, 64, 64, lim // 8 + 1, lim // 8 + 1, lim // 8 + 1)
     assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
     assert L.ftgemm_last_invalid_arg() == 5
+    # the FP64 beta pass reads each tile of C_in through one window: 127 ldc
+    # + 128 elements
+    ok_c = (lim // 8 - 128) // 127
+    d = desc(F.F64, 0, 0, 512, 512, 512, 512, 512)
+    d.ldc = ok_c + 1
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 13
+    wide_c = desc(F.F64, 0, 0, 512, 512, 512, 512, 512)
+    wide_c.ldc = ok_c
     # the largest leading dimensions that fit pass the checks
     for d in (desc(F.F64, 0, 0, 512, 512, 512, ok, 512),
               desc(F.F64, 1, 1, 512, 512, 512, ok_t, ok),
-              desc(F.BF16, 1, 0, 512, 512, 512, ok_bf, 512)):
+              desc(F.BF16, 1, 0, 512, 512, 512, ok_bf, 512), wide_c):
         d.alpha, d.beta = 0.0, 1.0
         assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.OK
 
