@@ -392,11 +392,10 @@ int check_windows(const ftgemm_gemm_desc &d)
         // elements from the window's first element to the last one a step reads
         if (scols > 1 && o.ld > (lim / eb - srows) / (scols - 1)) return o.pos_ld;
     }
-    // the FP64 beta pass reads C_in through one window per tile (its 128
-    // columns of 128 rows), with 32-bit offsets
-    if (d.dtype == FTGEMM_F64 && d.n > 1 &&
-        d.ldc > (lim / 8 - 128) / (std::min<int64_t>(128, d.n) - 1))
-        return 13;
+    // the beta pass reads C_in through one window per tile (its 128
+    // columns of up to 128 FP64 or 256 FP32 rows), with 32-bit offsets
+    const int64_t ceb = d.dtype == FTGEMM_F64 ? 8 : 4;
+    if (d.n > 1 && d.ldc > (lim / ceb - outer) / (std::min<int64_t>(128, d.n) - 1)) return 13;
     return 0;
 }
 

@@ -524,6 +524,41 @@ __device__ __forceinline__ int owner_reg(int row, int col)
     return ((row & 63) >> 4) * (4 * Geo<BM>::NI) + ((col % Geo<BM>::WC) >> 4) * 4 + (row & 3);
 }
 
+// C_in for the beta pass, read through a buffer resource that starts at the
+// tile and ends with C, so what lies past C's last element reads as 0; rows
+// and columns past the tile's own inside C are read and must be dropped by
+// the caller.  Offsets are 32-bit: the host limits ldc so that a tile spans
+// less than 2 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t cin_rsrc(const float *C, int64_t ldc, int64_t m,
+                                                           int64_t n, int64_t i0, int64_t j0)
+{
+    const int64_t first = i0 + j0 * ldc;
+    int64_t ext = (ldc * (n - 1) + m - first) * 4;
+    if (ext < 0) ext = 0;
+    if (ext > 0x7FFFFFFF) ext = 0x7FFFFFFF;
+    return make_rsrc(C + first, (uint64_t)ext);
+}
+
+// The C_in elements under this thread's accumulators of row group mi (acc
+// layout).  The epilogues fetch group mi + 1 before they work on group mi,
+// so one group's wait overlaps the previous group's work (instead of one
+// wait per row).
+template <int BM>
+__device__ __forceinline__ void load_cin(__amdgpu_buffer_rsrc_t rs, int64_t ldc, int mi, int wm,
+                                         int wn, int q, int c16, float cv[Geo<BM>::NI][4])
+{
+#pragma unroll
+    for (int ni = 0; ni < Geo<BM>::NI; ++ni)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = wm * 64 + 16 * mi + 4 * q + r;
+            const int col = wn * Geo<BM>::WC + 16 * ni + c16;
+            cv[ni][r] = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(
+                           rs, (int)(uint32_t)((row + (int64_t)col * ldc) * 4), 0, 0));
+        }
+}
+
 // ONE: the one-sided mode -- only the column checksum of the tile (one
 // entry per row, C^c = C e) is encoded and verified, and any disagreement has
 // the tile computed again.  PRE (implied by ONE): the threshold norms come
@@ -877,9 +912,13 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         la.t = t;
         lb.t = t;
 
+        const __amdgpu_buffer_rsrc_t crs = cin_rsrc(C, ldc, m, n, i0, j0);
+        float cn[NI][4] = {}, cx[NI][4] = {};
+        if (use_c) load_cin<BM>(crs, ldc, 0, wm, wn, q, c16, cn);
         if (!ABFT) {
 #pragma unroll
-            for (int mi = 0; mi < 4; ++mi)
+            for (int mi = 0; mi < 4; ++mi) {
+                if (use_c && mi + 1 < 4) load_cin<BM>(crs, ldc, mi + 1, wm, wn, q, c16, cx);
 #pragma unroll
                 for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
@@ -887,13 +926,21 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                         const int row = wm * 64 + 16 * mi + 4 * q + r;
                         const int col = wn * G::WC + 16 * ni + c16;
                         if (row < hrows && col < wcols) {
-                            float *pc = C + (i0 + row) + (j0 + col) * ldc;
                             const double o = g.alpha * (double)acc[mi][ni][r];
-                            *pc = (float)(use_c ? o + g.beta * (double)*pc : o);
+                            C[(i0 + row) + (j0 + col) * ldc] =
+                                (float)(use_c ? o + g.beta * (double)cn[ni][r] : o);
                         }
                     }
+#pragma unroll
+                for (int ni = 0; ni < NI; ++ni)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) cn[ni][r] = cx[ni][r];
+            }
             return;
         }
+        // the report's largest ratio so far, read while the tile is verified
+        unsigned long long seen = 0;
+        if (t == 0) seen = atomic_peek(&g.counters->max_ratio_bits);
 
         if (kMma) {
             // encoded checksums from the matrix cores: row parts (lanes with
@@ -929,9 +976,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
 
         // Beta pass fused with the C_in part of the encoding; the output is
         // rounded to FP32 and the reference sums are taken of what is stored.
+        // (row group mi + 1 of C_in is fetched while group mi is summed)
         double col_o[NI] = {}, col_c[NI] = {}, col_c2[NI] = {};
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
+        for (int mi = 0; mi < 4; ++mi) {
+            if (use_c && mi + 1 < 4) load_cin<BM>(crs, ldc, mi + 1, wm, wn, q, c16, cx);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 double row_o = 0, row_c = 0, row_c2 = 0;
@@ -940,7 +989,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                 for (int ni = 0; ni < NI; ++ni) {
                     const int col = wn * G::WC + 16 * ni + c16;
                     const bool ok = row < hrows && col < wcols;
-                    const double cin = (use_c && ok) ? (double)C[(i0 + row) + (j0 + col) * ldc] : 0.0;
+                    const double cin = (use_c && ok) ? (double)cn[ni][r] : 0.0;
                     double o = g.alpha * (double)acc[mi][ni][r];
                     if (use_c) o = o + g.beta * cin;
                     const float of = ok ? (float)o : 0.0f;
@@ -956,6 +1005,11 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                     sm.u.epi.cin2_row[wn][row] = row_c2;
                 }
             }
+#pragma unroll
+            for (int ni = 0; ni < NI; ++ni)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cn[ni][r] = cx[ni][r];
+        }
 #pragma unroll
         for (int ni = 0; ni < NI; ++ni) {
             col_o[ni] = sum_rows(col_o[ni]);
@@ -1110,7 +1164,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
             double r = 0.0;
 #pragma unroll
             for (int v = 0; v < G::kVW; ++v) r = fmax(r, sm.wratio[v]);
-            atomic_max_nonneg(&g.counters->max_ratio_bits, r);
+            atomic_max_seen(&g.counters->max_ratio_bits, r, seen);
         }
 
         const int nr = sm.nbad_r, nc = sm.nbad_c;

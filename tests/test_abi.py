@@ -228,11 +228,15 @@ def test_operand_windows_wider_than_the_loaders_reach_are_refused():
     d = desc(F.F64, 1, 0, 64, 64, lim // 8 + 1, lim // 8 + 1, lim // 8 + 1)
     assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
     assert L.ftgemm_last_invalid_arg() == 5
-    # the FP64 beta pass reads each tile of C_in through one window: 127 ldc
-    # + 128 elements
+    # the beta pass reads each tile of C_in through one window: 127 ldc + 128
+    # FP64 elements, or 127 ldc + 256 FP32 ones
     ok_c = (lim // 8 - 128) // 127
     d = desc(F.F64, 0, 0, 512, 512, 512, 512, 512)
     d.ldc = ok_c + 1
+    assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
+    assert L.ftgemm_last_invalid_arg() == 13
+    d = desc(F.BF16, 0, 0, 512, 512, 512, 512, 512)
+    d.ldc = (lim // 4 - 256) // 127 + 1
     assert L.ftgemm_gemm_ex(C.byref(d), None, None) == F.ERR_INVALID_ARG
     assert L.ftgemm_last_invalid_arg() == 13
     wide_c = desc(F.F64, 0, 0, 512, 512, 512, 512, 512)
