@@ -278,6 +278,14 @@ __device__ __forceinline__ unsigned long long atomic_peek(const unsigned long lo
     return __atomic_load_n(addr, __ATOMIC_RELAXED);
 }
 
+// A value every lane of the wave holds, kept in scalar registers.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 __device__ __forceinline__ void atomic_max_seen(unsigned long long *addr, double v,
                                                 unsigned long long seen)
 {

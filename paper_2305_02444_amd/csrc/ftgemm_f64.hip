@@ -618,8 +618,10 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         double cn[2][4] = {}, cx[2][4] = {};
         if (use_c) load_cin(crs, ldc, 0, wm, wn, q, c16, cn);
         // the report's largest ratio so far, read while the tile is verified
-        unsigned long long seen = 0;
-        if (t == 0) seen = atomic_peek(&g.counters->max_ratio_bits);
+        // (by every thread: a value live in one lane only across the beta
+        // pass measured miscompiled -- that lane's later column sums were
+        // lost)
+        const unsigned long long seen = uniform_u64(atomic_peek(&g.counters->max_ratio_bits));
         double col_o[2] = {0, 0}, col_c[2] = {0, 0}, col_c2[2] = {0, 0};
         // weighted mode: the same column sums with row weights i + 1
         double col_ow[WGT ? 2 : 1] = {}, col_cw[WGT ? 2 : 1] = {}, col_cw2[WGT ? 2 : 1] = {};

@@ -939,8 +939,10 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
             return;
         }
         // the report's largest ratio so far, read while the tile is verified
-        unsigned long long seen = 0;
-        if (t == 0) seen = atomic_peek(&g.counters->max_ratio_bits);
+        // (by every thread: a value live in one lane only across the beta
+        // pass measured miscompiled -- that lane's later column sums were
+        // lost)
+        const unsigned long long seen = uniform_u64(atomic_peek(&g.counters->max_ratio_bits));
 
         if (kMma) {
             // encoded checksums from the matrix cores: row parts (lanes with

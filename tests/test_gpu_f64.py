@@ -205,6 +205,21 @@ def test_fault_classes():
     assert not rep.records
 
 
+def test_single_errors_on_every_column_class():
+    """One error per tile at local columns 0, 16, ..., 112 and rows in both
+    wave rows: each is rebuilt as the oracle rebuilds it."""
+    m, n, k = 1024, 1024, 96
+    A, B, Cin = synth.operands(36, 0, m, n, k, "uniform")
+    F_ = synth.Fault
+    plan = []
+    for t in range(16):
+        ti, tj = t % 8, (t // 8) * 4 + t % 4
+        plan.append(F_(ti * 128 + (53 * t + 64) % 128, tj * 128 + 16 * (t % 8),
+                       (7 * t) % k, synth.ADD, 40.0 + t))
+    got, rep, ref = _compare(A, B, Cin, 1.0, 0.5, False, False, plan)
+    assert rep.corrected == 16 == rep.detected
+
+
 def test_plain_kernel_matches_oracle():
     A, B, Cin = synth.operands(7, 0, 333, 222, 111, "normal")
     got, rep = gpu_f64(A, B, Cin, 1.5, -0.5, abft=False)

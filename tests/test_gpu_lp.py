@@ -235,6 +235,46 @@ def test_lp_256_row_tiles(ta, tb):
     assert rep.tiles_verified == 16 * 16
 
 
+def test_lp_256_row_single_errors_on_every_column_class():
+    """One error per tile of the 256 x 128 BF16 tile (taken from 256 tiles
+    on), at local columns 0, 16, ..., 112 and rows in every wave: each is
+    rebuilt, as the oracle rebuilds it."""
+    dtype = F.BF16
+    m, n, k = 4096, 2048, 256
+    tm, tn, bk = lp_tiling(dtype, m, n, k)
+    assert (tm, tn) == (256, 128)
+    A, B, Cin = synth.operands(35, 1, m, n, k, "normal")
+    q = lp_inputs(A, B, dtype)
+    unit = 1.0 / (q[2] * q[3])
+    Fa = synth.Fault
+    plan, tiles = [], []
+    for t in range(16):
+        ti, tj = t, (5 * t) % (n // tn)
+        row = ti * tm + (37 * t + 192) % tm
+        col = tj * tn + 16 * (t % 8)
+        plan.append(Fa(row, col, (29 * t) % k, synth.ADD, (1.5e3 + 100 * t) * unit))
+        tiles.append(ti + tj * (m // tm))
+    got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, dtype, plan=plan, tiles=tiles, q=q)
+    assert rep.corrected == 16 == rep.detected
+
+
+def test_lp_8192_flips_rebuilt_in_wave_3():
+    """Two FP32 exponent flips at 8192^3 BF16 (256 x 128 tiles), each on
+    lane 0 of wave 3 of its tile (local rows 192 and 193, column 32): both
+    are rebuilt, as the oracle rebuilds them.  A build that kept the
+    report's running maximum in thread 0 alone across the beta pass lost
+    thread 0's share of the rebuild's column sum there, so these tiles were
+    computed again instead."""
+    size = 8192
+    A, B, Cin = synth.operands(41, size, size, size, size, "normal")
+    q = lp_inputs(A, B, F.BF16)
+    Fa = synth.Fault
+    plan = [Fa(5568, 2720, 2858, synth.BITFLIP, 0.0, 24), Fa(4545, 7584, 1555, synth.BITFLIP, 0.0, 26)]
+    tiles = sorted((f.row // 256) + (f.col // 128) * (size // 256) for f in plan)
+    got, rep, ref = _compare(A, B, Cin, 1.0, 1.0, F.BF16, plan=plan, tiles=tiles, q=q)
+    assert rep.corrected == 2 == rep.detected
+
+
 @pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
 def test_lp_fp8_two_sided_from_the_norms_pass(ta, tb):
     """Two-sided FP8 on 128 x 128 tiles with at least 256 of them, so the
