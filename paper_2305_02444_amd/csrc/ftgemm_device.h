@@ -270,30 +270,6 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *addr, doub
     if (__atomic_load_n(addr, __ATOMIC_RELAXED) < bits) atomicMax(addr, bits);
 }
 
-// The same in two parts, so that the read (a round trip to memory) can be
-// issued early and its latency hidden: `seen` is the value read by
-// atomic_peek some time before (a stale value only costs an atomic).
-__device__ __forceinline__ unsigned long long atomic_peek(const unsigned long long *addr)
-{
-    return __atomic_load_n(addr, __ATOMIC_RELAXED);
-}
-
-// A value every lane of the wave holds, kept in scalar registers.
-__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
-{
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
-    return ((unsigned long long)hi << 32) | lo;
-}
-
-__device__ __forceinline__ void atomic_max_seen(unsigned long long *addr, double v,
-                                                unsigned long long seen)
-{
-    if (!(v > 0.0)) return;
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-    if (seen < bits) atomicMax(addr, bits);
-}
-
 __device__ __forceinline__ double flip_bit_f64(double v, int bit)
 {
     return __longlong_as_double(__double_as_longlong(v) ^ (1ll << bit));

@@ -617,11 +617,6 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         const __amdgpu_buffer_rsrc_t crs = cin_rsrc(C, ldc, m, n, i0, j0);
         double cn[2][4] = {}, cx[2][4] = {};
         if (use_c) load_cin(crs, ldc, 0, wm, wn, q, c16, cn);
-        // the report's largest ratio so far, read while the tile is verified
-        // (by every thread: a value live in one lane only across the beta
-        // pass measured miscompiled -- that lane's later column sums were
-        // lost)
-        const unsigned long long seen = uniform_u64(atomic_peek(&g.counters->max_ratio_bits));
         double col_o[2] = {0, 0}, col_c[2] = {0, 0}, col_c2[2] = {0, 0};
         // weighted mode: the same column sums with row weights i + 1
         double col_ow[WGT ? 2 : 1] = {}, col_cw[WGT ? 2 : 1] = {}, col_cw2[WGT ? 2 : 1] = {};
@@ -833,10 +828,9 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         }
         __syncthreads();
         if (t == 0)
-            atomic_max_seen(&g.counters->max_ratio_bits,
-                            fmax(fmax(sm.wratio[0], sm.wratio[1]),
-                                 fmax(sm.wratio[2], sm.wratio[3])),
-                            seen);
+            atomic_max_nonneg(&g.counters->max_ratio_bits,
+                              fmax(fmax(sm.wratio[0], sm.wratio[1]),
+                                   fmax(sm.wratio[2], sm.wratio[3])));
 
         const int nr = sm.nbad_r, nc = sm.nbad_c;
         if (nr == 0 && nc == 0) {

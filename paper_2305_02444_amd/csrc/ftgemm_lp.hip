@@ -938,11 +938,6 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
             }
             return;
         }
-        // the report's largest ratio so far, read while the tile is verified
-        // (by every thread: a value live in one lane only across the beta
-        // pass measured miscompiled -- that lane's later column sums were
-        // lost)
-        const unsigned long long seen = uniform_u64(atomic_peek(&g.counters->max_ratio_bits));
 
         if (kMma) {
             // encoded checksums from the matrix cores: row parts (lanes with
@@ -1166,7 +1161,7 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
             double r = 0.0;
 #pragma unroll
             for (int v = 0; v < G::kVW; ++v) r = fmax(r, sm.wratio[v]);
-            atomic_max_seen(&g.counters->max_ratio_bits, r, seen);
+            atomic_max_nonneg(&g.counters->max_ratio_bits, r);
         }
 
         const int nr = sm.nbad_r, nc = sm.nbad_c;
