@@ -190,6 +190,11 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
                                      lambda: timed(torch, call(False), steps, warmup, reset))
     else:
         t_plain_same = t_plain
+    # the operand checksums and norms formed in the tiles from the staged
+    # operands (the entry point that allocates nothing takes no pass before
+    # the product; its tiles are the same)
+    dn = F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype)
+    t_in_tile, _ = timed(torch, lambda: F.gemm_ex_noalloc(dn), steps, warmup, reset)
     tiles = (-(-m // tm)) * (-(-n // tn))
     gp = synth.rng(wid, size, synth.STREAM_PLAN)
     # exponent flips (bits 27..30) of FP32 accumulators: always far above
@@ -311,6 +316,9 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
         "abft_overhead_pct": round(100.0 * (t_ft / t_plain - 1.0), 2),
         "plain_same_tile_tflops": round(flops / (t_plain_same * 1e-3) / 1e12, 3),
         "abft_overhead_same_tile_pct": round(100.0 * (t_ft / t_plain_same - 1.0), 2),
+        "checksums_in_tiles": {"tflops": round(flops / (t_in_tile * 1e-3) / 1e12, 3),
+                               "abft_overhead_same_tile_pct":
+                                   round(100.0 * (t_in_tile / t_plain_same - 1.0), 2)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[name],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK[name], 4),
                      "traffic": read_traffic("ftgemm_%s_8192_counters.txt" % name,
