@@ -1,28 +1,31 @@
 // ftgemm_f64.hip -- FP64 fault-tolerant GEMM tile for gfx950.
 //
 // One workgroup (8 waves, 2 x 4) owns a 128 x 128 output tile and walks the
-// inner dimension in steps of 16.  Each step is staged HBM -> VGPR -> LDS
+// inner dimension in steps of 32.  Each step is staged HBM -> VGPR -> LDS
 // (double-buffered, one barrier per step) and multiplied with
 // v_mfma_f64_16x16x4_f64; every wave owns a 64 x 32 sub-tile, and the two
 // waves on each SIMD hide each other's LDS and barrier latency.
 //
-// Fault tolerance (FT-GEMM, Section 2.2), entirely on the staged operand
-// values in registers, so it adds no HBM traffic and leaves the MFMA loop
-// untouched:
-//   * every thread's 4 staged elements of a step share one inner index p;
+// Fault tolerance (FT-GEMM, Section 2.2), on the staged operand values, so
+// it adds no HBM traffic:
+//   * every thread's 8 staged elements of a step share one inner index p;
 //     before the step's barrier it adds them into the operand checksums
 //     x_p = sum_i A(i,p) and y_p = sum_j B(p,j) (a short cross-lane
-//     reduction finishes them in LDS) and into the squared norms of its rows
-//     of A / columns of B (each staged element reused, as in the paper's
-//     packing routines);
-//   * after the barrier, with x_p and y_p complete, the same registers feed
-//     the encoded checksums Pc_i += A(i,p) y_p and Pr_j += x_p B(p,j);
+//     reduction finishes them in LDS);
+//   * after the barrier, with x_p and y_p complete, the staged A registers
+//     feed the encoded column checksums Pc_i += A(i,p) y_p and the squared
+//     row norms of A, and the staged B tile in LDS feeds the encoded row
+//     checksums Pr_j += x_p B(p,j) and the squared column norms of B (one
+//     column and a quarter of the p per thread);
 //   * the encoding of C_in is fused into the beta pass of the epilogue, and
 //     the reference checksums are summed from the accumulator registers
 //     before anything is written;
-//   * verify, locate, rebuild and confirm one element per tile; a tile with
-//     several disagreements is computed again by the same workgroup (C is
-//     not written until the tile verifies).
+//   * verify, locate, rebuild and confirm (one error, errors on one line, or
+//     errors in distinct rows and columns); a tile whose disagreements fit
+//     none of these is computed again by the same workgroup (C is not
+//     written until the tile verifies).
+// The weighted mode adds a weighted row checksum per column (weights i + 1)
+// that locates and confirms corrections.
 #include "ftgemm_device.h"
 #include "ftgemm_kernels.h"
 
@@ -293,9 +296,9 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
     // B transposed: its columns (j) do.
     OpLoader<!TA> la;
     OpLoader<TB> lb;
-    // weighted mode with A's partial sums spread over the waves: finished
-    // once per step behind a second barrier
-    constexpr bool kFinish = WGT && OpLoader<!TA>::kParts > 1;
+    // x_p (and x'_p) left as wave partials (A transposed): finished once
+    // per step behind a second barrier, for the B-side sums read from LDS
+    constexpr bool kFinish = ABFT && OpLoader<!TA>::kParts > 1;
     la.init((const double *)g.A, g.lda, TA ? k : m, TA ? m : k, t);
     lb.init((const double *)g.B, g.ldb, TB ? n : k, TB ? k : n, t);
     // Staged operand registers of one step.
@@ -313,16 +316,19 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
             sm.u.st[buf].B[b_p][phys(lb.o(r))] = rb[r];
         }
     };
-    // (weighted mode, A not transposed: the squares of the step's x_p and
-    // x'_p of this thread's p go into vx, vxw)
+    // (A not transposed: the squares of the step's x_p and, in the
+    // weighted mode, x'_p of this thread's p go into vx, vxw)
     auto sums = [&](int buf, float &vx, float &vxw) {
         const double x = la.sum_to(ra, sm.xs[buf]);
+        if (!kFinish) {
+            const float fx = (float)x;
+            vx = fmaf(fx, fx, vx);
+        }
         if (WGT) {
             const double xw = kFinish ? la.wsum_to(ra, sm.xws[buf], 0)
                                       : la.wsum_to(ra, sm.xs[buf], 1);
             if (!kFinish) {
-                const float fx = (float)x, fw = (float)xw;
-                vx = fmaf(fx, fx, vx);
+                const float fw = (float)xw;
                 vxw = fmaf(fw, fw, vxw);
             }
         }
@@ -353,20 +359,18 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
 #pragma unroll
             for (int ni = 0; ni < 2; ++ni)
                 acc[mi][ni] = (d4){0.0, 0.0, 0.0, 0.0};
-        // Per-thread checksum partials over the steps, for this thread's 4
-        // outer indices (rows of A in the A loader, columns of B in the B one).
+        // Checksum partials over the steps.  The A side comes from the
+        // staged registers: this thread's 8 rows of A (A . y and the squared
+        // row norms).  The B side comes from the staged B tile in LDS, one
+        // register per sum instead of one per staged element: thread t
+        // covers column j = t mod 128 and a quarter of each step's p, and
+        // sums x_p B(p, j) (x'_p B(p, j) in the weighted mode) and B(p, j)^2.
         // The norms only scale the rounding-error threshold, so FP32 is ample
         // for them (and halves their registers).
-        double enc_a[EPT] = {}, enc_b[WGT ? 1 : EPT] = {};
-        // The weighted mode takes the B side from the staged B tile in LDS
-        // instead (one register per sum instead of one per staged element,
-        // which leaves room for the weighted sums): thread t covers column
-        // j = t mod 128 and a quarter of each step's p, and sums x_p B(p, j),
-        // x'_p B(p, j), B(p, j)^2, x_p^2 and x'_p^2 there.
-        double enc_w = 0.0;
-        float vxw = 0.0f;
-        float nrm_a[EPT] = {}, nrm_b[WGT ? 1 : EPT] = {};
-        float vx = 0.0f, vy = 0.0f;  // x_p^2, y_p^2 over the steps, for this thread's p
+        double enc_a[EPT] = {}, enc_b = 0.0, enc_w = 0.0;
+        float nrm_a[EPT] = {}, nrm_b = 0.0f;
+        float vx = 0.0f, vy = 0.0f;  // x_p^2, y_p^2 over the steps
+        float vxw = 0.0f;            // weighted mode: x'_p^2
 
         load(0);
         if (ABFT) sums(0, vx, vxw);
@@ -416,7 +420,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
             // The steps run in segments that end where a planned fault lands, so
             // the fault hook sits outside the hot loop.
             int s = 0;
-    #pragma unroll 1
+#pragma unroll 1
             while (s < nsteps) {
                 int stop = nsteps - 1;
                 if (faults_on)
@@ -425,7 +429,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                         if (sm.faults[f].target == FTGEMM_TGT_ACC && fs >= s && fs < stop)
                             stop = fs;
                     }
-    #pragma unroll 1
+#pragma unroll 1
                 for (; s <= stop; ++s) {
                     const int buf = s & 1;
                     store(buf);
@@ -435,12 +439,15 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                         // partials (each thread reads eight p per step)
                         if (t < BK) {
                             const double x = gather<NW>(sm.xs[buf], t);
-                            const double xw = gather<NW>(sm.xws[buf], t);
                             sm.xfin[t][0] = x;
-                            sm.xfin[t][1] = xw;
-                            const float fx = (float)x, fw = (float)xw;
+                            const float fx = (float)x;
                             vx = fmaf(fx, fx, vx);
-                            vxw = fmaf(fw, fw, vxw);
+                            if (WGT) {
+                                const double xw = gather<NW>(sm.xws[buf], t);
+                                sm.xfin[t][1] = xw;
+                                const float fw = (float)xw;
+                                vxw = fmaf(fw, fw, vxw);
+                            }
                         }
                         __syncthreads();
                     }
@@ -454,58 +461,49 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                     // with it at 8192^3).
                     const int enc_kk =
                         WGT && __builtin_amdgcn_readfirstlane(threadIdx.x >> 8) ? 4 : 1;
-                    double yv = 0.0, xv = 0.0;
+                    double yv = 0.0;
                     if (ABFT) yv = gather<OpLoader<TB>::kParts>(sm.ys[buf], la.p());
-                    if (ABFT && !WGT) xv = gather<OpLoader<!TA>::kParts>(sm.xs[buf], lb.p());
-    #pragma unroll
+#pragma unroll
                     for (int kk = 0; kk < BK / 4; ++kk) {
                         if (kk == (ABFT ? enc_kk : 0)) {
                             if (ABFT) {
                                 // the encoded checksums and norms of step s,
                                 // before ra/rb take step s + 1
-    #pragma unroll
+#pragma unroll
                                 for (int r = 0; r < EPT; ++r) {
                                     enc_a[r] += ra[r] * yv;
                                     // squares of the FP32-rounded values: two
                                     // instructions (convert, FP32 fma)
                                     const float fa = (float)ra[r];
                                     nrm_a[r] = fmaf(fa, fa, nrm_a[r]);
-                                    if constexpr (!WGT) {
-                                        enc_b[r] += xv * rb[r];
-                                        const float fb = (float)rb[r];
-                                        nrm_b[r] = fmaf(fb, fb, nrm_b[r]);
-                                    }
                                 }
                                 const float fy = (float)yv;
                                 vy = fmaf(fy, fy, vy);
-                                if (!WGT) {
-                                    const float fx = (float)xv;
-                                    vx = fmaf(fx, fx, vx);
-                                }
                             }
                             if (s + 1 < nsteps) load(s + 1);
                         }
-                        if (WGT) {
-                            // one p of this thread's quarter per sub-step
+                        if (ABFT) {
+                            // the B side: one p of this thread's quarter per
+                            // sub-step (x_p and x'_p read together)
                             const int pw = (t / TN) * (BK / 4) + kk;
                             const double bv = sm.u.st[buf].B[pw][phys(t & (TN - 1))];
                             const double2 xq = *reinterpret_cast<const double2 *>(
                                 kFinish ? &sm.xfin[pw][0] : &sm.xs[buf][pw][0]);
-                            enc_b[0] = fma(xq.x, bv, enc_b[0]);
-                            enc_w = fma(xq.y, bv, enc_w);
+                            enc_b = fma(xq.x, bv, enc_b);
+                            if (WGT) enc_w = fma(xq.y, bv, enc_w);
                             const float fb = (float)bv;
-                            nrm_b[0] = fmaf(fb, fb, nrm_b[0]);
+                            nrm_b = fmaf(fb, fb, nrm_b);
                         }
                         double fa[4], fb[2];
-    #pragma unroll
+#pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
                             fa[mi] = sm.u.st[buf].A[4 * kk + q][phys(wm * 64 + 16 * mi + c16)];
-    #pragma unroll
+#pragma unroll
                         for (int ni = 0; ni < 2; ++ni)
                             fb[ni] = sm.u.st[buf].B[4 * kk + q][phys(wn * 32 + 16 * ni + c16)];
-    #pragma unroll
+#pragma unroll
                         for (int mi = 0; mi < 4; ++mi)
-    #pragma unroll
+#pragma unroll
                             for (int ni = 0; ni < 2; ++ni)
                                 acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(
                                     fa[mi], fb[ni], acc[mi][ni], 0, 0, 0);
@@ -524,12 +522,12 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                         if (w != owner_wave(tf.row, tf.col)) continue;
                         const int ol = owner_lane(tf.row, tf.col), sel = owner_reg(tf.row, tf.col);
                         double before = 0.0;
-    #pragma unroll
+#pragma unroll
                         for (int e = 0; e < 32; ++e)
                             if (sel == e) before = acc[e >> 3][(e >> 2) & 1][e & 3];
                         const double after = tf.mode == FTGEMM_INJ_ADD ? before + tf.delta
                                                                        : flip_bit_f64(before, tf.bit);
-    #pragma unroll
+#pragma unroll
                         for (int e = 0; e < 32; ++e)
                             if (sel == e && lane == ol) acc[e >> 3][(e >> 2) & 1][e & 3] = after;
                         if (lane == ol) {
@@ -584,30 +582,25 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
             return;
         }
 
-        // Publish the per-thread partials: rows of A from the A loader,
-        // columns of B from the B loader (the other p completed in lanes).
-        // The y_p loaded by the A loader's threads and the x_p by the B
-        // loader's are the same for every thread of a p: one thread per p
-        // accounts for it.  The A loader's p gathers y, the B loader's x.
+        // Publish the per-thread partials: rows of A from the A loader (the
+        // other p completed in lanes); columns of B, one partial per quarter
+        // of p.  The y_p gathered by the A loader's threads is the same for
+        // every thread of a p: one thread per p accounts for it, and the
+        // squares of x_p (x'_p) come from the threads that summed them, one
+        // per p.
         la.partials_to(enc_a, sm.u.epi.enc_row);
         la.partials_to(nrm_a, sm.u.epi.nrm_row);
         if (la.first_of_p()) sm.vnrm[1][la.p()] = (double)vy;
-        if constexpr (!WGT) {
-            lb.partials_to(enc_b, sm.u.epi.enc_col);
-            lb.partials_to(nrm_b, sm.u.epi.nrm_col);
-            if (lb.first_of_p()) sm.vnrm[0][lb.p()] = (double)vx;
-        } else {
-            // one partial per quarter of p; the squares of x_p and x'_p from
-            // the threads that summed them (one per p)
+        {
             const int jw = t & (TN - 1), qw = t / TN;
-            sm.u.epi.enc_col[qw][jw] = enc_b[0];
-            sm.u.epi.nrm_col[qw][jw] = (double)nrm_b[0];
-            sm.u.epi.enc_colw[qw][jw] = enc_w;
+            sm.u.epi.enc_col[qw][jw] = enc_b;
+            sm.u.epi.nrm_col[qw][jw] = (double)nrm_b;
+            if (WGT) sm.u.epi.enc_colw[qw][jw] = enc_w;
             const bool own = kFinish ? t < BK : la.first_of_p();
             const int pv = kFinish ? t : la.p();
             if (own) {
                 sm.vnrm[0][pv] = (double)vx;
-                sm.vnrmw[pv] = (double)vxw;
+                if (WGT) sm.vnrmw[pv] = (double)vxw;
             }
         }
 
@@ -699,7 +692,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
             sm.u.epi.fin_row[x] = e;
         } else if (is_col) {
             double e = 0, nr = 0, ew = 0;
-            constexpr int parts = WGT ? NT / TN : OpLoader<TB>::kOuterParts;
+            constexpr int parts = NT / TN;
 #pragma unroll
             for (int v = 0; v < parts; ++v) {
                 e += sm.u.epi.enc_col[v][x];
