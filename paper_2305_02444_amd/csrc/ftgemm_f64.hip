@@ -365,10 +365,12 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         // register per sum instead of one per staged element: thread t
         // covers column j = t mod 128 and a quarter of each step's p, and
         // sums x_p B(p, j) (x'_p B(p, j) in the weighted mode) and B(p, j)^2.
-        // The norms only scale the rounding-error threshold, so FP32 is ample
-        // for them (and halves their registers).
-        double enc_a[EPT] = {}, enc_b = 0.0, enc_w = 0.0;
-        float nrm_a[EPT] = {}, nrm_b = 0.0f;
+        // The norms only scale the rounding-error threshold: the A side
+        // squares its FP32-rounded values in FP32 (half the registers of one
+        // double per staged element), the B side, one register in all, takes
+        // one FP64 fma per element.
+        double enc_a[EPT] = {}, enc_b = 0.0, enc_w = 0.0, nrm_b = 0.0;
+        float nrm_a[EPT] = {};
         float vx = 0.0f, vy = 0.0f;  // x_p^2, y_p^2 over the steps
         float vxw = 0.0f;            // weighted mode: x'_p^2
 
@@ -491,8 +493,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
                                 kFinish ? &sm.xfin[pw][0] : &sm.xs[buf][pw][0]);
                             enc_b = fma(xq.x, bv, enc_b);
                             if (WGT) enc_w = fma(xq.y, bv, enc_w);
-                            const float fb = (float)bv;
-                            nrm_b = fmaf(fb, fb, nrm_b);
+                            nrm_b = fma(bv, bv, nrm_b);
                         }
                         double fa[4], fb[2];
 #pragma unroll
@@ -594,7 +595,7 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         {
             const int jw = t & (TN - 1), qw = t / TN;
             sm.u.epi.enc_col[qw][jw] = enc_b;
-            sm.u.epi.nrm_col[qw][jw] = (double)nrm_b;
+            sm.u.epi.nrm_col[qw][jw] = nrm_b;
             if (WGT) sm.u.epi.enc_colw[qw][jw] = enc_w;
             const bool own = kFinish ? t < BK : la.first_of_p();
             const int pv = kFinish ? t : la.p();
