@@ -559,6 +559,25 @@ __device__ __forceinline__ void load_cin(__amdgpu_buffer_rsrc_t rs, int64_t ldc,
         }
 }
 
+// Four outputs of one column, rows row0 .. row0 + 3 of the tile (each lane
+// holds four consecutive rows of a column): one 16-byte store where all four
+// lie inside the matrix and C's columns start on 16-byte boundaries (vec),
+// else one store per element inside it.
+__device__ __forceinline__ void store_rows4(float *C, int64_t ldc, int64_t i0, int64_t j0,
+                                            int row0, int col, int hrows, int wcols, bool vec,
+                                            const f4 v)
+{
+    if (col >= wcols) return;
+    float *p = C + (i0 + row0) + (j0 + col) * ldc;
+    if (vec && row0 + 4 <= hrows) {
+        *reinterpret_cast<f4 *>(p) = v;
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (row0 + r < hrows) p[r] = v[r];
+    }
+}
+
 // ONE: the one-sided mode -- only the column checksum of the tile (one
 // entry per row, C^c = C e) is encoded and verified, and any disagreement has
 // the tile computed again.  PRE (implied by ONE): the threshold norms come
@@ -916,21 +935,21 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
         float cn[NI][4] = {}, cx[NI][4] = {};
         if (use_c) load_cin<BM>(crs, ldc, 0, wm, wn, q, c16, cn);
         if (!ABFT) {
+            const bool vec = ((reinterpret_cast<uintptr_t>(C) | ((uintptr_t)ldc << 2)) & 15) == 0;
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi) {
                 if (use_c && mi + 1 < 4) load_cin<BM>(crs, ldc, mi + 1, wm, wn, q, c16, cx);
 #pragma unroll
-                for (int ni = 0; ni < NI; ++ni)
+                for (int ni = 0; ni < NI; ++ni) {
+                    f4 v;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int row = wm * 64 + 16 * mi + 4 * q + r;
-                        const int col = wn * G::WC + 16 * ni + c16;
-                        if (row < hrows && col < wcols) {
-                            const double o = g.alpha * (double)acc[mi][ni][r];
-                            C[(i0 + row) + (j0 + col) * ldc] =
-                                (float)(use_c ? o + g.beta * (double)cn[ni][r] : o);
-                        }
+                        const double o = g.alpha * (double)acc[mi][ni][r];
+                        v[r] = (float)(use_c ? o + g.beta * (double)cn[ni][r] : o);
                     }
+                    store_rows4(C, ldc, i0, j0, wm * 64 + 16 * mi + 4 * q,
+                                wn * G::WC + 16 * ni + c16, hrows, wcols, vec, v);
+                }
 #pragma unroll
                 for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
@@ -1397,17 +1416,13 @@ __device__ void tile(const GemmArgs &g, int tile_m, int tile_n, Smem<BM> &sm)
                 }
             }
         }
+        const bool vec = ((reinterpret_cast<uintptr_t>(C) | ((uintptr_t)ldc << 2)) & 15) == 0;
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
             for (int ni = 0; ni < NI; ++ni)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = wm * 64 + 16 * mi + 4 * q + r;
-                    const int col = wn * G::WC + 16 * ni + c16;
-                    if (row < hrows && col < wcols)
-                        C[(i0 + row) + (j0 + col) * ldc] = acc[mi][ni][r];
-                }
+                store_rows4(C, ldc, i0, j0, wm * 64 + 16 * mi + 4 * q,
+                            wn * G::WC + 16 * ni + c16, hrows, wcols, vec, acc[mi][ni]);
         if (npairs > 0) {
             // Paired corrections: the lane that stored each element takes
             // the pair's residual off it in memory (its own store is ordered

@@ -171,11 +171,17 @@ def test_lp_special_cases(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_lp_padded_leading_dimension_of_c(dtype):
+@pytest.mark.parametrize("pad", [5, 2])
+@pytest.mark.parametrize("abft", [1, 0])
+def test_lp_padded_leading_dimension_of_c(dtype, pad, abft):
+    """ldc = 135 (columns off 16-byte boundaries: one store per element) and
+    132 (16-byte stores of four rows, the last tile row's partial group of
+    130 rows element by element), with and without checksums."""
     A, B, Cin = synth.operands(34, 0, 130, 140, 33, "uniform")
     ca, cb, sa, sb, dA, dB = lp_inputs(A, B, dtype)
     C32 = _c32(Cin)
-    got, rep = gpu_lp(ca, cb, C32, 1.0, 1.0, dtype, scale_a=sa, scale_b=sb, ldc_pad=5)
+    got, rep = gpu_lp(ca, cb, C32, 1.0, 1.0, dtype, scale_a=sa, scale_b=sb, ldc_pad=pad,
+                      abft=abft)
     assert normwise(got, O.default().gemm(dA, dB, C32, sa * sb, 1.0)) <= TOL[dtype]
 
 
