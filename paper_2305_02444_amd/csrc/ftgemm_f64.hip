@@ -583,6 +583,12 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
             return;
         }
 
+        // The first row group of C_in is on its way while the partials are
+        // published.
+        const __amdgpu_buffer_rsrc_t crs = cin_rsrc(C, ldc, m, n, i0, j0);
+        double cn[2][4] = {}, cx[2][4] = {};
+        if (use_c) load_cin(crs, ldc, 0, wm, wn, q, c16, cn);
+
         // Publish the per-thread partials: rows of A from the A loader (the
         // other p completed in lanes); columns of B, one partial per quarter
         // of p.  The y_p gathered by the A loader's threads is the same for
@@ -608,9 +614,6 @@ __device__ __forceinline__ void tile(const GemmArgs &g, int tile_m, int tile_n, 
         // Beta pass fused with the C_in part of the encoding (Section 2.2)
         // and the reference sums of the output.
         // (row group mi + 1 of C_in is fetched while group mi is summed)
-        const __amdgpu_buffer_rsrc_t crs = cin_rsrc(C, ldc, m, n, i0, j0);
-        double cn[2][4] = {}, cx[2][4] = {};
-        if (use_c) load_cin(crs, ldc, 0, wm, wn, q, c16, cn);
         double col_o[2] = {0, 0}, col_c[2] = {0, 0}, col_c2[2] = {0, 0};
         // weighted mode: the same column sums with row weights i + 1
         double col_ow[WGT ? 2 : 1] = {}, col_cw[WGT ? 2 : 1] = {}, col_cw2[WGT ? 2 : 1] = {};
