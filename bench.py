@@ -192,9 +192,18 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
         t_plain_same = t_plain
     # the operand checksums and norms formed in the tiles from the staged
     # operands (the entry point that allocates nothing takes no pass before
-    # the product; its tiles are the same)
+    # the product; fault-tolerant FP8 tiles have 128 rows there), against
+    # the kernel without checksums on the same tile
     dn = F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype)
     t_in_tile, _ = timed(torch, lambda: F.gemm_ex_noalloc(dn), steps, warmup, reset)
+    tm_in = 128 if dtype == F.FP8_E4M3 else tm
+    if tm_in == tm:
+        t_plain_in = t_plain_same
+    elif tm_in == tm0:
+        t_plain_in = t_plain
+    else:
+        t_plain_in, _ = with_table(F, "tile %d 0 %d\n" % (dtype, tm_in),
+                                   lambda: timed(torch, call(False), steps, warmup, reset))
     tiles = (-(-m // tm)) * (-(-n // tn))
     gp = synth.rng(wid, size, synth.STREAM_PLAN)
     # exponent flips (bits 27..30) of FP32 accumulators: always far above
@@ -317,8 +326,9 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
         "plain_same_tile_tflops": round(flops / (t_plain_same * 1e-3) / 1e12, 3),
         "abft_overhead_same_tile_pct": round(100.0 * (t_ft / t_plain_same - 1.0), 2),
         "checksums_in_tiles": {"tflops": round(flops / (t_in_tile * 1e-3) / 1e12, 3),
+                               "tile": [tm_in, tn, bk],
                                "abft_overhead_same_tile_pct":
-                                   round(100.0 * (t_in_tile / t_plain_same - 1.0), 2)},
+                                   round(100.0 * (t_in_tile / t_plain_in - 1.0), 2)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[name],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK[name], 4),
                      "traffic": read_traffic("ftgemm_%s_8192_counters.txt" % name,
@@ -466,8 +476,9 @@ def profile_run(kind, size, calls=3):
     at size^3 (alpha = beta = 1, no report), or, for `copy`, device copies of
     a 512 MiB buffer (the scale of the traffic counters).  Kinds: the
     fault-tolerant call (f64, bf16, fp8), the same kernel with checksums
-    compiled out on its default tile (-plain) and, for FP8, on the
-    fault-tolerant call's 128-row tile (fp8-plain-128), the unfused and
+    compiled out on its default tile (-plain) and, for FP8, on the 128-row
+    tile of the call that forms its checksums in the tiles (fp8-plain-128),
+    the unfused and
     weighted FP64 modes, and the low-precision fault tolerance with every operand checksum
     formed in the tiles from the staged operands (-fused: the entry point
     that allocates nothing, which takes no pass before the product)."""

@@ -259,7 +259,8 @@ ftgemm_status ftgemm_gemm_batched(int32_t count, const ftgemm_gemm_desc *problem
  * of few tiles) and BF16 / FP8 tiles form their threshold norms and operand
  * checksums themselves, with no pass over A and B before the product (C is
  * the same; a rebuilt element may differ from ftgemm_gemm_ex's in its last
- * FP32 bits).  Refused with FTGEMM_ERR_UNSUPPORTED: abft 2 and 3 (their
+ * FP32 bits).  Fault-tolerant FP8 tiles have 128 rows here (those sums do
+ * not fit a 256-row FP8 tile), unless the tuning table says otherwise.  Refused with FTGEMM_ERR_UNSUPPORTED: abft 2 and 3 (their
  * workspace grows with the problem), abft 4 and an armed fault plan longer than
  * 256 entries.  Records beyond 1024 are dropped (still counted).  Every
  * call on a GPU shares that GPU's array and keeps the last call's contents

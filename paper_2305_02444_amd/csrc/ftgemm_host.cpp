@@ -400,9 +400,10 @@ int check_windows(const ftgemm_gemm_desc &d)
 }
 
 // Tile of a single low-precision call: the default choice, or the table's.
-void lp_tiling(const ftgemm_gemm_desc &d, int *tm, int *tn, int *bk)
+// in_tile: the call forms its operand checksums and norms in the tiles.
+void lp_tiling(const ftgemm_gemm_desc &d, int *tm, int *tn, int *bk, bool in_tile = false)
 {
-    ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, tm, tn, bk);
+    ftg::tiling_lp(d.dtype == FTGEMM_FP8_E4M3, d.abft, d.m, d.n, false, in_tile, tm, tn, bk);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     const int rows = tune_table().single_rows[d.dtype][d.abft < 3 ? d.abft : 0];
     if (rows) *tm = rows;
@@ -996,7 +997,7 @@ ftgemm_status run_batched(int32_t count, const ftgemm_gemm_desc *descs, ftgemm_r
     if (d0.dtype == FTGEMM_F64)
         ftg::tiling_f64(&tm, &tn, &bk);
     else
-        ftg::tiling_lp(d0.dtype == FTGEMM_FP8_E4M3, d0.abft, 0, 0, true, &tm, &tn, &bk);
+        ftg::tiling_lp(d0.dtype == FTGEMM_FP8_E4M3, d0.abft, 0, 0, true, true, &tm, &tn, &bk);
     const bool lp = d0.dtype != FTGEMM_F64;
     std::vector<ftg::GemmArgs> probs(count);
     std::vector<int> live;
@@ -1211,7 +1212,7 @@ ftgemm_status run_noalloc(const ftgemm_gemm_desc &d, ftgemm_report *rep, hipStre
     if (d.dtype == FTGEMM_F64)
         ftg::tiling_f64(&tm, &tn, &bk);
     else
-        lp_tiling(d, &tm, &tn, &bk);
+        lp_tiling(d, &tm, &tn, &bk, true);
     GemmArgs g = base_args(d, tm, tn);
     const bool ta = d.transA == FTGEMM_OP_T, tb = d.transB == FTGEMM_OP_T;
     g.counters = counters;

@@ -22,10 +22,11 @@ void tiling_f64(int *tm, int *tn, int *bk);
 hipError_t launch_lp(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode, bool pre, int tm,
                      hipStream_t stream);
 // Tile of an m x n low-precision output in a mode (batched: the batched
-// kernel's tile).
+// kernel's tile; in_tile: the operand checksums and norms are formed in the
+// tiles, with no pass before the product).
 constexpr int64_t kLargeTileMin = 256;  // 256-row tiles from this many tiles on
-void tiling_lp(bool fp8, int mode, int64_t m, int64_t n, bool batched, int *tm, int *tn,
-               int *bk);
+void tiling_lp(bool fp8, int mode, int64_t m, int64_t n, bool batched, bool in_tile, int *tm,
+               int *tn, int *bk);
 
 // Squared norms and largest magnitudes of the lines of a column-major R x Cn
 // matrix of BF16 / E4M3 codes: of each row (along_rows; R results) or of

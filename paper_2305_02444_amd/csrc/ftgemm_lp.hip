@@ -1593,14 +1593,16 @@ hipError_t launch_lp_batched(const BatchArgs &b, bool fp8, bool ta, bool tb, boo
 
 // 256-row tiles once they still give every compute unit a tile (they do
 // twice the matrix work per staged byte of the 128-row tiles), 128 rows
-// otherwise and in batches.  The two-sided fault-tolerant FP8 kernel keeps
-// 128-row tiles: at 256 rows its per-row checksum and norm registers no
-// longer fit beside the accumulators and it spills inside the main loop.
-void tiling_lp(bool fp8, int mode, int64_t m, int64_t n, bool batched, int *tm, int *tn,
-               int *bk)
+// otherwise and in batches.  The two-sided fault-tolerant FP8 kernel that
+// forms its operand checksums and norms in the tile (in_tile: the entry
+// point that allocates nothing) keeps 128-row tiles: at 256 rows those
+// registers no longer fit beside the accumulators.
+void tiling_lp(bool fp8, int mode, int64_t m, int64_t n, bool batched, bool in_tile, int *tm,
+               int *tn, int *bk)
 {
     const int64_t tiles256 = ((m + 255) / 256) * ((n + lp::TN - 1) / lp::TN);
-    const bool large = !batched && !(fp8 && mode == 1) && tiles256 >= kLargeTileMin;
+    const bool large =
+        !batched && !(fp8 && mode == 1 && in_tile) && tiles256 >= kLargeTileMin;
     *tm = large ? 256 : lp::kBatchBM;
     *tn = lp::TN;
     *bk = fp8 ? lp::Elem<true>::BK : lp::Elem<false>::BK;

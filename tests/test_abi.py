@@ -146,10 +146,10 @@ def test_query_tiling():
     assert (tm, tn, sk) == (128, 128, 1) and bk in (16, 32)
     assert F.lib().ftgemm_query_tiling(9, 1, 1, 1, None, None, None, None) == F.ERR_INVALID_ARG
     # low precision: 128 bytes of the inner dimension per row per step, no
-    # split; BF16 256-row tiles once there are at least 256 of them, FP8
-    # (fault-tolerant) 128-row tiles
+    # split; 256-row tiles once there are at least 256 of them
     assert F.query_tiling(F.BF16, 8192, 8192, 8192) == (256, 128, 64, 1)
-    assert F.query_tiling(F.FP8_E4M3, 8192, 8192, 8192) == (128, 128, 128, 1)
+    assert F.query_tiling(F.FP8_E4M3, 8192, 8192, 8192) == (256, 128, 128, 1)
+    assert F.query_tiling(F.FP8_E4M3, 4096, 1920, 64) == (128, 128, 128, 1)   # 16 x 15
     assert F.query_tiling(F.BF16, 4096, 2048, 64) == (256, 128, 64, 1)      # 16 x 16 tiles
     assert F.query_tiling(F.BF16, 3841, 2048, 64) == (256, 128, 64, 1)      # 16 x 16
     assert F.query_tiling(F.BF16, 4096, 1920, 64) == (128, 128, 64, 1)      # 16 x 15

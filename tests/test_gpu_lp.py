@@ -142,9 +142,8 @@ def test_lp_small_and_edge_shapes(dtype, m, n, k):
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("m,n,k", [(333, 222, 111), (3999, 2001, 301)])
 def test_lp_plain_kernel_bitwise_equals_ft(dtype, m, n, k):
-    """With no faults the checksum-free kernel writes the same bits (also
-    where the two use different tiles: at 3999 x 2001 the FP8 kernel
-    without checksums takes 256-row tiles, the fault-tolerant one 128)."""
+    """With no faults the checksum-free kernel writes the same bits (128-row
+    tiles at 333 x 222, 256-row ones at 3999 x 2001)."""
     A, B, Cin = synth.operands(32, 0, m, n, k, "normal")
     ca, cb, sa, sb, dA, dB = lp_inputs(A, B, dtype)
     C32 = _c32(Cin)
@@ -281,19 +280,32 @@ def test_lp_8192_flips_rebuilt_in_wave_3():
     assert rep.corrected == 2 == rep.detected
 
 
+@pytest.mark.parametrize("rows", [256, 128])
 @pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
-def test_lp_fp8_two_sided_from_the_norms_pass(ta, tb):
-    """Two-sided FP8 on 128 x 128 tiles with at least 256 of them, so the
-    threshold norms and both operand checksums come from the pass over A
-    and B before the product: ragged in every dimension (k not a multiple
-    of the step), every transpose (each operand's checksums then come from
-    the other of the pass's two kernels), faults in the last row and
-    column tiles and the interior, checked against the oracle on the whole
+def test_lp_fp8_two_sided_from_the_norms_pass(ta, tb, rows, tmp_path):
+    """Two-sided FP8 with at least 256 tiles, so the threshold norms and
+    both operand checksums come from the pass over A and B before the
+    product: on the default 256 x 128 tiles and on 128 x 128 ones (set by
+    the tuning table); ragged in every dimension (k not a multiple of the
+    step), every transpose (each operand's checksums then come from the
+    other of the pass's two kernels), faults in the last row and column
+    tiles and the interior, checked against the oracle on the whole
     output."""
     dtype = F.FP8_E4M3
     m, n, k = 3999, 2001, 301
+    if rows == 128:
+        table = tmp_path / "fp8_128.tune"
+        table.write_text("tile %d 1 128\n" % dtype)
+        F.load_tune_table(str(table))
+    try:
+        _fp8_two_sided_from_the_norms_pass(ta, tb, rows, dtype, m, n, k)
+    finally:
+        F.load_tune_table(None)
+
+
+def _fp8_two_sided_from_the_norms_pass(ta, tb, rows, dtype, m, n, k):
     tm, tn, bk = lp_tiling(dtype, m, n, k)
-    assert (tm, tn) == (128, 128)
+    assert (tm, tn) == (rows, 128)
     A, B, Cin = synth.operands(32, 1, m, n, k, "normal", ta, tb)
     q = lp_inputs(A, B, dtype)
     unit = 1.0 / (q[2] * q[3])  # accumulator units per output unit
@@ -304,7 +316,7 @@ def test_lp_fp8_two_sided_from_the_norms_pass(ta, tb):
             Fa(1000, 1000, 150, synth.ADD, 3e3 * unit)]          # interior
     got, rep, ref = _compare(A, B, Cin, 0.9, -1.1, dtype, ta, tb, plan, q=q)
     assert rep.corrected == 4 == rep.detected
-    assert rep.tiles_verified == 32 * 16
+    assert rep.tiles_verified == -(-m // rows) * 16
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -364,8 +376,8 @@ def test_lp_crossing_pairs(dtype):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_lp_8192_sampled_tiles(dtype):
-    """m = n = k = 8192, normal inputs, as timed by the benchmark (BF16:
-    256 x 128 tiles; FP8: 128 x 128).  Error-free: no tile flagged.  With
+    """m = n = k = 8192, normal inputs, as timed by the benchmark (256 x 128
+    tiles).  Error-free: no tile flagged.  With
     one guarded FP32
     bit flip per 64 tiles: every one located and rebuilt; the oracle checks
     the tiles holding a fault plus sampled clean and corner tiles."""
@@ -374,7 +386,7 @@ def test_lp_8192_sampled_tiles(dtype):
     q = lp_inputs(A, B, dtype)
     ca, cb, sa, sb, dA, dB = q
     tm, tn, bk = lp_tiling(dtype, size, size, size)
-    assert (tm, tn) == ((256, 128) if dtype == F.BF16 else (128, 128))
+    assert (tm, tn) == (256, 128)
     tiles_m, tiles_n = size // tm, size // tn
     ntiles = tiles_m * tiles_n
     extra = [0, ntiles - 1, tiles_m - 1, ntiles - tiles_m] + [

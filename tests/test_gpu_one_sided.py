@@ -123,7 +123,7 @@ def test_one_sided_ragged(dtype, m, n, k, ta, tb):
 def test_one_sided_fault_free_bits(dtype):
     """Without faults the one-sided call writes the bits of the kernel
     without checksums and of the two-sided one (here all three take the
-    same 256-row tiles for BF16; FP8's two-sided call takes 128 rows)."""
+    same 256-row tiles)."""
     m, n, k = 3999, 2001, 301
     A, B, Cin = synth.operands(61, 0, m, n, k, "normal")
     ca, cb, sa, sb, dA, dB = lp_inputs(A, B, dtype)
