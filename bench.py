@@ -69,17 +69,35 @@ def with_table(F, text, fn):
         os.unlink(path)
 
 
-def timed(torch, fn, steps, warmup, reset=None):
+# warm-up time of the legs beside the headline (see timed)
+SETTLE_MS = 50.0
+
+
+def timed(torch, fn, steps, warmup, reset=None, settle_ms=0.0):
     """Average per-call time (ms) over `steps` calls, from HIP events on the
     launch stream around each call.  reset (optional) runs before every
     call, outside the events: it restores C from a pristine copy, since
-    with beta != 0 C is read and written.  Returns (ms_per_call, ms_total /
-    steps), the second including the resets."""
+    with beta != 0 C is read and written.  The warm-up is `warmup` calls,
+    continued until it has taken settle_ms of device time: a short kernel
+    launched right after a different heavy one has measured up to 10%
+    slower for some tens of milliseconds, which a few warm-up calls of a
+    2 ms kernel do not cover.  Returns (ms_per_call, ms_total / steps), the
+    second including the resets."""
     stream = torch.cuda.current_stream()
-    for _ in range(warmup):
+    w0 = torch.cuda.Event(enable_timing=True)
+    w1 = torch.cuda.Event(enable_timing=True)
+    w0.record(stream)
+    done = 0
+    while done < warmup or settle_ms > 0.0:
         if reset:
             reset()
         fn()
+        done += 1
+        if done >= warmup and settle_ms > 0.0:
+            w1.record(stream)
+            torch.cuda.synchronize()
+            if w0.elapsed_time(w1) >= settle_ms or done >= warmup + 500:
+                break
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
@@ -137,7 +155,7 @@ def cpu_baseline(A, B, Cin, m, n, k, budget_s=(8.0, 6.0)):
                       "per tile)" % (c_all, dt_all, c_one, dt_one, ntiles, m, n, k)}
 
 
-def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
+def lp_leg(torch, F, synth, np, dtype, size, steps, warmup, settle_ms=SETTLE_MS):
     """One low-precision leg at size^3: normal(0,1) inputs quantised to the
     format (FP8: per-tensor scales amax / 448), FP32 C, alpha = beta = 1."""
     m = n = k = size
@@ -179,15 +197,16 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
         got = dC[i0:i0 + 256, j0:j0 + 256].to(torch.float64)
         errs.append(float((got - ref).abs().max() / ref.abs().max()))
     reset = lambda: dC.copy_(dC0)
-    t_ft, _ = timed(torch, call(True), steps, warmup, reset)
-    t_plain, _ = timed(torch, call(False), steps, warmup, reset)
+    t_ft, _ = timed(torch, call(True), steps, warmup, reset, SETTLE_MS)
+    t_plain, _ = timed(torch, call(False), steps, warmup, reset, SETTLE_MS)
     tm, tn, bk, _ = F.query_tiling(dtype, m, n, k)
     tm0 = F.query_tiling_ex(dtype, m, n, k, abft=0)[0]
     # the same kernel with checksums compiled out on the fault-tolerant
     # call's own tile (the plain call's default tile may differ)
     if tm0 != tm:
         t_plain_same, _ = with_table(F, "tile %d 0 %d\n" % (dtype, tm),
-                                     lambda: timed(torch, call(False), steps, warmup, reset))
+                                     lambda: timed(torch, call(False), steps, warmup, reset,
+                                                   SETTLE_MS))
     else:
         t_plain_same = t_plain
     # the operand checksums and norms formed in the tiles from the staged
@@ -195,7 +214,7 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
     # the product; fault-tolerant FP8 tiles have 128 rows there), against
     # the kernel without checksums on the same tile
     dn = F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype)
-    t_in_tile, _ = timed(torch, lambda: F.gemm_ex_noalloc(dn), steps, warmup, reset)
+    t_in_tile, _ = timed(torch, lambda: F.gemm_ex_noalloc(dn), steps, warmup, reset, SETTLE_MS)
     tm_in = 128 if dtype == F.FP8_E4M3 else tm
     if tm_in == tm:
         t_plain_in = t_plain_same
@@ -203,14 +222,15 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
         t_plain_in = t_plain
     else:
         t_plain_in, _ = with_table(F, "tile %d 0 %d\n" % (dtype, tm_in),
-                                   lambda: timed(torch, call(False), steps, warmup, reset))
+                                   lambda: timed(torch, call(False), steps, warmup, reset,
+                                                 SETTLE_MS))
     tiles = (-(-m // tm)) * (-(-n // tn))
     gp = synth.rng(wid, size, synth.STREAM_PLAN)
     # exponent flips (bits 27..30) of FP32 accumulators: always far above
     # the rounding threshold unless the accumulator is exactly zero
     plan = synth.bitflip_plan(gp, m, n, k, tm, tn, -(-tiles // 64), bits=[27, 28, 29, 30])
     F.set_fault_plan(plan)
-    t_inj, _ = timed(torch, call(True), steps, warmup, reset)
+    t_inj, _ = timed(torch, call(True), steps, warmup, reset, SETTLE_MS)
     rb = F.ReportBuffer()
     dC.copy_(dC0)
     F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype), report=rb)
@@ -271,7 +291,7 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
         else:
             band += 1
     F.set_fault_plan(accepted)
-    t_gb, _ = timed(torch, call(True), steps, warmup, reset)
+    t_gb, _ = timed(torch, call(True), steps, warmup, reset, SETTLE_MS)
     rbg = F.ReportBuffer()
     dC.copy_(dC0)
     F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, scaleA=sa, scaleB=sb, dtype=dtype), report=rbg)
@@ -291,13 +311,13 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
     F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=2, scaleA=sa, scaleB=sb, dtype=dtype),
               report=rb1)
     clean1 = rb1.view()
-    t_one, _ = timed(torch, call(2), steps, warmup, reset)
+    t_one, _ = timed(torch, call(2), steps, warmup, reset, SETTLE_MS)
     tm1, tn1, bk1, _ = F.query_tiling_ex(dtype, m, n, k, abft=2)
     tiles1 = (-(-m // tm1)) * (-(-n // tn1))
     plan1 = synth.bitflip_plan(synth.rng(wid, size, synth.STREAM_PLAN), m, n, k, tm1, tn1,
                                -(-tiles1 // 64), bits=[27, 28, 29, 30])
     F.set_fault_plan(plan1)
-    t_one_inj, _ = timed(torch, call(2), steps, warmup, reset)
+    t_one_inj, _ = timed(torch, call(2), steps, warmup, reset, SETTLE_MS)
     rb1 = F.ReportBuffer()
     dC.copy_(dC0)
     F.gemm_ex(F.make_desc(dA, dB, dC, 1.0, 1.0, abft=2, scaleA=sa, scaleB=sb, dtype=dtype),
@@ -353,7 +373,7 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup):
     }
 
 
-def split_leg(torch, F, synth, steps, warmup):
+def split_leg(torch, F, synth, steps, warmup, settle_ms=SETTLE_MS):
     """Small-output FP64 shapes (normal inputs, alpha = beta = 1): the split
     inner dimension and its verified reduction, one fault per 32 tiles."""
     out = []
@@ -368,15 +388,15 @@ def split_leg(torch, F, synth, steps, warmup):
         slices = F.query_tiling(F.F64, m, n, k)[3]
         F.clear_fault_plan()
         t_ft, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0)), steps, warmup,
-                        reset)
+                        reset, SETTLE_MS)
         t_pl, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0, abft=False)),
-                        steps, warmup, reset)
+                        steps, warmup, reset, SETTLE_MS)
         tiles = (-(-m // 128)) * (-(-n // 128))
         plan = synth.additive_plan(synth.rng(50, k, synth.STREAM_PLAN), m, n, k, 128, 128,
                                    max(1, tiles // 32), synth.log_magnitude((k + 1.0) ** 0.5))
         F.set_fault_plan(plan)
         t_inj, _ = timed(torch, lambda: F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0)), steps, warmup,
-                         reset)
+                         reset, SETTLE_MS)
         rb = F.ReportBuffer()
         reset()
         F.gemm_ex(F.make_desc(A, B, C, 1.0, 1.0), report=rb)
@@ -394,7 +414,7 @@ def split_leg(torch, F, synth, steps, warmup):
     return out
 
 
-def batched_leg(torch, F, synth, np, dtype, steps, warmup):
+def batched_leg(torch, F, synth, np, dtype, steps, warmup, settle_ms=SETTLE_MS):
     """512 problems, m, n, k log-uniform in [64, 2048], U[-1,1], alpha = 1,
     beta = 0: one persistent launch replayed from a graph against the loop
     of per-problem launches; truncated Poisson(1) faults per problem."""
@@ -415,10 +435,10 @@ def batched_leg(torch, F, synth, np, dtype, steps, warmup):
     F.clear_fault_plan()
     F.gemm_batched(descs)  # tunes the tiles and the schedule, captures the graph
     rows = F.batch_tiling(descs)
-    t_b, _ = timed(torch, lambda: F.gemm_batched(descs), steps, warmup)
+    t_b, _ = timed(torch, lambda: F.gemm_batched(descs), steps, warmup, settle_ms=SETTLE_MS)
     F.gemm_batched(descs_plain)
     rows_plain = F.batch_tiling(descs_plain)
-    t_bp, _ = timed(torch, lambda: F.gemm_batched(descs_plain), steps, warmup)
+    t_bp, _ = timed(torch, lambda: F.gemm_batched(descs_plain), steps, warmup, settle_ms=SETTLE_MS)
     per_choice = {}
     if dtype != F.F64:
         # each tile choice fixed by the table, fault-tolerant against plain
@@ -426,9 +446,11 @@ def batched_leg(torch, F, synth, np, dtype, steps, warmup):
                              ("256_from_256", 256)):
             def both():
                 F.gemm_batched(descs)
-                a, _ = timed(torch, lambda: F.gemm_batched(descs), steps, warmup)
+                a, _ = timed(torch, lambda: F.gemm_batched(descs), steps, warmup,
+                             settle_ms=SETTLE_MS)
                 F.gemm_batched(descs_plain)
-                b, _ = timed(torch, lambda: F.gemm_batched(descs_plain), steps, warmup)
+                b, _ = timed(torch, lambda: F.gemm_batched(descs_plain), steps, warmup,
+                             settle_ms=SETTLE_MS)
                 return a, b
             a, b = with_table(F, "batch_mstar %d\n" % mstar, both)
             per_choice[label] = {"tflops": round(flops / (a * 1e-3) / 1e12, 3),
@@ -445,7 +467,7 @@ def batched_leg(torch, F, synth, np, dtype, steps, warmup):
             f.problem = p
             plan.append(f)
     F.set_fault_plan(plan)
-    t_bi, _ = timed(torch, lambda: F.gemm_batched(descs), steps, warmup)
+    t_bi, _ = timed(torch, lambda: F.gemm_batched(descs), steps, warmup, settle_ms=SETTLE_MS)
     reps = [F.ReportBuffer(record_capacity=8, echo_capacity=8) for _ in shapes]
     F.gemm_batched(descs, reps)
     views = [r.view() for r in reps]
