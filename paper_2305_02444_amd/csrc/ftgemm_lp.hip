@@ -1515,30 +1515,32 @@ __global__ __launch_bounds__(NT, 2) void batched_kernel(BatchArgs b)
 
 // Kernels built in a translation unit of their own, ftgemm_lp_ilp.hip, which
 // includes this file with FTG_LP_OWN_UNIT defined and is compiled with the
-// compiler's iterative ILP scheduling strategy: the BF16 two-sided kernel on
-// 256-row tiles with its norms from the pass before the product, and the FP8
-// one-sided kernel on 256-row tiles (measured 5% faster with that strategy,
-// where the others measured slower, FP8 two-sided by 45%).
-hipError_t launch_own_unit(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode,
+// compiler's iterative ILP scheduling strategy: the BF16 two-sided kernels
+// on 256-row tiles (norms from the pass before the product, or from the
+// tiles), and the FP8 one-sided kernel on 256-row tiles (measured 4-5%
+// faster with that strategy, where the others measured slower, FP8
+// two-sided by 45%).
+hipError_t launch_own_unit(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode, bool pre,
                            hipStream_t stream);
 
 #ifdef FTG_LP_OWN_UNIT
-hipError_t launch_own_unit(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode,
+hipError_t launch_own_unit(const GemmArgs &g, bool fp8, bool ta, bool tb, int mode, bool pre,
                            hipStream_t stream)
 {
     const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n;
     if (grid == 0) return hipSuccess;
-#define FTG_LP_OWN(F, a, b, d) \
-    hipLaunchKernelGGL((kernel<F, a, b, true, 256, d, true>), dim3(grid), dim3(NT), 0, stream, g)
-#define FTG_LP_OWN_T(F, d)                                     \
+#define FTG_LP_OWN(F, a, b, d, e) \
+    hipLaunchKernelGGL((kernel<F, a, b, true, 256, d, e>), dim3(grid), dim3(NT), 0, stream, g)
+#define FTG_LP_OWN_T(F, d, e)                                  \
     do {                                                       \
-        if (!ta && !tb) FTG_LP_OWN(F, false, false, d);        \
-        else if (!ta && tb) FTG_LP_OWN(F, false, true, d);     \
-        else if (ta && !tb) FTG_LP_OWN(F, true, false, d);     \
-        else FTG_LP_OWN(F, true, true, d);                     \
+        if (!ta && !tb) FTG_LP_OWN(F, false, false, d, e);     \
+        else if (!ta && tb) FTG_LP_OWN(F, false, true, d, e);  \
+        else if (ta && !tb) FTG_LP_OWN(F, true, false, d, e);  \
+        else FTG_LP_OWN(F, true, true, d, e);                  \
     } while (0)
-    if (fp8 && mode == 2) FTG_LP_OWN_T(true, true);
-    else if (!fp8 && mode == 1) FTG_LP_OWN_T(false, false);
+    if (fp8 && mode == 2 && pre) FTG_LP_OWN_T(true, true, true);
+    else if (!fp8 && mode == 1 && pre) FTG_LP_OWN_T(false, false, true);
+    else if (!fp8 && mode == 1) FTG_LP_OWN_T(false, false, false);
     else return hipErrorInvalidValue;
 #undef FTG_LP_OWN_T
 #undef FTG_LP_OWN
@@ -1590,13 +1592,14 @@ hipError_t launch(const GemmArgs &g, bool ta, bool tb, int mode, bool pre, hipSt
         else FTG_LP_CASE(true, true, c, d, e);                 \
     } while (0)
     if (mode == 2) {
-        if constexpr (FP8 && BM == 256) return launch_own_unit(g, FP8, ta, tb, mode, stream);
+        if constexpr (FP8 && BM == 256) return launch_own_unit(g, FP8, ta, tb, mode, pre, stream);
         else FTG_LP_MODE(true, true, true);
     } else if (mode == 1 && pre) {
-        if constexpr (!FP8 && BM == 256) return launch_own_unit(g, FP8, ta, tb, mode, stream);
+        if constexpr (!FP8 && BM == 256) return launch_own_unit(g, FP8, ta, tb, mode, pre, stream);
         else FTG_LP_MODE(true, false, true);
     } else if (mode == 1) {
-        FTG_LP_MODE(true, false, false);
+        if constexpr (!FP8 && BM == 256) return launch_own_unit(g, FP8, ta, tb, mode, pre, stream);
+        else FTG_LP_MODE(true, false, false);
     } else {
         FTG_LP_MODE(false, false, false);
     }
