@@ -352,8 +352,8 @@ def lp_leg(torch, F, synth, np, dtype, size, steps, warmup, settle_ms=SETTLE_MS)
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[name],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK[name], 4),
                      "traffic": read_traffic("ftgemm_%s_8192_counters.txt" % name,
-                                             ["ftgemm_lp.hip", "ftgemm_norms.hip",
-                                              "ftgemm_device.h"])
+                                             ["ftgemm_lp.hip", "ftgemm_lp_ilp.hip",
+                                              "ftgemm_norms.hip", "ftgemm_device.h"])
                      if size == 8192 else None},
         "injected": {"faults_per_call": len(plan), "kind": "FP32 exponent bit flip",
                      "tflops": round(flops / (t_inj * 1e-3) / 1e12, 3),
